@@ -1,0 +1,164 @@
+"""MAGUS controller oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain single-threaded C (``magus_oracle.c``) loaded with ctypes.  Only the
+tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package; the product library never does and shares no code with
+it.  The C source states, step by step and in the paper's order, what the
+controller of arXiv 2502.03796 computes (Alg. 1, Alg. 2 and the decision rule
+of Sec. 3.2 / Sec. 4); its header lists every reading taken where the paper is
+silent.
+
+Configs are passed as plain dicts with the keys
+``window, hold, inc_q16, dec_q16, hf_num, hf_den, level_min, level_max,
+level_init`` (integers; thresholds in Q16.16).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "magus_oracle.c")
+_LIB = os.path.join(_HERE, "libmagus_oracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/libmagus_oracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+             "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("direv_length", ctypes.c_uint32), ("tune_len", ctypes.c_uint32),
+                ("inc_q", ctypes.c_int32), ("dec_q", ctypes.c_int32),
+                ("hf_num", ctypes.c_uint32), ("hf_den", ctypes.c_uint32),
+                ("level_min", ctypes.c_uint32), ("level_max", ctypes.c_uint32),
+                ("level_init", ctypes.c_uint32)]
+
+
+class _Res(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_uint64), ("level_sum", ctypes.c_uint64),
+                ("transitions", ctypes.c_uint64), ("ticks_high", ctypes.c_uint64)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_config_valid.argtypes = [ctypes.POINTER(_Cfg)]
+        lib.oracle_replay_trace.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(_Cfg), P, ctypes.POINTER(_Res)]
+        lib.oracle_replay_trace_fp64.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(_Cfg),
+                                                 ctypes.c_double, ctypes.c_double, P,
+                                                 ctypes.POINTER(_Res)]
+        lib.oracle_replay_batch.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint32, P, P, P]
+        lib.oracle_sweep.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint32, P, P]
+        _lib = lib
+    return _lib
+
+
+def _cfg(d: dict) -> _Cfg:
+    return _Cfg(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
+                int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
+                int(d["level_max"]), int(d["level_init"]))
+
+
+def _cfg_array(cfgs):
+    arr = (_Cfg * len(cfgs))()
+    for i, d in enumerate(cfgs):
+        arr[i] = _cfg(d)
+    return arr
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def config_valid(cfg: dict) -> bool:
+    c = _cfg(cfg)
+    return bool(_load().oracle_config_valid(ctypes.byref(c)))
+
+
+def replay_trace(x, cfg: dict, want_bytes: bool = True):
+    """Run one trace.  Returns (result dict, per-step decision bytes or None)."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    c = _cfg(cfg)
+    r = _Res()
+    out = np.empty(len(x), dtype=np.uint8) if want_bytes else None
+    rc = _load().oracle_replay_trace(_ptr(x), len(x), ctypes.byref(c), _ptr(out), ctypes.byref(r))
+    if rc != 0:
+        raise ValueError("oracle: invalid config or trace")
+    return _res_dict(r), out
+
+
+def replay_trace_fp64(x, cfg: dict, inc_threshold: float, dec_threshold: float,
+                      want_bytes: bool = True):
+    """FP64 side-form of the predictor with decimal thresholds."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    c = _cfg(cfg)
+    r = _Res()
+    out = np.empty(len(x), dtype=np.uint8) if want_bytes else None
+    rc = _load().oracle_replay_trace_fp64(_ptr(x), len(x), ctypes.byref(c),
+                                          float(inc_threshold), float(dec_threshold),
+                                          _ptr(out), ctypes.byref(r))
+    if rc != 0:
+        raise ValueError("oracle: invalid config or trace")
+    return _res_dict(r), out
+
+
+def _res_dict(r: _Res) -> dict:
+    return {"score": r.score, "level_sum": r.level_sum,
+            "transitions": r.transitions, "ticks_high": r.ticks_high}
+
+
+def replay_batch(samples, offsets, cfgs, cfg_of_trace=None, want_bytes=False):
+    """Run every trace of a CSR batch.  Returns (results[n,4] uint64, bytes or None).
+
+    results columns: score, level_sum, transitions, ticks_high.
+    """
+    samples = np.ascontiguousarray(samples, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n_traces = len(offsets) - 1
+    carr = _cfg_array(cfgs)
+    cot = None if cfg_of_trace is None else np.ascontiguousarray(cfg_of_trace, dtype=np.uint32)
+    res = np.zeros((n_traces, 4), dtype=np.uint64)
+    out = np.empty(len(samples), dtype=np.uint8) if want_bytes else None
+    rc = _load().oracle_replay_batch(_ptr(samples), _ptr(offsets), n_traces, carr, len(cfgs),
+                                     _ptr(cot), _ptr(res), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle: invalid batch")
+    return res, out
+
+
+def sweep(samples, offsets, cfgs, want_scores=True):
+    """Every trace against every config.  Returns (scores[n_traces, n_cfgs] or None, argmin)."""
+    samples = np.ascontiguousarray(samples, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n_traces = len(offsets) - 1
+    carr = _cfg_array(cfgs)
+    scores = np.zeros((n_traces, len(cfgs)), dtype=np.uint64) if want_scores else None
+    argmin = np.zeros(n_traces, dtype=np.uint32)
+    rc = _load().oracle_sweep(_ptr(samples), _ptr(offsets), n_traces, carr, len(cfgs),
+                              _ptr(scores), _ptr(argmin))
+    if rc != 0:
+        raise ValueError("oracle: invalid sweep")
+    return scores, argmin
+
+
+def decode(byte_arr):
+    """Split decision bytes into (level, high, pred) arrays."""
+    b = np.asarray(byte_arr, dtype=np.uint8)
+    return (b & 31).astype(np.int64), ((b >> 5) & 1).astype(np.int64), \
+        (b >> 6).astype(np.int64) - 1

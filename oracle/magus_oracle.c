@@ -1,0 +1,238 @@
+/*
+ * MAGUS controller oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU statement of what the MAGUS hot path
+ * computes (Zheng, Sultanov, Papka, Lan: "Exploring Uncore Frequency Scaling
+ * for Heterogeneous Computing", arXiv 2502.03796).  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load this code; the
+ * product path never does.  It shares no code, header, table or constant with
+ * the HIP library.
+ *
+ * Each monitoring step follows the paper's order:
+ *   1. Monitor: push the new memory-throughput sample into the fixed-size FIFO
+ *      mem_throughput_ls (Sec. 3.1, "fixed-size first-in first-out queue").
+ *   2. Predict (Alg. 1): derivative of the FIFO's newest vs oldest entry over
+ *      direv_length, compared with inc_threshold (> -> +1) and dec_threshold
+ *      (< -> -1), else 0.  The result is a temporary decision (Sec. 3.1).
+ *   3. Log: push a binary flag "a frequency change would be triggered" into the
+ *      FIFO uncore_tune_ls (Sec. 3.2).
+ *   4. Detect (Alg. 2): freq = sum(uncore_tune_ls)/len(uncore_tune_ls);
+ *      high if freq >= high_freq_threshold (0.6 in Sec. 3.2).
+ *   5. Decide (Sec. 3.2, Sec. 4, Sec. 6.1): in the high state the uncore goes
+ *      to its maximum; otherwise the temporary decision is executed, where an
+ *      increase goes to the maximum and a decrease goes directly to the lower
+ *      bound; 0 keeps the level.  Nodes start idle at the minimum (Sec. 4).
+ *
+ * Readings taken where the paper is silent (each one is listed in the design
+ * notes of the repository):
+ *   - The derivative is taken relative to the smaller of the two samples,
+ *       r = (ls[-1] - ls[0]) / (direv_length * min(ls[0], ls[-1])),
+ *     so that thresholds are dimensionless and an up-step by k and a
+ *     down-step by 1/k give the same |r|.  A zero base gives +inf / -inf, and
+ *     0/0 gives no event.
+ *   - Thresholds are Q16.16 integers (inc_q / 65536, dec_q / 65536) and the
+ *     comparison is exact: r > inc_q/65536 is evaluated as the integer
+ *     cross-product (b - a) * 65536 > inc_q * W * min(a, b).  No rounding
+ *     happens anywhere; only the thresholds are quantised.
+ *   - Until the FIFO holds direv_length samples the prediction is 0 (warm-up);
+ *     uncore_tune_ls has a fixed length H and starts filled with zeros.
+ *   - high_freq_threshold is the fraction hf_num / hf_den and the test
+ *     sum/len >= num/den is evaluated as sum * den >= num * len.
+ *   - The flag logged is (temporary decision != 0), also while high.
+ *   - Per step the tick is accounted after the decision:
+ *       transitions += (new level != old level); level_sum += new level;
+ *     score = level_sum + 1000 * transitions.
+ *
+ * A second predictor, the "FP64 side-form", evaluates the same derivative in
+ * IEEE double with decimal thresholds; it is run beside the exact form only to
+ * report how often the two disagree.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "magus_oracle.h"
+
+#define ORACLE_FIFO_MAX 64
+
+/* ---------------------------------------------------------------- validation */
+
+int oracle_config_valid(const oracle_config* c)
+{
+    if (!c) return 0;
+    if (c->direv_length < 2 || c->direv_length > 32) return 0;
+    if (c->tune_len < 1 || c->tune_len > 32) return 0;
+    if (c->inc_q < 0 || c->inc_q > (1 << 20)) return 0;
+    if (c->dec_q > 0 || c->dec_q < -(1 << 20)) return 0;
+    if (c->hf_den < 1 || c->hf_num > c->hf_den) return 0;
+    if (c->level_min >= c->level_max || c->level_max > 31) return 0;
+    if (c->level_init < c->level_min || c->level_init > c->level_max) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------- Alg. 1, exact form */
+
+/*
+ * MEM_THROUGHPUT_TREND_PREDICTION (Alg. 1) with the relative derivative and
+ * Q16.16 thresholds.  ls holds direv_length samples, ls[0] oldest.
+ */
+static int predict_exact(int32_t inc_q, int32_t dec_q,
+                         const uint32_t* ls, uint32_t direv_length)
+{
+    int64_t first = ls[0];
+    int64_t last = ls[direv_length - 1];
+    int64_t base = first < last ? first : last;
+    int64_t delta = last - first;
+    /* derivative = delta / (direv_length * base); compare with q / 65536
+       by cross-multiplying with the positive (or zero) denominator.       */
+    int64_t lhs = delta * 65536;
+    int64_t den = (int64_t)direv_length * base;
+    if (lhs > (int64_t)inc_q * den) return 1;        /* derivative > inc */
+    if (lhs < (int64_t)dec_q * den) return -1;       /* derivative < dec */
+    return 0;
+}
+
+/* ------------------------------------------------------ Alg. 1, FP64 form */
+
+static int predict_fp64(double inc_threshold, double dec_threshold,
+                        const uint32_t* ls, uint32_t direv_length)
+{
+    double first = (double)ls[0];
+    double last = (double)ls[direv_length - 1];
+    double base = first < last ? first : last;
+    double derivative = (last - first) / ((double)direv_length * base);
+    if (derivative > inc_threshold) return 1;
+    if (derivative < dec_threshold) return -1;
+    return 0;                                        /* includes 0/0 = NaN */
+}
+
+/* ------------------------------------------------------------- Alg. 2 form */
+
+static int high_freq_detection(uint32_t hf_num, uint32_t hf_den,
+                               const uint8_t* uncore_tune_ls, uint32_t len)
+{
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < len; ++i) sum += uncore_tune_ls[i];
+    /* freq = sum / len >= hf_num / hf_den */
+    return (uint64_t)sum * hf_den >= (uint64_t)hf_num * len;
+}
+
+/* ----------------------------------------------------------- the controller */
+
+static void run_trace(const uint32_t* x, uint64_t n, const oracle_config* c,
+                      int use_fp64, double inc_threshold, double dec_threshold,
+                      uint8_t* bytes, oracle_result* res)
+{
+    uint32_t mem_throughput_ls[ORACLE_FIFO_MAX];
+    uint8_t uncore_tune_ls[ORACLE_FIFO_MAX];
+    uint32_t filled = 0;                 /* samples currently in the FIFO */
+    const uint32_t W = c->direv_length;
+    const uint32_t H = c->tune_len;
+    memset(uncore_tune_ls, 0, sizeof uncore_tune_ls);
+
+    uint32_t level = c->level_init;      /* idle nodes sit at the minimum */
+    uint64_t level_sum = 0, transitions = 0, ticks_high = 0;
+
+    for (uint64_t t = 0; t < n; ++t) {
+        /* 1. monitor: FIFO of the last W samples */
+        if (filled == W) {
+            memmove(mem_throughput_ls, mem_throughput_ls + 1, (W - 1) * sizeof(uint32_t));
+            mem_throughput_ls[W - 1] = x[t];
+        } else {
+            mem_throughput_ls[filled++] = x[t];
+        }
+
+        /* 2. predict (temporary decision) */
+        int pred = 0;
+        if (filled == W) {
+            pred = use_fp64 ? predict_fp64(inc_threshold, dec_threshold, mem_throughput_ls, W)
+                            : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W);
+        }
+
+        /* 3. log whether a frequency change would be triggered */
+        memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);
+        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);
+
+        /* 4. detect the high-frequency state */
+        int high = high_freq_detection(c->hf_num, c->hf_den, uncore_tune_ls, H);
+
+        /* 5. decide */
+        uint32_t next = level;
+        if (high) next = c->level_max;
+        else if (pred == 1) next = c->level_max;
+        else if (pred == -1) next = c->level_min;
+
+        transitions += (next != level);
+        level = next;
+        level_sum += level;
+        ticks_high += (uint64_t)high;
+        if (bytes)
+            bytes[t] = (uint8_t)(level | ((uint32_t)high << 5) | ((uint32_t)(pred + 1) << 6));
+    }
+    res->level_sum = level_sum;
+    res->transitions = transitions;
+    res->ticks_high = ticks_high;
+    res->score = level_sum + 1000u * transitions;
+}
+
+int oracle_replay_trace(const uint32_t* x, uint64_t n, const oracle_config* cfg,
+                        uint8_t* bytes, oracle_result* res)
+{
+    if (!oracle_config_valid(cfg) || !res || (n && !x)) return -1;
+    run_trace(x, n, cfg, 0, 0.0, 0.0, bytes, res);
+    return 0;
+}
+
+int oracle_replay_trace_fp64(const uint32_t* x, uint64_t n, const oracle_config* cfg,
+                             double inc_threshold, double dec_threshold,
+                             uint8_t* bytes, oracle_result* res)
+{
+    if (!oracle_config_valid(cfg) || !res || (n && !x)) return -1;
+    run_trace(x, n, cfg, 1, inc_threshold, dec_threshold, bytes, res);
+    return 0;
+}
+
+/* ----------------------------------------------------------------- batches */
+
+int oracle_replay_batch(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                        const oracle_config* cfgs, uint32_t n_cfgs,
+                        const uint32_t* cfg_of_trace, oracle_result* results, uint8_t* bytes)
+{
+    if (!offsets || !cfgs || !results || n_cfgs == 0) return -1;
+    for (uint32_t i = 0; i < n_cfgs; ++i)
+        if (!oracle_config_valid(&cfgs[i])) return -1;
+    for (uint32_t t = 0; t < n_traces; ++t) {
+        uint32_t k = cfg_of_trace ? cfg_of_trace[t] : 0;
+        if (k >= n_cfgs || offsets[t + 1] < offsets[t]) return -1;
+        uint64_t n = offsets[t + 1] - offsets[t];
+        run_trace(samples + offsets[t], n, &cfgs[k], 0, 0.0, 0.0,
+                  bytes ? bytes + offsets[t] : NULL, &results[t]);
+    }
+    return 0;
+}
+
+/*
+ * Parameter sweep: every trace against every config.  scores[t * n_cfgs + c]
+ * (optional) and argmin[t] = smallest config index among the minimal scores.
+ */
+int oracle_sweep(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                 const oracle_config* cfgs, uint32_t n_cfgs,
+                 uint64_t* scores, uint32_t* argmin)
+{
+    if (!offsets || !cfgs || n_cfgs == 0) return -1;
+    for (uint32_t i = 0; i < n_cfgs; ++i)
+        if (!oracle_config_valid(&cfgs[i])) return -1;
+    for (uint32_t t = 0; t < n_traces; ++t) {
+        uint64_t n = offsets[t + 1] - offsets[t];
+        uint64_t best = UINT64_MAX;
+        uint32_t best_c = 0;
+        for (uint32_t c = 0; c < n_cfgs; ++c) {
+            oracle_result r;
+            run_trace(samples + offsets[t], n, &cfgs[c], 0, 0.0, 0.0, NULL, &r);
+            if (scores) scores[(uint64_t)t * n_cfgs + c] = r.score;
+            if (r.score < best) { best = r.score; best_c = c; }
+        }
+        if (argmin) argmin[t] = best_c;
+    }
+    return 0;
+}

@@ -1,0 +1,45 @@
+/*
+ * MAGUS controller oracle -- TEST INFRASTRUCTURE ONLY (tests, smoke check and
+ * the CPU-baseline leg of the benchmark).  Plain single-threaded C.
+ * Names follow the paper's notation: direv_length is the derivative window of
+ * Alg. 1, tune_len is len(uncore_tune_ls) of Alg. 2, hf_num/hf_den is
+ * high_freq_threshold (0.6 = 3/5 in Sec. 3.2).
+ */
+#ifndef MAGUS_ORACLE_H
+#define MAGUS_ORACLE_H
+#include <stdint.h>
+
+typedef struct oracle_config {
+    uint32_t direv_length;  /* W, 2..32                                   */
+    uint32_t tune_len;      /* H = len(uncore_tune_ls), 1..32             */
+    int32_t inc_q;          /* inc_threshold in Q16.16, 0..2^20           */
+    int32_t dec_q;          /* dec_threshold in Q16.16, -2^20..0          */
+    uint32_t hf_num;        /* high_freq_threshold = hf_num / hf_den      */
+    uint32_t hf_den;
+    uint32_t level_min;     /* uncore ladder index of the lower bound      */
+    uint32_t level_max;     /* ... of the upper bound (<= 31)              */
+    uint32_t level_init;    /* level before the first step                 */
+} oracle_config;
+
+typedef struct oracle_result {
+    uint64_t score;         /* level_sum + 1000 * transitions              */
+    uint64_t level_sum;     /* sum over steps of the level after the step  */
+    uint64_t transitions;   /* steps whose level differs from the previous */
+    uint64_t ticks_high;    /* steps spent in the high-frequency state     */
+} oracle_result;
+
+int oracle_config_valid(const oracle_config* c);
+
+/* bytes (optional, n entries): bits 0-4 level, bit 5 high, bits 6-7 pred+1 */
+int oracle_replay_trace(const uint32_t* x, uint64_t n, const oracle_config* cfg,
+                        uint8_t* bytes, oracle_result* res);
+int oracle_replay_trace_fp64(const uint32_t* x, uint64_t n, const oracle_config* cfg,
+                             double inc_threshold, double dec_threshold,
+                             uint8_t* bytes, oracle_result* res);
+int oracle_replay_batch(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                        const oracle_config* cfgs, uint32_t n_cfgs,
+                        const uint32_t* cfg_of_trace, oracle_result* results, uint8_t* bytes);
+int oracle_sweep(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                 const oracle_config* cfgs, uint32_t n_cfgs,
+                 uint64_t* scores, uint32_t* argmin);
+#endif

@@ -1,0 +1,78 @@
+"""Exact-rational transliteration of the MAGUS controller for tiny inputs.
+
+Written independently of the C oracle, straight from the paper's two listings
+and the decision rule of Sec. 3.2: Python lists are the FIFOs, the derivative is
+a ``fractions.Fraction`` (an actual division, not a cross-multiplication), the
+thresholds are the rationals q/65536, and Alg. 2's freq is sum/len as a
+Fraction.  It is slow and meant for brute force over tiny traces only.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+INF = float("inf")
+
+
+def trend_prediction(inc_threshold, dec_threshold, mem_throughput_ls, direv_length):
+    """Alg. 1 with the derivative taken relative to the smaller end sample."""
+    first, last = mem_throughput_ls[0], mem_throughput_ls[-1]
+    base = min(first, last)
+    if base == 0:
+        if last == first:
+            return 0                      # 0/0: no trend
+        derivative = INF if last > first else -INF
+    else:
+        derivative = Fraction(last - first, direv_length * base)
+    if derivative > inc_threshold:
+        return 1
+    elif derivative < dec_threshold:
+        return -1
+    return 0
+
+
+def high_freq_detection(high_freq_threshold, uncore_tune_ls):
+    """Alg. 2."""
+    freq = Fraction(sum(uncore_tune_ls), len(uncore_tune_ls))
+    return freq >= high_freq_threshold
+
+
+def run(trace, cfg):
+    """Returns (per-step (level, high, pred) list, score, level_sum, transitions, ticks_high)."""
+    inc = Fraction(cfg["inc_q16"], 65536)
+    dec = Fraction(cfg["dec_q16"], 65536)
+    hft = Fraction(cfg["hf_num"], cfg["hf_den"])
+    W, H = cfg["window"], cfg["hold"]
+    mem_throughput_ls: list[int] = []
+    uncore_tune_ls = [0] * H
+    level = cfg["level_init"]
+    steps = []
+    level_sum = transitions = ticks_high = 0
+    for x in trace:
+        mem_throughput_ls.append(int(x))
+        if len(mem_throughput_ls) > W:
+            mem_throughput_ls.pop(0)
+        pred = trend_prediction(inc, dec, mem_throughput_ls, W) \
+            if len(mem_throughput_ls) == W else 0
+        uncore_tune_ls.pop(0)
+        uncore_tune_ls.append(1 if pred != 0 else 0)
+        high = high_freq_detection(hft, uncore_tune_ls)
+        if high:
+            new = cfg["level_max"]
+        elif pred == 1:
+            new = cfg["level_max"]
+        elif pred == -1:
+            new = cfg["level_min"]
+        else:
+            new = level
+        if new != level:
+            transitions += 1
+        level = new
+        level_sum += level
+        ticks_high += int(high)
+        steps.append((level, int(high), pred))
+    return steps, level_sum + 1000 * transitions, level_sum, transitions, ticks_high
+
+
+def encode(steps):
+    """Same byte layout as the oracle: level | high << 5 | (pred + 1) << 6."""
+    return bytes(lv | (h << 5) | ((p + 1) << 6) for lv, h, p in steps)

@@ -1,0 +1,100 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of the oracle's C source (on the CPU),
+compiles it, swaps it in for the real oracle and runs the pin checks of
+test_oracle_pins.py; at least one of them must fail.
+"""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "magus_oracle.c")
+
+MUTANTS = [
+    ("inc compare not strict", "if (lhs > (int64_t)inc_q * den) return 1;",
+     "if (lhs >= (int64_t)inc_q * den) return 1;"),
+    ("dec compare not strict", "if (lhs < (int64_t)dec_q * den) return -1;",
+     "if (lhs <= (int64_t)dec_q * den) return -1;"),
+    ("derivative not divided by the window", "int64_t den = (int64_t)direv_length * base;",
+     "int64_t den = base;"),
+    ("oldest sample as the base", "int64_t base = first < last ? first : last;",
+     "int64_t base = first;"),
+    ("newest sample taken one step early", "int64_t last = ls[direv_length - 1];",
+     "int64_t last = ls[direv_length - 2];"),
+    ("sign of dec_threshold flipped", "if (lhs < (int64_t)dec_q * den) return -1;",
+     "if (lhs < -(int64_t)dec_q * den) return -1;"),
+    ("Alg. 2 with > instead of >=", "return (uint64_t)sum * hf_den >= (uint64_t)hf_num * len;",
+     "return (uint64_t)sum * hf_den > (uint64_t)hf_num * len;"),
+    ("high state does not override", "if (high) next = c->level_max;",
+     "if (0) next = c->level_max;"),
+    ("only increases are logged", "uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
+     "uncore_tune_ls[H - 1] = (uint8_t)(pred == 1);"),
+    ("decrease by one step instead of to the bound",
+     "else if (pred == -1) next = c->level_min;",
+     "else if (pred == -1) next = level > c->level_min ? level - 1 : level;"),
+    ("first transition from idle not counted", "transitions += (next != level);",
+     "transitions += (t > 0 && next != level);"),
+    ("transition weight wrong", "res->score = level_sum + 1000u * transitions;",
+     "res->score = level_sum + 100u * transitions;"),
+    ("event FIFO one step short", "memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);\n"
+     "        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
+     "memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);\n"
+     "        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0); if (H > 1) uncore_tune_ls[0] = 0;"),
+]
+
+
+def _checks():
+    om = oracle
+    return [
+        lambda: pins.test_constant_trace_never_moves(om, 777, 4, 10),
+        lambda: [pins.test_clean_step_up(om, w, s) for w in (2, 4, 6) for s in (1, 40)],
+        lambda: pins.test_clean_step_down_goes_straight_to_the_lower_bound(om),
+        lambda: pins.test_q16_boundary_is_strict_and_disagrees_with_fp64(om),
+        lambda: pins.test_q16_boundary_downward(om),
+        lambda: pins.test_high_frequency_example_of_section_3_2(om),
+        lambda: pins.test_hold_one_locks_at_first_event(om),
+        lambda: pins.test_zero_high_freq_threshold_is_always_high(om),
+        lambda: pins.test_stuck_at_max_after_a_long_fall(om),
+        lambda: pins.test_alternation_locks_at_max(om),
+        lambda: pins.test_events_still_logged_while_high(om),
+        lambda: [pins.test_relative_derivative_is_scale_invariant(om, c) for c in (3, 1000)],
+        lambda: pins.test_up_by_k_and_down_by_k_are_symmetric(om),
+        lambda: [pins.test_decision_rule_invariants(om, i) for i in (0, 4096 + 77, 16383)],
+        lambda: pins.test_large_values_against_transliteration(om),
+        lambda: pins.test_brute_force_against_exact_rational_transliteration(om),
+    ]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found: {name}"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "mut.c")
+        so = os.path.join(d, "libmut.so")
+        open(c, "w").write(src.replace(old, new))
+        subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-I",
+                               os.path.dirname(SRC), "-o", so, c])
+        real = oracle._load()
+        mut = ctypes.CDLL(so)
+        for fn in ("oracle_config_valid", "oracle_replay_trace", "oracle_replay_trace_fp64",
+                   "oracle_replay_batch", "oracle_sweep"):
+            getattr(mut, fn).argtypes = getattr(real, fn).argtypes
+        oracle._lib = mut
+        try:
+            caught = False
+            for chk in _checks():
+                try:
+                    chk()
+                except AssertionError:
+                    caught = True
+                    break
+            assert caught, f"no pin catches: {name}"
+        finally:
+            oracle._lib = real

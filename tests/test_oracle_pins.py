@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: they use hand-derived closed
+forms, the paper's worked example of the 0.6 threshold (Sec. 3.2), invariants
+of the decision rule, scale invariance of the relative derivative, and brute
+force against an exact-rational transliteration of Alg. 1 / Alg. 2.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import default_config
+from tests import exact_reference as ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MAX = 16
+
+
+def run(oracle_mod, x, cfg):
+    res, b = oracle_mod.replay_trace(np.asarray(x, dtype=np.uint32), cfg)
+    lv, hi, pr = oracle_mod.decode(b)
+    return res, lv, hi, pr
+
+
+# ---------------------------------------------------------------- P1, P2
+
+@pytest.mark.parametrize("value", [0, 1, 777, 65536, 2**32 - 1])
+@pytest.mark.parametrize("window,hold", [(2, 1), (4, 10), (16, 16), (32, 32)])
+def test_constant_trace_never_moves(oracle_mod, value, window, hold):
+    """Zero derivative: no prediction, no event, the node stays idle at the minimum."""
+    cfg = default_config(window=window, hold=hold)
+    res, lv, hi, pr = run(oracle_mod, [value] * 300, cfg)
+    assert res == dict(score=0, level_sum=0, transitions=0, ticks_high=0)
+    assert (pr == 0).all() and (hi == 0).all() and (lv == 0).all()
+
+
+def test_constant_trace_keeps_a_non_minimal_initial_level(oracle_mod):
+    cfg = default_config(level_init=7)
+    res, lv, _, _ = run(oracle_mod, [5000] * 50, cfg)
+    assert (lv == 7).all()
+    assert res["level_sum"] == 7 * 50 and res["transitions"] == 0
+
+
+@pytest.mark.parametrize("window", [2, 4, 9, 32])
+def test_shorter_than_window_is_warm_up(oracle_mod, window):
+    """Until the FIFO holds direv_length samples there is no prediction."""
+    x = [1, 1000000, 3, 4000000, 0, 7, 1, 9, 100, 1, 10**9] * 3
+    x = x[:window - 1]
+    res, lv, hi, pr = run(oracle_mod, x, default_config(window=window, hold=1))
+    assert res["score"] == 0 and (pr == 0).all() and (hi == 0).all()
+
+
+# ---------------------------------------------------------------- P3
+
+@pytest.mark.parametrize("window", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("s", [1, 40, 99])
+def test_clean_step_up(oracle_mod, window, s):
+    """10,000 -> 20,000 at tick s: r = 10000/(W*10000) = 1/W > 0.1, so the
+    prediction is +1 on ticks s..s+W-2 (while the old sample is still in the
+    FIFO); W-1 <= 5 events never reach 6 of 10, so no high state; the level
+    jumps to MAX at s (detection delay 0) and stays: score 16(n-s) + 1000."""
+    n = 100
+    x = [10000] * s + [20000] * (n - s)
+    res, lv, hi, pr = run(oracle_mod, x, default_config(window=window))
+    expect_pred = np.zeros(n, dtype=np.int64)
+    expect_pred[s:min(n, s + window - 1)] = 1
+    if s < window - 1:                 # step inside the warm-up
+        expect_pred[:window - 1] = 0
+        expect_pred[window - 1:s + window - 1] = 1
+    assert (pr == expect_pred).all()
+    first = int(np.argmax(expect_pred != 0))
+    assert (lv[:first] == 0).all() and (lv[first:] == MAX).all()
+    assert res["transitions"] == 1 and res["ticks_high"] == 0
+    assert res["score"] == 16 * (n - first) + 1000
+
+
+def test_clean_step_down_goes_straight_to_the_lower_bound(oracle_mod):
+    """Sec. 6.1: a decrease goes directly to the lower bound."""
+    x = [10000] * 10 + [20000] * 30 + [5000] * 30
+    res, lv, _, pr = run(oracle_mod, x, default_config())
+    assert lv[10] == MAX and (lv[10:40] == MAX).all()
+    assert pr[40] == -1 and (lv[40:] == 0).all()
+    assert res["transitions"] == 2
+    assert res["score"] == 16 * 30 + 2000
+
+
+# ---------------------------------------------------------------- P4
+
+def test_q16_boundary_is_strict_and_disagrees_with_fp64(oracle_mod):
+    """65,536 -> 91,752 at W = 4: r = 26216 / 262144 = 6554/65536 exactly, which
+    is inc_q; '>' is strict so no event.  91,753 fires.  In FP64 with the
+    decimal threshold 0.1, r = 0.100006103515625 > 0.1 does fire."""
+    cfg = default_config()
+    r0, _ = oracle_mod.replay_trace(np.array([65536] * 4 + [91752] * 4, np.uint32), cfg)
+    r1, _ = oracle_mod.replay_trace(np.array([65536] * 4 + [91753] * 4, np.uint32), cfg)
+    f0, _ = oracle_mod.replay_trace_fp64(np.array([65536] * 4 + [91752] * 4, np.uint32),
+                                         cfg, 0.1, -0.1)
+    assert r0["score"] == 0
+    assert r1["score"] == 16 * 4 + 1000
+    assert f0["score"] == 16 * 4 + 1000
+
+
+def test_q16_boundary_downward(oracle_mod):
+    """Down: a*65536 > b*(65536 + W*|dec|).  b = 65536, W = 4, dec = -6554:
+    the boundary a = 65536 + 26216 = 91752 gives no event, 91753 does."""
+    cfg = default_config()
+    r0, _ = oracle_mod.replay_trace(np.array([91752] * 4 + [65536] * 4, np.uint32), cfg)
+    r1, b1 = oracle_mod.replay_trace(np.array([91753] * 4 + [65536] * 4, np.uint32), cfg)
+    assert r0["score"] == 0
+    _, _, pr = oracle_mod.decode(b1)
+    assert list(pr[4:7]) == [-1, -1, -1] and r1["score"] == 0   # already at MIN
+
+
+# ---------------------------------------------------------------- P5 (paper example)
+
+def _events_trace(event_ticks, n, lo=10000, hi=20000):
+    """W = 2 trace with a prediction event exactly at the given ticks."""
+    v, x, ev = lo, [], set(event_ticks)
+    for t in range(n):
+        if t in ev:
+            v = hi if v == lo else lo
+        x.append(v)
+    return x
+
+
+def test_high_frequency_example_of_section_3_2(oracle_mod):
+    rows = [tuple(int(v) for v in ln.split()) for ln in
+            open(os.path.join(GOLDEN, "high_freq_example.txt")) if ln.strip() and ln[0] != "#"]
+    for H, k, expect in rows:
+        cfg = default_config(window=2, hold=H)
+        ev = list(range(30, 30 + k))
+        x = _events_trace(ev, 60)
+        _, _, hi, pr = run(oracle_mod, x, cfg)
+        assert (pr[ev] != 0).all() and (np.delete(pr, ev) == 0).all()
+        # the window ending at the last event holds exactly k events
+        t_last = 30 + k - 1 if k else 45
+        assert hi[t_last] == expect, (H, k)
+        assert hi.max() == expect
+
+
+# ---------------------------------------------------------------- P6
+
+def test_hold_one_locks_at_first_event(oracle_mod):
+    """H = 1: the event rate is the current flag, so any event is 'high' and
+    forces MAX; a -1 is never executed."""
+    x = [30000] * 20 + [10000] * 20 + [40000] * 20 + [9000] * 20
+    res, lv, hi, pr = run(oracle_mod, x, default_config(hold=1))
+    assert ((pr != 0) == (hi == 1)).all()
+    first = int(np.argmax(pr != 0))
+    assert pr[first] == -1                 # the first event is a decrease ...
+    assert (lv[:first] == 0).all() and (lv[first:] == MAX).all()   # ... yet MAX
+    assert res["transitions"] == 1
+
+
+def test_zero_high_freq_threshold_is_always_high(oracle_mod):
+    """Alg. 2 with high_freq_threshold = 0: freq >= 0 holds at every step, so the
+    node leaves its idle minimum on the very first step and never comes back:
+    n ticks at MAX and one transition (the one out of the idle level)."""
+    x = [10000, 50000, 1000, 2000] * 25
+    res, lv, hi, _ = run(oracle_mod, x, default_config(hf_num=0))
+    assert (hi == 1).all() and (lv == MAX).all()
+    assert res == dict(score=16 * 100 + 1000, level_sum=1600, transitions=1, ticks_high=100)
+
+
+# ---------------------------------------------------------------- P7, P8
+
+def test_stuck_at_max_after_a_long_fall(oracle_mod):
+    """W = 16, H = 10, 40,000 -> 10,000 at s = 40: r = -30000/(16*10000) =
+    -0.1875 < -0.1 on ticks 40..54 (15 events).  The 6th event (t = 45) is
+    high -> MAX; after the events stop the prediction is 0 and the level is
+    kept: MAX for ever.  score = 16 * (100 - 45) + 1000 = 1880."""
+    x = [40000] * 40 + [10000] * 60
+    res, lv, hi, pr = run(oracle_mod, x, default_config(window=16))
+    assert (pr[40:55] == -1).all() and (pr[55:] == 0).all()
+    assert (lv[:45] == 0).all() and (lv[45:] == MAX).all()
+    assert list(np.nonzero(hi)[0]) == list(range(45, 59))
+    assert res == dict(score=1880, level_sum=880, transitions=1, ticks_high=14)
+
+
+def test_alternation_locks_at_max(oracle_mod):
+    """W = 2 alternating 10,000 / 20,000, low first: +1 on odd ticks, -1 on even
+    ticks >= 2.  Levels MAX/MIN alternate on t = 1..5 (5 transitions), the 6th
+    event (t = 6) is high and the level stays MAX (Sec. 3.2 / Sec. 6.3 lock).
+    97 ticks at MAX: score = 16 * 97 + 5 * 1000 = 6552."""
+    x = [10000, 20000] * 50
+    res, lv, hi, pr = run(oracle_mod, x, default_config(window=2))
+    assert list(lv[:7]) == [0, MAX, 0, MAX, 0, MAX, MAX]
+    assert (lv[6:] == MAX).all() and (hi[6:] == 1).all() and (hi[:6] == 0).all()
+    assert res == dict(score=6552, level_sum=1552, transitions=5, ticks_high=94)
+
+
+def test_events_still_logged_while_high(oracle_mod):
+    """Sec. 3.2: predictions keep being logged while high; the high state ends
+    once fewer than 6 of the last 10 steps had an event."""
+    x = [10000, 20000] * 10 + [20000] * 30
+    _, lv, hi, pr = run(oracle_mod, x, default_config(window=2))
+    assert (pr[1:20] != 0).all()
+    # events on ticks 1..19; the window 14..23 holds 6 of them, 15..24 only 5
+    assert hi[19] == 1 and hi[23] == 1 and hi[24] == 0 and (hi[24:] == 0).all()
+    assert (lv[6:] == MAX).all()
+
+
+# ---------------------------------------------------------------- P9
+
+@pytest.mark.parametrize("c", [2, 3, 7, 1000])
+def test_relative_derivative_is_scale_invariant(oracle_mod, c):
+    """Multiplying every sample by c leaves (b-a)/(W min(a,b)) unchanged."""
+    key = synth.stream_key(99, c)
+    x = synth.geometric_phase_trace(3000, key, mean=20.0, short_prob=0.2,
+                                    median=1000.0)
+    x = np.minimum(x, (2**32 - 1) // c).astype(np.uint32)
+    for cfg in (default_config(), synth.sweep_config(7777), synth.sweep_config(1234)):
+        a = oracle_mod.replay_trace(x, cfg)[1]
+        b = oracle_mod.replay_trace(x * np.uint32(c), cfg)[1]
+        assert (a == b).all()
+
+
+def test_up_by_k_and_down_by_k_are_symmetric(oracle_mod):
+    """min() as the base: x -> kx and kx -> x give the same |r|."""
+    for k in (1.5, 2.0, 3.0):
+        base = 12345
+        up = [base] * 8 + [int(base * k)] * 8
+        dn = [int(base * k)] * 8 + [base] * 8
+        for q in (1000, 8000, 20000, 60000):
+            cfg = default_config(inc_q16=q, dec_q16=-q)
+            _, _, _, pu = run(oracle_mod, up, cfg)
+            _, _, _, pd = run(oracle_mod, dn, cfg)
+            assert ((pu == 1) == (pd == -1)).all()
+
+
+# ---------------------------------------------------------------- invariants
+
+def _random_traces(n_traces=40, n=2000):
+    out = []
+    for i in range(n_traces):
+        key = synth.stream_key(1234, i)
+        if i % 2:
+            out.append(synth.geometric_phase_trace(n, key, mean=15.0, short_prob=0.3))
+        else:
+            out.append(synth.four_phase_trace(n, key))
+    return out
+
+
+@pytest.mark.parametrize("cfg_index", [0, 1, 300, 4095, 4096 + 77, 8191, 12000, 16383])
+def test_decision_rule_invariants(oracle_mod, cfg_index):
+    cfg = synth.sweep_config(cfg_index)
+    for x in _random_traces(12, 1500):
+        res, lv, hi, pr = run(oracle_mod, x, cfg)
+        assert set(np.unique(lv)) <= {0, MAX}
+        assert (lv[hi == 1] == MAX).all()                 # high -> MAX
+        assert (lv[pr == 1] == MAX).all()                 # +1 -> MAX
+        assert (lv[(pr == -1) & (hi == 0)] == 0).all()    # executed -1 -> MIN
+        keep = (pr == 0) & (hi == 0)
+        prev = np.concatenate([[cfg["level_init"]], lv[:-1]])
+        assert (lv[keep] == prev[keep]).all()             # 0 keeps the level
+        assert res["level_sum"] == int(lv.sum())
+        assert res["transitions"] == int((lv != prev).sum())
+        assert res["ticks_high"] == int(hi.sum())
+        assert res["score"] == res["level_sum"] + 1000 * res["transitions"]
+        assert (pr[:cfg["window"] - 1] == 0).all()
+
+
+def test_batch_and_sweep_agree_with_single_traces(oracle_mod):
+    traces = _random_traces(10, 700) + [np.zeros(0, np.uint32), np.array([5], np.uint32)]
+    samples, offsets = synth.make_batch(traces)
+    cfgs = [synth.sweep_config(i) for i in (3, 999, 5000, 9000, 16000)]
+    cot = np.arange(len(traces), dtype=np.uint32) % len(cfgs)
+    res, b = oracle_mod.replay_batch(samples, offsets, cfgs, cot, want_bytes=True)
+    scores, argmin = oracle_mod.sweep(samples, offsets, cfgs)
+    for t, x in enumerate(traces):
+        r, bb = oracle_mod.replay_trace(x, cfgs[cot[t]])
+        assert list(res[t]) == [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]]
+        assert (b[int(offsets[t]):int(offsets[t + 1])] == bb).all()
+        s = [oracle_mod.replay_trace(x, c, want_bytes=False)[0]["score"] for c in cfgs]
+        assert list(scores[t]) == s
+        assert argmin[t] == int(np.argmin(s))             # lowest index among ties
+
+
+def test_invalid_configs_are_rejected(oracle_mod):
+    good = default_config()
+    assert oracle_mod.config_valid(good)
+    for bad in (dict(window=1), dict(window=33), dict(hold=0), dict(hold=33),
+                dict(inc_q16=-1), dict(dec_q16=1), dict(inc_q16=2**20 + 1),
+                dict(hf_den=0), dict(hf_num=6, hf_den=5), dict(level_min=16, level_max=16),
+                dict(level_max=32), dict(level_init=17)):
+        assert not oracle_mod.config_valid(default_config(**bad)), bad
+
+
+# ---------------------------------------------------------------- FP64 side-form
+
+def test_fp64_side_form_agrees_away_from_boundaries(oracle_mod):
+    """Decimal thresholds in FP64 vs Q16.16: decisions agree except where a
+    derivative falls between v and its Q16.16 rounding."""
+    for x in _random_traces(10, 3000):
+        for v in (0.1, 0.25, 0.5):
+            q = synth.threshold_q16(v)
+            cfg = default_config(inc_q16=q, dec_q16=-q)
+            _, be = oracle_mod.replay_trace(x, cfg)
+            _, bf = oracle_mod.replay_trace_fp64(x, cfg, v, -v)
+            if q / 65536 == v:
+                assert (be == bf).all()
+            else:
+                assert np.mean(be != bf) < 0.01
+
+
+# ---------------------------------------------------------------- P12 brute force
+
+def _brute_traces():
+    out = []
+    for n in range(1, 6):
+        out.extend(itertools.product(range(5), repeat=n))
+    return out
+
+
+def test_brute_force_against_exact_rational_transliteration(oracle_mod):
+    """All traces over {0..4} of length <= 5, W in {2,3,4}, H in {1,2,3,5},
+    thresholds including exact-equality cases (e.g. 1 -> 2 at W = 4 gives
+    r = 1/4 = 16384/65536), against the Fraction-based Alg. 1 / Alg. 2."""
+    traces = _brute_traces()
+    samples, offsets = synth.make_batch([np.array(t, np.uint32) for t in traces])
+    incs = (0, 1, 16384, 32768, 65536)
+    decs = (0, -16384, -32768)
+    checked = 0
+    for W, H, inc, dec in itertools.product((2, 3, 4), (1, 2, 3, 5), incs, decs):
+        cfg = default_config(window=W, hold=H, inc_q16=inc, dec_q16=dec)
+        res, b = oracle_mod.replay_batch(samples, offsets, [cfg], want_bytes=True)
+        for i, t in enumerate(traces):
+            steps, score, ls, tr, th = ref.run(t, cfg)
+            got = b[int(offsets[i]):int(offsets[i + 1])].tobytes()
+            if got != ref.encode(steps) or list(res[i]) != [score, ls, tr, th]:
+                raise AssertionError(f"mismatch W={W} H={H} inc={inc} dec={dec} trace={t}")
+            checked += 1
+    assert checked == len(traces) * 3 * 4 * len(incs) * len(decs)
+
+
+def test_brute_force_hf_threshold_and_levels(oracle_mod):
+    """Other high_freq_threshold fractions and ladders, against the transliteration."""
+    traces = [t for t in _brute_traces() if len(t) >= 3]
+    rng = np.random.default_rng(5)
+    for _ in range(60):
+        lmin = int(rng.integers(0, 10))
+        lmax = int(rng.integers(lmin + 1, 32))
+        den = int(rng.integers(1, 8))
+        cfg = default_config(window=int(rng.integers(2, 5)), hold=int(rng.integers(1, 7)),
+                             inc_q16=int(rng.choice([0, 9000, 16384, 40000])),
+                             dec_q16=-int(rng.choice([0, 9000, 16384, 40000])),
+                             hf_num=int(rng.integers(0, den + 1)), hf_den=den,
+                             level_min=lmin, level_max=lmax,
+                             level_init=int(rng.integers(lmin, lmax + 1)))
+        for t in traces[::7]:
+            steps, score, ls, tr, th = ref.run(t, cfg)
+            r, b = oracle_mod.replay_trace(np.array(t, np.uint32), cfg)
+            assert b.tobytes() == ref.encode(steps)
+            assert [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]] == \
+                [score, ls, tr, th]
+
+
+def test_large_values_against_transliteration(oracle_mod):
+    """Random 32-bit samples incl. 0 and 2^32-1 (64-bit products near the top)."""
+    rng = np.random.default_rng(11)
+    for _ in range(30):
+        n = 40
+        x = rng.integers(0, 2**32, size=n, dtype=np.uint64)
+        x[rng.integers(0, n, 5)] = 0
+        x[rng.integers(0, n, 5)] = 2**32 - 1
+        x[rng.integers(0, n, 5)] = 1
+        for W, q in ((2, 2**20), (32, 2**20), (7, 1), (3, 12345)):
+            cfg = default_config(window=W, hold=3, inc_q16=q, dec_q16=-q)
+            steps, score, *_ = ref.run([int(v) for v in x], cfg)
+            r, b = oracle_mod.replay_trace(x.astype(np.uint32), cfg)
+            assert b.tobytes() == ref.encode(steps) and r["score"] == score
