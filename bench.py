@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the MAGUS hot path on one MI355X.
+
+One step = one magus_replay of the bulk workload: 4,096 synthetic traces x
+100,000 uint32 memory-throughput samples, one default controller config
+(W = 4, +-0.1, H = 10, 0.6, 17-level ladder), inputs resident in HBM.
+The metric is trace-samples x configs evaluated per second.
+
+Prints ONE JSON line on stdout (progress goes to stderr).  Beside the headline
+it reports: the roofline of the dominant kernel (the chunk kernel, timed with
+HIP events on its stream), the oracle timed on the host, the parameter sweep
+(1,024 x 50,000 samples x 16,384 configs), the serving step at 65,536 streams
+(p50/p99 latency) and the FP64 side-form disagreement rate.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# int32 VALU issue peak: 256 CUs x 64 lanes per clock x 2.4 GHz
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chunk_kernel_bulk_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("replay.hip", "magus_internal.h"):
+        with open(os.path.join(ROOT, "paper_2502_03796_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(n_samples):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash() or t.get("n_samples") != n_samples:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--traces", type=int, default=4096)
+    ap.add_argument("--length", type=int, default=100000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip sweep/serve/fp64 reports")
+    ap.add_argument("--serve-ticks", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the hot path shards with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_03796_amd as magus
+    import synth
+
+    dev = torch.device("cuda:0")
+    log(f"generating bulk workload {args.traces} x {args.length} ...")
+    t0 = time.time()
+    samples, offsets = synth.workload_bulk(args.traces, args.length)
+    n_samples = int(offsets[-1])
+    log(f"  {n_samples} samples in {time.time() - t0:.1f} s")
+    s = torch.from_numpy(samples.view(np.int32)).to(dev)
+    o = torch.from_numpy(offsets.view(np.int64)).to(dev)
+    cfg = synth.default_config()
+    ctx = magus.Context(0)
+    results = torch.empty((args.traces, 4), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        ctx.replay(s, o, [cfg], results=results)
+    ctx.check()
+
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    ctx.kernel_time(magus.KERNEL_REPLAY)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.replay(s, o, [cfg], results=results)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    kms, launches = ctx.kernel_time(magus.KERNEL_REPLAY)
+    ctx.check()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n_samples / (ms_per_step * 1e-3)
+    avg_kernel_ms = kms / max(launches, 1)
+    bytes_per_launch = 4.0 * n_samples            # one read of every uint32 sample
+    achieved = bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9
+    log(f"replay: {ms_per_step:.4f} ms/step, chunk kernel {avg_kernel_ms:.4f} ms "
+        f"({achieved:.0f} GB/s), {value:.3e} samples/s")
+
+    # parity spot check of the timed launch against the oracle
+    import oracle
+    got = results.cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(0)
+    pick = sorted(set(rng.integers(0, args.traces, 8).tolist()))
+    for t in pick:
+        x = samples[int(offsets[t]):int(offsets[t + 1])]
+        r, _ = oracle.replay_trace(x, cfg, want_bytes=False)
+        if list(got[t]) != [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]]:
+            raise SystemExit(f"parity failure on trace {t}")
+    parity = f"ok: {len(pick)} sampled traces equal the oracle"
+
+    out = {
+        "metric": "trace-samples x configs evaluated/s at 1 GPU",
+        "value": value,
+        "unit": "samples*configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"bulk replay: {args.traces} traces x {args.length} uint32 "
+                               "samples, 1 default config (W=4, +-0.1, H=10, 0.6)",
+                   "traces": args.traces, "samples_per_trace": args.length, "configs": 1,
+                   "chunk_steps": ctx.chunk},
+        "parity": parity,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(n_samples),
+                     "kernel": "chunk_kernel", "avg_kernel_ms": avg_kernel_ms,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+
+    if not args.no_cpu:
+        log("oracle baseline on the host ...")
+        t0 = time.perf_counter()
+        oracle.replay_batch(samples, offsets, [cfg])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_samples / dt, "unit": "samples*configs/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"all {args.traces} traces x {args.length} samples, "
+                                         f"1 config, single thread, {dt:.1f} s"}
+        log(f"  oracle {n_samples / dt:.3e} samples/s ({dt:.1f} s)")
+
+    if not args.no_extra:
+        extra = {}
+        # FP64 side-form vs the exact Q16.16 form
+        dp = dl = tot = 0
+        for t in range(0, args.traces, max(1, args.traces // 32)):
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            _, be = oracle.replay_trace(x, cfg)
+            _, bf = oracle.replay_trace_fp64(x, cfg, 0.1, -0.1)
+            dp += int(((be >> 6) != (bf >> 6)).sum())
+            dl += int(((be & 31) != (bf & 31)).sum())
+            tot += len(x)
+        extra["fp64_side_form"] = {"pred_disagreement_rate": dp / tot,
+                                   "level_disagreement_rate": dl / tot, "steps": tot}
+        del s, o
+        torch.cuda.empty_cache()
+
+        log("sweep workload ...")
+        ssmp, soff = synth.workload_sweep_traces()
+        ss = torch.from_numpy(ssmp.view(np.int32)).to(dev)
+        so = torch.from_numpy(soff.view(np.int64)).to(dev)
+        grid = synth.sweep_grid()
+        ctx.sweep(ss, so, grid)
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        ctx.kernel_time(magus.KERNEL_SWEEP)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, arg = ctx.sweep(ss, so, grid)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ctx.set_profiling(False)
+        kms, kn = ctx.kernel_time(magus.KERNEL_SWEEP)
+        ctx.check()
+        evals = float(len(ssmp)) * len(grid)
+        kern_s = kms / kn * 1e-3
+        extra["sweep"] = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
+                          "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3,
+                          "kernel_ms": kern_s * 1e3,
+                          "useful_op_frac_12ops": evals / kern_s * 12 / VALU_PEAK_OPS}
+        log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
+        del ss, so
+
+        log("serving step at 65,536 streams ...")
+        n = 65536
+        srv = magus.Server(ctx, n * magus.Server.slot_bytes())
+        slots = np.array([srv.open(grid[(i * 2654435761) % len(grid)]) for i in range(n)],
+                         np.uint32)
+        data = [synth.serve_stream_samples(i, args.serve_ticks) for i in range(0, n, 1024)]
+        ticks = np.stack([np.tile(d, 1) for d in data])          # 64 distinct streams
+        buf = torch.empty(n, dtype=torch.uint8).pin_memory().numpy()
+        lat = []
+        for k in range(args.serve_ticks):
+            smp = np.repeat(ticks[:, k], 1024)[:n]
+            ta = time.perf_counter()
+            srv.step(slots, smp, decisions=buf)
+            lat.append(time.perf_counter() - ta)
+        lat = np.array(lat[5:]) * 1e3
+        extra["serve"] = {"streams": n, "ticks": len(lat),
+                          "p50_ms": float(np.percentile(lat, 50)),
+                          "p99_ms": float(np.percentile(lat, 99)),
+                          "samples_per_s": n / (np.mean(lat) * 1e-3),
+                          "mode": "one batched step per tick (host arrays -> decisions in "
+                                  "pinned host memory)"}
+        log(f"  serve p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+        srv.close()
+        out["extra"] = extra
+
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * magus.h -- C ABI of the MI355X (gfx950) library that replays, sweeps and
+ * serves the MAGUS uncore-frequency controller (arXiv 2502.03796) in batch.
+ *
+ * The controller, per monitoring step of one telemetry stream (Sec. 3):
+ *   - Alg. 1 (memory throughput trend prediction): the derivative of the
+ *     newest vs the oldest of the last `window` throughput samples, taken
+ *     relative to the smaller of the two and divided by the window,
+ *       r = (x[t] - x[t-W+1]) / (W * min(x[t], x[t-W+1])),
+ *     gives +1 if r > inc, -1 if r < dec, else 0 (the "temporary decision").
+ *     Thresholds are Q16.16 integers and the comparison is exact.  The first
+ *     W-1 steps of a stream predict 0.
+ *   - Sec. 3.2: a flag (prediction != 0) is pushed into the event FIFO
+ *     uncore_tune_ls of length `hold` (H, zero-filled at start), also while
+ *     the high state holds.
+ *   - Alg. 2 (high frequency detection): high if sum/len >= hf_num/hf_den
+ *     (0.6 = 3/5 in Sec. 3.2).
+ *   - Decision (Sec. 3.2, Sec. 4, Sec. 6.1): high or +1 -> level_max; else -1
+ *     -> level_min (straight to the lower bound); else keep.  Streams start at
+ *     level_init (idle nodes sit at the minimum, Sec. 4).
+ *   - Accounting per step, after the decision: transitions += (level changed);
+ *     level_sum += level; score = level_sum + 1000 * transitions.
+ *
+ * Conventions for every call:
+ *   - d_* pointers are device memory (any allocator, e.g. torch tensors) owned
+ *     by the caller; h_* pointers are host memory owned by the caller.
+ *   - Calls return MAGUS_OK (0) or a negative MAGUS_E* code and never throw.
+ *     The message of the last failure on the calling thread is available from
+ *     magus_last_error().
+ *   - Host-side arguments (configs, sizes) are validated synchronously.  Work
+ *     is enqueued on `stream` (a hipStream_t; NULL is the default stream) and
+ *     runs asynchronously; data faults found on the device (non-monotone
+ *     offsets, config index out of range, trace too long) produce no output
+ *     and are reported by the next magus_ctx_check().
+ *   - One context serves one stream at a time: calls on the same context from
+ *     different streams that overlap in time race on its scratch memory.
+ */
+#ifndef MAGUS_H
+#define MAGUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAGUS_OK 0
+#define MAGUS_EINVAL (-1)   /* bad argument or config                          */
+#define MAGUS_ENOMEM (-2)   /* device or pinned host allocation failed         */
+#define MAGUS_ENOSLOT (-3)  /* serving: no free slot within the memory budget  */
+#define MAGUS_EDEVICE (-4)  /* a HIP runtime call failed                        */
+#define MAGUS_EDATA (-5)    /* device-side data check failed (magus_ctx_check)  */
+
+/* Longest trace (samples) accepted by replay and sweep. */
+#define MAGUS_MAX_TRACE_LEN ((1u << 30) - 1u)
+
+/*
+ * One controller configuration (Alg. 1 and Alg. 2 arguments, Sec. 3.2 rule).
+ *   window      W = direv_length of Alg. 1, 2..32.
+ *   hold        H = len(uncore_tune_ls) of Alg. 2, 1..32.
+ *   inc_q16     inc_threshold as a Q16.16 integer, 0..2^20 (e.g. 0.1 -> 6554).
+ *   dec_q16     dec_threshold as a Q16.16 integer, -2^20..0.
+ *   hf_num/den  high_freq_threshold = hf_num / hf_den, 0 <= num <= den, den >= 1
+ *               (Sec. 3.2 uses 0.6 = 3/5).
+ *   level_min   lower bound on the uncore ladder (level i = 800 + 100 i MHz on
+ *   level_max   the 17-level 0.8-2.4 GHz ladder); min < max <= 31.
+ *   level_init  level before the first step, min <= init <= max (Sec. 4: min).
+ *   up_step,    0 = jump to the bound (Sec. 6.1).  Other values are rejected.
+ *   down_step
+ */
+typedef struct magus_config {
+    uint16_t window;
+    uint16_t hold;
+    int32_t inc_q16;
+    int32_t dec_q16;
+    uint8_t hf_num, hf_den;
+    uint8_t level_min, level_max;
+    uint8_t level_init;
+    uint8_t up_step, down_step;
+    uint8_t reserved;           /* must be 0 */
+} magus_config;
+
+/* Per-trace replay result. */
+typedef struct magus_result {
+    uint64_t score;             /* level_sum + 1000 * transitions             */
+    uint64_t level_sum;         /* sum over steps of the level after the step */
+    uint64_t transitions;       /* steps whose level differs from the last    */
+    uint64_t ticks_high;        /* steps in the high-frequency state          */
+} magus_result;
+
+typedef struct magus_ctx magus_ctx;
+typedef struct magus_server magus_server;
+
+/* Per-step decision byte: bits 0-4 level, bit 5 high, bits 6-7 prediction+1. */
+#define MAGUS_DECISION_LEVEL(b) ((b) & 31u)
+#define MAGUS_DECISION_HIGH(b) (((b) >> 5) & 1u)
+#define MAGUS_DECISION_PRED(b) ((int)(((b) >> 6) & 3u) - 1)
+
+/* Library version string. */
+const char* magus_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* magus_last_error(void);
+
+/* Checks a config on the host; MAGUS_OK or MAGUS_EINVAL. */
+int magus_config_check(const magus_config* h_cfg);
+
+/*
+ * Creates a context on HIP device `device`.  The context owns its scratch
+ * memory (chunk summaries, config tables, device error word), grown on demand
+ * and freed by magus_ctx_destroy.
+ */
+int magus_ctx_create(int device, magus_ctx** out);
+int magus_ctx_destroy(magus_ctx* ctx);
+
+/*
+ * Time-chunk length (steps, a multiple of 64, 64..2^24) used to split long
+ * traces across wavefronts; 0 restores the default.  Results never depend on
+ * it.
+ */
+int magus_ctx_set_chunk(magus_ctx* ctx, uint32_t chunk_steps);
+uint32_t magus_ctx_get_chunk(const magus_ctx* ctx);
+
+/*
+ * Kernel timing.  While enabled, every call records a pair of HIP events on
+ * its stream right before and after its dominant kernel (MAGUS_KERNEL_REPLAY:
+ * the chunk kernel of magus_replay; MAGUS_KERNEL_SWEEP: the sweep kernel;
+ * MAGUS_KERNEL_SERVE: the serve-step kernel of a server on this context).
+ * magus_ctx_kernel_time waits for the recorded events, returns the summed
+ * elapsed time and the number of launches since its last call, and resets.
+ */
+#define MAGUS_KERNEL_REPLAY 0
+#define MAGUS_KERNEL_SWEEP 1
+#define MAGUS_KERNEL_SERVE 2
+int magus_ctx_set_profiling(magus_ctx* ctx, int enable);
+int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t* launches);
+
+/*
+ * Synchronizes `stream` and returns MAGUS_EDATA if a device-side data check
+ * of an earlier call on this context failed since the last check (clearing
+ * it), else MAGUS_OK.
+ */
+int magus_ctx_check(magus_ctx* ctx, hipStream_t stream);
+
+/*
+ * Replay: runs every trace of a CSR batch through the controller.
+ *   d_samples       uint32 throughput samples (MB/s), n_samples of them.
+ *   d_offsets       n_traces+1 uint64, non-decreasing, trace t is
+ *                   samples[offsets[t] .. offsets[t+1]), offsets[n_traces] <=
+ *                   n_samples, each trace at most MAGUS_MAX_TRACE_LEN long.
+ *   h_cfgs          n_cfgs >= 1 configs (host memory, read before return).
+ *   d_cfg_of_trace  NULL (every trace uses h_cfgs[0]) or n_traces uint32
+ *                   indices into h_cfgs.
+ *   d_results       n_traces magus_result (written).
+ *   d_levels        NULL or n_samples bytes: the decision byte of every step,
+ *                   at the sample's own index (samples outside all traces
+ *                   are left untouched).
+ */
+int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                 const uint64_t* d_offsets, uint32_t n_traces,
+                 const magus_config* h_cfgs, uint32_t n_cfgs,
+                 const uint32_t* d_cfg_of_trace, magus_result* d_results,
+                 uint8_t* d_levels, hipStream_t stream);
+
+/*
+ * Parameter sweep: every trace against every config.
+ *   d_scores   NULL or n_traces * n_cfgs uint64, row-major [trace][config].
+ *   d_argmin   n_traces uint32: index of the config with the lowest score,
+ *              the lowest index among equal scores.
+ * Same sample/offset rules as magus_replay, and n_cfgs <= 2^23 (the arg-min
+ * packs score and index into 64 bits; scores of traces of at most
+ * MAGUS_MAX_TRACE_LEN steps stay below 2^41).
+ */
+int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                const uint64_t* d_offsets, uint32_t n_traces,
+                const magus_config* h_cfgs, uint32_t n_cfgs,
+                uint64_t* d_scores, uint32_t* d_argmin, hipStream_t stream);
+
+/*
+ * Serving: a pool of slots, one per live telemetry stream, whose controller
+ * state stays in device memory between steps.
+ *   magus_server_create   capacity = as many slots as `mem_budget_bytes` of
+ *                         device memory holds (magus_server_slot_bytes() each),
+ *                         at least 1; the server owns the pool and its pinned
+ *                         staging buffers.
+ *   magus_stream_open     admits a stream with config h_cfg into a free slot
+ *                         (MAGUS_ENOSLOT if none); its state is reset by the
+ *                         next magus_serve_step on the server.
+ *   magus_stream_close    frees the slot (the slot may be handed out again).
+ *   magus_serve_step      one step for n (slot, sample) pairs: h_slots and
+ *                         h_samples are host arrays (copied before return),
+ *                         every slot must be open and appear at most once
+ *                         (MAGUS_EINVAL otherwise).  Decision bytes for the n
+ *                         pairs are written to h_decisions (host memory; pinned
+ *                         memory lets the copy run asynchronously) once
+ *                         `stream` has completed the step.  Steps of one server
+ *                         must be issued on one stream, or otherwise ordered.
+ *   magus_stream_result   (synchronous) the running magus_result of a slot.
+ */
+size_t magus_server_slot_bytes(void);
+int magus_server_create(magus_ctx* ctx, size_t mem_budget_bytes, magus_server** out);
+int magus_server_destroy(magus_server* srv);
+uint32_t magus_server_capacity(const magus_server* srv);
+uint32_t magus_server_open_count(const magus_server* srv);
+int magus_stream_open(magus_server* srv, const magus_config* h_cfg, uint32_t* slot_out);
+int magus_stream_close(magus_server* srv, uint32_t slot);
+int magus_serve_step(magus_server* srv, const uint32_t* h_slots, const uint32_t* h_samples,
+                     uint32_t n, uint8_t* h_decisions, hipStream_t stream);
+int magus_stream_result(magus_server* srv, uint32_t slot, magus_result* h_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAGUS_H */

@@ -1,0 +1,305 @@
+"""Python binding of libmagus: MAGUS (arXiv 2502.03796) replay, sweep and serving
+on MI355X (gfx950).
+
+Argument marshalling only: every step of the controller runs in the HIP
+kernels behind the C ABI of ``include/magus.h``.  PyTorch supplies device
+memory and streams.  There is no CPU fallback: if ``libmagus.so`` has not been
+built, every entry point raises.
+
+Configs are dicts with the keys ``window, hold, inc_q16, dec_q16, hf_num,
+hf_den, level_min, level_max, level_init`` and optionally ``up_step,
+down_step`` (see ``include/magus.h`` for meaning and ranges).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmagus.so")
+
+OK, EINVAL, ENOMEM, ENOSLOT, EDEVICE, EDATA = 0, -1, -2, -3, -4, -5
+KERNEL_REPLAY, KERNEL_SWEEP, KERNEL_SERVE = 0, 1, 2
+MAX_TRACE_LEN = (1 << 30) - 1
+
+
+class MagusError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"magus error {code}: {msg}")
+        self.code = code
+
+
+class MagusConfig(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_uint16), ("hold", ctypes.c_uint16),
+                ("inc_q16", ctypes.c_int32), ("dec_q16", ctypes.c_int32),
+                ("hf_num", ctypes.c_uint8), ("hf_den", ctypes.c_uint8),
+                ("level_min", ctypes.c_uint8), ("level_max", ctypes.c_uint8),
+                ("level_init", ctypes.c_uint8), ("up_step", ctypes.c_uint8),
+                ("down_step", ctypes.c_uint8), ("reserved", ctypes.c_uint8)]
+
+
+class MagusResult(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_uint64), ("level_sum", ctypes.c_uint64),
+                ("transitions", ctypes.c_uint64), ("ticks_high", ctypes.c_uint64)]
+
+
+assert ctypes.sizeof(MagusConfig) == 20 and ctypes.sizeof(MagusResult) == 32
+
+_lib = None
+
+# name -> (restype, argtypes); every symbol of include/magus.h
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "magus_version": (ctypes.c_char_p, []),
+    "magus_last_error": (ctypes.c_char_p, []),
+    "magus_config_check": (ctypes.c_int, [_P]),
+    "magus_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "magus_ctx_destroy": (ctypes.c_int, [_P]),
+    "magus_ctx_set_chunk": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "magus_ctx_get_chunk": (ctypes.c_uint32, [_P]),
+    "magus_ctx_check": (ctypes.c_int, [_P, _P]),
+    "magus_ctx_set_profiling": (ctypes.c_int, [_P, ctypes.c_int]),
+    "magus_ctx_kernel_time": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+    "magus_replay": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
+                                    ctypes.c_uint32, _P, _P, _P, _P]),
+    "magus_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
+                                   ctypes.c_uint32, _P, _P, _P]),
+    "magus_server_slot_bytes": (ctypes.c_size_t, []),
+    "magus_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "magus_server_destroy": (ctypes.c_int, [_P]),
+    "magus_server_capacity": (ctypes.c_uint32, [_P]),
+    "magus_server_open_count": (ctypes.c_uint32, [_P]),
+    "magus_stream_open": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_uint32)]),
+    "magus_stream_close": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "magus_serve_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, _P]),
+    "magus_stream_result": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(MagusResult)]),
+}
+
+
+def load() -> ctypes.CDLL:
+    """Load libmagus.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "paper_2502_03796_amd.build.build() (no CPU fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise MagusError(rc, load().magus_last_error().decode())
+
+
+def make_config(d: dict) -> MagusConfig:
+    return MagusConfig(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
+                       int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
+                       int(d["level_max"]), int(d["level_init"]), int(d.get("up_step", 0)),
+                       int(d.get("down_step", 0)), 0)
+
+
+def config_array(cfgs) -> ctypes.Array:
+    arr = (MagusConfig * len(cfgs))()
+    for i, d in enumerate(cfgs):
+        arr[i] = make_config(d)
+    return arr
+
+
+def config_check(cfg: dict) -> None:
+    c = make_config(cfg)
+    _check(load().magus_config_check(ctypes.byref(c)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, name, dtypes):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream, device):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A libmagus context on one HIP device (owns scratch memory)."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib.magus_ctx_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().magus_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def chunk(self) -> int:
+        return int(load().magus_ctx_get_chunk(self._h))
+
+    def set_chunk(self, steps: int) -> None:
+        _check(load().magus_ctx_set_chunk(self._h, int(steps)))
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(load().magus_ctx_set_profiling(self._h, int(bool(enable))))
+
+    def kernel_time(self, kernel: int):
+        """(total ms, launches) of the dominant kernel since the last query."""
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        _check(load().magus_ctx_kernel_time(self._h, int(kernel), ctypes.byref(ms),
+                                            ctypes.byref(n)))
+        return ms.value, n.value
+
+    def check(self, stream=None) -> None:
+        """Synchronize and raise MagusError(EDATA) on a device-side data fault."""
+        _check(load().magus_ctx_check(self._h, _stream_handle(stream, self.device)))
+
+    def replay(self, samples, offsets, cfgs, cfg_of_trace=None, levels: bool = False,
+               results=None, levels_out=None, stream=None):
+        """Replay every trace; returns (results int64[n_traces, 4], levels uint8 or None).
+
+        results columns: score, level_sum, transitions, ticks_high.
+        """
+        torch = _torch()
+        cfgs = [cfgs] if isinstance(cfgs, dict) else list(cfgs)
+        sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
+        op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
+        n_traces = offsets.numel() - 1
+        if results is None:
+            results = torch.empty((n_traces, 4), dtype=torch.int64, device=samples.device)
+        rp = _dev_ptr(results, "results", (torch.int64,))
+        cp = None
+        if cfg_of_trace is not None:
+            cp = _dev_ptr(cfg_of_trace, "cfg_of_trace", (torch.int32, torch.uint32))
+        lp = None
+        if levels:
+            if levels_out is None:
+                levels_out = torch.zeros(samples.numel(), dtype=torch.uint8, device=samples.device)
+            lp = _dev_ptr(levels_out, "levels", (torch.uint8,))
+        arr = config_array(cfgs)
+        _check(load().magus_replay(self._h, sp, samples.numel(), op, n_traces, arr, len(cfgs),
+                                   cp, rp, lp, _stream_handle(stream, self.device)))
+        return results, (levels_out if levels else None)
+
+    def sweep(self, samples, offsets, cfgs, scores: bool = False, stream=None):
+        """Every trace against every config; returns (scores int64[T, C] or None, argmin int32[T])."""
+        torch = _torch()
+        cfgs = list(cfgs)
+        sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
+        op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
+        n_traces = offsets.numel() - 1
+        argmin = torch.empty(n_traces, dtype=torch.int32, device=samples.device)
+        sc = None
+        scp = None
+        if scores:
+            sc = torch.empty((n_traces, len(cfgs)), dtype=torch.int64, device=samples.device)
+            scp = _dev_ptr(sc, "scores", (torch.int64,))
+        arr = config_array(cfgs)
+        _check(load().magus_sweep(self._h, sp, samples.numel(), op, n_traces, arr, len(cfgs),
+                                  scp, _dev_ptr(argmin, "argmin", (torch.int32,)),
+                                  _stream_handle(stream, self.device)))
+        return sc, argmin
+
+
+class Server:
+    """Serving slot pool: controller state of every live stream stays on the GPU."""
+
+    def __init__(self, ctx: Context, mem_budget_bytes: int):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(load().magus_server_create(ctx._h, int(mem_budget_bytes), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def slot_bytes() -> int:
+        return int(load().magus_server_slot_bytes())
+
+    @property
+    def capacity(self) -> int:
+        return int(load().magus_server_capacity(self._h))
+
+    @property
+    def open_count(self) -> int:
+        return int(load().magus_server_open_count(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().magus_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open(self, cfg: dict) -> int:
+        c = make_config(cfg)
+        slot = ctypes.c_uint32()
+        _check(load().magus_stream_open(self._h, ctypes.byref(c), ctypes.byref(slot)))
+        return slot.value
+
+    def try_open(self, cfg: dict):
+        """Like open() but returns None when admission is refused (no free slot)."""
+        try:
+            return self.open(cfg)
+        except MagusError as e:
+            if e.code == ENOSLOT:
+                return None
+            raise
+
+    def close_stream(self, slot: int) -> None:
+        _check(load().magus_stream_close(self._h, int(slot)))
+
+    def step(self, slots, samples, decisions=None, stream=None, sync: bool = True):
+        """One step for the given (slot, sample) pairs; returns uint8 decisions."""
+        slots = np.ascontiguousarray(slots, dtype=np.uint32)
+        samples = np.ascontiguousarray(samples, dtype=np.uint32)
+        if slots.shape != samples.shape:
+            raise ValueError("slots and samples differ in length")
+        if decisions is None:
+            decisions = np.empty(len(slots), dtype=np.uint8)
+        sh = _stream_handle(stream, self.ctx.device)
+        _check(load().magus_serve_step(self._h, slots.ctypes.data_as(_P),
+                                       samples.ctypes.data_as(_P), len(slots),
+                                       decisions.ctypes.data_as(_P), sh))
+        if sync:
+            _torch().cuda.current_stream(self.ctx.device).synchronize() if stream is None \
+                else stream.synchronize()
+        return decisions
+
+    def result(self, slot: int) -> dict:
+        r = MagusResult()
+        _check(load().magus_stream_result(self._h, int(slot), ctypes.byref(r)))
+        return {"score": r.score, "level_sum": r.level_sum,
+                "transitions": r.transitions, "ticks_high": r.ticks_high}

@@ -1,0 +1,625 @@
+// Host side of libmagus: the C ABI declared in magus.h.
+//
+// Validates arguments, derives the kernel form of each controller config,
+// owns per-context scratch memory and the serving slot pool, and enqueues the
+// kernels of replay.hip, sweep.hip and serve.hip on the caller's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "magus_internal.h"
+
+using namespace magus;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(MAGUS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr uint32_t kDefaultChunk = 16384;
+
+// Derives the kernel form of a config; MAGUS_OK or MAGUS_EINVAL.
+int derive(const magus_config* c, DevCfg* d) {
+    if (!c) return fail(MAGUS_EINVAL, "config is NULL");
+    if (c->window < 2 || c->window > 32)
+        return fail(MAGUS_EINVAL, "window %u outside 2..32", (unsigned)c->window);
+    if (c->hold < 1 || c->hold > 32)
+        return fail(MAGUS_EINVAL, "hold %u outside 1..32", (unsigned)c->hold);
+    if (c->inc_q16 < 0 || c->inc_q16 > (1 << 20))
+        return fail(MAGUS_EINVAL, "inc_q16 %d outside 0..2^20", c->inc_q16);
+    if (c->dec_q16 > 0 || c->dec_q16 < -(1 << 20))
+        return fail(MAGUS_EINVAL, "dec_q16 %d outside -2^20..0", c->dec_q16);
+    if (c->hf_den == 0 || c->hf_num > c->hf_den)
+        return fail(MAGUS_EINVAL, "high_freq_threshold %u/%u not in [0, 1]",
+                    (unsigned)c->hf_num, (unsigned)c->hf_den);
+    if (c->level_min >= c->level_max || c->level_max > 31)
+        return fail(MAGUS_EINVAL, "levels need min < max <= 31 (got %u, %u)",
+                    (unsigned)c->level_min, (unsigned)c->level_max);
+    if (c->level_init < c->level_min || c->level_init > c->level_max)
+        return fail(MAGUS_EINVAL, "level_init %u outside [min, max]", (unsigned)c->level_init);
+    if (c->up_step || c->down_step)
+        return fail(MAGUS_EINVAL, "only jump-to-bound actuation (steps 0) is supported");
+    if (c->reserved) return fail(MAGUS_EINVAL, "reserved byte must be 0");
+    d->W = c->window;
+    d->H = c->hold;
+    d->mu = (uint32_t)c->window * (uint32_t)c->inc_q16;
+    d->md = (uint32_t)c->window * (uint32_t)(-c->dec_q16);
+    d->inc_q = c->inc_q16;
+    d->dec_q = c->dec_q16;
+    d->thr = ((uint32_t)c->hf_num * c->hold + c->hf_den - 1) / c->hf_den;
+    d->lmin = c->level_min;
+    d->lmax = c->level_max;
+    d->linit = c->level_init;
+    d->pad = 0;
+    return MAGUS_OK;
+}
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return MAGUS_OK;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return fail(MAGUS_EDEVICE, "hipFree: %s", hipGetErrorString(e));
+        }
+        size_t want = std::max(bytes, (size_t)256);
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return fail(MAGUS_ENOMEM, "hipMalloc(%zu) failed", want);
+        }
+        cap = want;
+        return MAGUS_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct magus_ctx {
+    int device = 0;
+    uint32_t chunk = kDefaultChunk;
+    DevBuf err;          // uint32 sticky error word
+    DevBuf chunk_base;   // replay: chunk prefix sum + status
+    DevBuf sums;         // replay: ChunkSum per chunk
+    DevBuf fix;          // replay: ChunkFix per chunk
+    DevBuf cfgs;         // replay: DevCfg table
+    std::vector<DevCfg> cfg_host;   // last uploaded table
+    DevBuf keys;         // sweep: arg-min keys + status
+    DevBuf sweep_tab;    // sweep: lane tables
+    std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
+    SweepPlan plan{};
+    // kernel timing: event pairs recorded around the dominant kernel of a call
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> recorded[3];
+
+    // Returns a pair of events to record for `kernel`, or nulls when off.
+    std::pair<hipEvent_t, hipEvent_t> timing_pair(int kernel) {
+        if (!prof) return {nullptr, nullptr};
+        hipEvent_t e[2] = {nullptr, nullptr};
+        for (auto& ev : e) {
+            if (!ev_pool.empty()) {
+                ev = ev_pool.back();
+                ev_pool.pop_back();
+            } else if (hipEventCreate(&ev) != hipSuccess) {
+                ev = nullptr;
+            }
+        }
+        if (!e[0] || !e[1]) {
+            for (auto ev : e)
+                if (ev) ev_pool.push_back(ev);
+            return {nullptr, nullptr};
+        }
+        recorded[kernel].push_back({e[0], e[1]});
+        return {e[0], e[1]};
+    }
+};
+
+struct magus_server {
+    magus_ctx* ctx = nullptr;
+    uint32_t cap = 0;
+    DevBuf st, acc, slot_cfg;
+    std::vector<uint8_t> open;
+    std::vector<DevCfg> host_cfg;
+    std::vector<uint32_t> free_slots;
+    std::map<uint32_t, DevCfg> pending;     // slots to (re)initialise at the next step
+    std::vector<uint32_t> mark;              // duplicate detection per step
+    uint32_t epoch = 0;
+    struct Stage {
+        uint32_t* h_pairs = nullptr;
+        ServeInit* h_inits = nullptr;
+        uint32_t cap_pairs = 0, cap_inits = 0;
+        DevBuf d_pairs, d_inits, d_dec;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    static constexpr int kStages = 3;
+    Stage stages[kStages];
+    uint32_t next_stage = 0;
+};
+
+extern "C" {
+
+const char* magus_version(void) { return "magus-mi355x 0.1 (gfx950)"; }
+
+const char* magus_last_error(void) { return g_last_error.c_str(); }
+
+int magus_config_check(const magus_config* h_cfg) {
+    DevCfg d;
+    return derive(h_cfg, &d);
+}
+
+int magus_ctx_create(int device, magus_ctx** out) {
+    if (!out) return fail(MAGUS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return fail(MAGUS_EINVAL, "no HIP device %d (%d visible)", device, n);
+    DeviceGuard g(device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", device);
+    magus_ctx* c = new magus_ctx();
+    c->device = device;
+    int rc = c->err.ensure(256);
+    if (rc == MAGUS_OK && hipMemset(c->err.p, 0, 256) != hipSuccess)
+        rc = fail(MAGUS_EDEVICE, "hipMemset failed");
+    if (rc != MAGUS_OK) {
+        c->err.release();
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return MAGUS_OK;
+}
+
+int magus_ctx_destroy(magus_ctx* ctx) {
+    if (!ctx) return MAGUS_OK;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (DevBuf* b : {&ctx->err, &ctx->chunk_base, &ctx->sums, &ctx->fix, &ctx->cfgs,
+                          &ctx->keys, &ctx->sweep_tab})
+            b->release();
+        for (auto& r : ctx->recorded)
+            for (auto& pr : r) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+        for (auto ev : ctx->ev_pool) (void)hipEventDestroy(ev);
+    }
+    delete ctx;
+    return MAGUS_OK;
+}
+
+int magus_ctx_set_chunk(magus_ctx* ctx, uint32_t chunk_steps) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (chunk_steps == 0) chunk_steps = kDefaultChunk;
+    if (chunk_steps % 64 || chunk_steps > (1u << 24))
+        return fail(MAGUS_EINVAL, "chunk %u is not a multiple of 64 in 64..2^24", chunk_steps);
+    ctx->chunk = chunk_steps;
+    return MAGUS_OK;
+}
+
+uint32_t magus_ctx_get_chunk(const magus_ctx* ctx) { return ctx ? ctx->chunk : 0; }
+
+int magus_ctx_set_profiling(magus_ctx* ctx, int enable) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    ctx->prof = enable != 0;
+    return MAGUS_OK;
+}
+
+int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t* launches) {
+    if (!ctx || !total_ms || !launches) return fail(MAGUS_EINVAL, "NULL argument");
+    if (kernel < 0 || kernel > 2) return fail(MAGUS_EINVAL, "unknown kernel id %d", kernel);
+    DeviceGuard g(ctx->device);
+    double sum = 0.0;
+    uint64_t n = 0;
+    int rc = MAGUS_OK;
+    for (auto& pr : ctx->recorded[kernel]) {
+        float ms = 0.f;
+        if (rc == MAGUS_OK) {
+            hipError_t e = hipEventSynchronize(pr.second);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+            if (e != hipSuccess)
+                rc = fail(MAGUS_EDEVICE, "event timing: %s", hipGetErrorString(e));
+        }
+        sum += ms;
+        ++n;
+        ctx->ev_pool.push_back(pr.first);
+        ctx->ev_pool.push_back(pr.second);
+    }
+    ctx->recorded[kernel].clear();
+    *total_ms = sum;
+    *launches = n;
+    return rc;
+}
+
+int magus_ctx_check(magus_ctx* ctx, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(hipStreamSynchronize(stream));
+    uint32_t e = 0;
+    HIP_TRY(hipMemcpy(&e, ctx->err.p, 4, hipMemcpyDeviceToHost));
+    if (e) {
+        HIP_TRY(hipMemset(ctx->err.p, 0, 4));
+        return fail(MAGUS_EDATA, "device data check failed:%s%s%s",
+                    (e & kErrOffsets) ? " offsets not monotone or beyond n_samples" : "",
+                    (e & kErrTooLong) ? " trace longer than MAGUS_MAX_TRACE_LEN" : "",
+                    (e & kErrCfgIndex) ? " cfg_of_trace index out of range" : "");
+    }
+    return MAGUS_OK;
+}
+
+int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                 const uint64_t* d_offsets, uint32_t n_traces, const magus_config* h_cfgs,
+                 uint32_t n_cfgs, const uint32_t* d_cfg_of_trace, magus_result* d_results,
+                 uint8_t* d_levels, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (!h_cfgs || n_cfgs == 0) return fail(MAGUS_EINVAL, "need at least one config");
+    if (n_traces && (!d_offsets || !d_results))
+        return fail(MAGUS_EINVAL, "offsets and results are required");
+    if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
+    if (n_traces > (1u << 30)) return fail(MAGUS_EINVAL, "too many traces");
+    std::vector<DevCfg> tab(n_cfgs);
+    for (uint32_t i = 0; i < n_cfgs; ++i) {
+        int rc = derive(&h_cfgs[i], &tab[i]);
+        if (rc != MAGUS_OK)
+            return fail(rc, "config %u: %s", i, std::string(g_last_error).c_str());
+    }
+    if (n_traces == 0) return MAGUS_OK;
+    const uint64_t max_chunks64 = n_samples / ctx->chunk + n_traces + 1;
+    if (max_chunks64 > 0xFFFFFFF0ull) return fail(MAGUS_EINVAL, "batch too large for one call");
+    const uint32_t max_chunks = (uint32_t)max_chunks64;
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    int rc;
+    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
+        (rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum))) ||
+        (rc = ctx->cfgs.ensure((size_t)n_cfgs * sizeof(DevCfg))))
+        return rc;
+    if (d_levels && (rc = ctx->fix.ensure((size_t)max_chunks * sizeof(ChunkFix)))) return rc;
+    const bool same = ctx->cfg_host.size() == tab.size() &&
+                      std::memcmp(ctx->cfg_host.data(), tab.data(), tab.size() * sizeof(DevCfg)) == 0;
+    if (!same) {
+        // pageable source: the runtime stages it before returning
+        HIP_TRY(hipMemcpyAsync(ctx->cfgs.p, tab.data(), tab.size() * sizeof(DevCfg),
+                               hipMemcpyHostToDevice, stream));
+        ctx->cfg_host = tab;
+    }
+    const auto tp = ctx->timing_pair(MAGUS_KERNEL_REPLAY);
+    HIP_TRY(launch_replay(d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(),
+                          n_cfgs, d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(),
+                          ctx->sums.as<ChunkSum>(), max_chunks,
+                          d_levels ? ctx->fix.as<ChunkFix>() : nullptr, d_results, d_levels,
+                          ctx->err.as<uint32_t>(), stream, tp.first, tp.second));
+    return MAGUS_OK;
+}
+
+int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                const uint64_t* d_offsets, uint32_t n_traces, const magus_config* h_cfgs,
+                uint32_t n_cfgs, uint64_t* d_scores, uint32_t* d_argmin, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (!h_cfgs || n_cfgs == 0) return fail(MAGUS_EINVAL, "need at least one config");
+    if (n_cfgs > (1u << 23)) return fail(MAGUS_EINVAL, "at most 2^23 configs per sweep");
+    if (n_traces && (!d_offsets || !d_argmin))
+        return fail(MAGUS_EINVAL, "offsets and argmin are required");
+    if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
+    std::vector<DevCfg> tab(n_cfgs);
+    for (uint32_t i = 0; i < n_cfgs; ++i) {
+        int rc = derive(&h_cfgs[i], &tab[i]);
+        if (rc != MAGUS_OK)
+            return fail(rc, "config %u: %s", i, std::string(g_last_error).c_str());
+    }
+    if (n_traces == 0) return MAGUS_OK;
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    const bool same = ctx->sweep_cfg_host.size() == n_cfgs &&
+                      std::memcmp(ctx->sweep_cfg_host.data(), h_cfgs,
+                                  (size_t)n_cfgs * sizeof(magus_config)) == 0;
+    if (!same) {
+        // Group configs by window into blocks of kSweepLanes lanes.
+        std::vector<uint32_t> order(n_cfgs);
+        for (uint32_t i = 0; i < n_cfgs; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t a, uint32_t b) { return tab[a].W < tab[b].W; });
+        std::vector<uint32_t> bw;
+        std::vector<int32_t> inc, dec;
+        std::vector<uint32_t> hmask, thr, lv, orig;
+        size_t i = 0;
+        while (i < order.size()) {
+            const uint32_t W = tab[order[i]].W;
+            bw.push_back(W);
+            for (int l = 0; l < kSweepLanes; ++l) {
+                if (i < order.size() && tab[order[i]].W == W) {
+                    const DevCfg& d = tab[order[i]];
+                    inc.push_back(d.inc_q);
+                    dec.push_back(d.dec_q);
+                    hmask.push_back(d.H >= 32 ? 0xFFFFFFFFu : ((1u << d.H) - 1u));
+                    thr.push_back(d.thr);
+                    lv.push_back(d.lmin | (d.lmax << 8) | (d.linit << 16));
+                    orig.push_back(order[i]);
+                    ++i;
+                } else {   // padding lane: never predicts, never reported
+                    inc.push_back(INT32_MAX);
+                    dec.push_back(INT32_MIN);
+                    hmask.push_back(1u);
+                    thr.push_back(1u);
+                    lv.push_back(0u | (1u << 8));
+                    orig.push_back(0xFFFFFFFFu);
+                }
+            }
+        }
+        const uint32_t nb = (uint32_t)bw.size();
+        if ((uint64_t)nb * n_traces >= (1ull << 31))
+            return fail(MAGUS_EINVAL, "traces x config blocks too large for one call");
+        const size_t nl = (size_t)nb * kSweepLanes;
+        const size_t bytes = nb * 4 + nl * 4 * 6 + 6 * 256;
+        int rc;
+        if ((rc = ctx->sweep_tab.ensure(bytes))) return rc;
+        std::vector<uint8_t> host(bytes, 0);
+        size_t off = 0;
+        auto put = [&](const void* src, size_t n) {
+            size_t at = off;
+            std::memcpy(host.data() + at, src, n);
+            off += (n + 255) & ~(size_t)255;
+            return at;
+        };
+        size_t o_bw = put(bw.data(), nb * 4), o_inc = put(inc.data(), nl * 4),
+               o_dec = put(dec.data(), nl * 4), o_hm = put(hmask.data(), nl * 4),
+               o_thr = put(thr.data(), nl * 4), o_lv = put(lv.data(), nl * 4),
+               o_orig = put(orig.data(), nl * 4);
+        HIP_TRY(hipMemcpyAsync(ctx->sweep_tab.p, host.data(), off, hipMemcpyHostToDevice, stream));
+        char* base = ctx->sweep_tab.as<char>();
+        ctx->plan.n_blocks = nb;
+        ctx->plan.block_w = reinterpret_cast<const uint32_t*>(base + o_bw);
+        ctx->plan.lane_inc = reinterpret_cast<const int32_t*>(base + o_inc);
+        ctx->plan.lane_dec = reinterpret_cast<const int32_t*>(base + o_dec);
+        ctx->plan.lane_hmask = reinterpret_cast<const uint32_t*>(base + o_hm);
+        ctx->plan.lane_thr = reinterpret_cast<const uint32_t*>(base + o_thr);
+        ctx->plan.lane_lv = reinterpret_cast<const uint32_t*>(base + o_lv);
+        ctx->plan.lane_orig = reinterpret_cast<const uint32_t*>(base + o_orig);
+        ctx->sweep_cfg_host.assign(h_cfgs, h_cfgs + n_cfgs);
+    }
+    if ((uint64_t)ctx->plan.n_blocks * n_traces >= (1ull << 31))
+        return fail(MAGUS_EINVAL, "traces x config blocks too large for one call");
+    int rc;
+    if ((rc = ctx->keys.ensure(((size_t)n_traces + 1) * 8))) return rc;
+    const auto tp = ctx->timing_pair(MAGUS_KERNEL_SWEEP);
+    HIP_TRY(launch_sweep(d_samples, n_samples, d_offsets, n_traces, ctx->plan, n_cfgs, d_scores,
+                         d_argmin, ctx->keys.as<uint64_t>(), ctx->err.as<uint32_t>(), stream,
+                         tp.first, tp.second));
+    return MAGUS_OK;
+}
+
+// ------------------------------------------------------------------ serving
+
+size_t magus_server_slot_bytes(void) {
+    return sizeof(SlotState) + sizeof(SlotAcc) + sizeof(DevCfg);
+}
+
+int magus_server_create(magus_ctx* ctx, size_t mem_budget_bytes, magus_server** out) {
+    if (!ctx || !out) return fail(MAGUS_EINVAL, "ctx/out is NULL");
+    *out = nullptr;
+    const size_t per = magus_server_slot_bytes();
+    const size_t cap64 = mem_budget_bytes / per;
+    if (cap64 == 0) return fail(MAGUS_ENOSLOT, "budget %zu B holds no slot (%zu B each)",
+                                mem_budget_bytes, per);
+    if (cap64 > (1u << 26)) return fail(MAGUS_EINVAL, "at most 2^26 slots");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    magus_server* s = new magus_server();
+    s->ctx = ctx;
+    s->cap = (uint32_t)cap64;
+    int rc;
+    if ((rc = s->st.ensure((size_t)s->cap * sizeof(SlotState))) ||
+        (rc = s->acc.ensure((size_t)s->cap * sizeof(SlotAcc))) ||
+        (rc = s->slot_cfg.ensure((size_t)s->cap * sizeof(DevCfg)))) {
+        magus_server_destroy(s);
+        return rc;
+    }
+    for (auto& st : s->stages) {
+        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+            magus_server_destroy(s);
+            return fail(MAGUS_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    s->open.assign(s->cap, 0);
+    s->host_cfg.resize(s->cap);
+    s->mark.assign(s->cap, 0);
+    s->free_slots.reserve(s->cap);
+    for (uint32_t i = s->cap; i-- > 0;) s->free_slots.push_back(i);
+    *out = s;
+    return MAGUS_OK;
+}
+
+int magus_server_destroy(magus_server* s) {
+    if (!s) return MAGUS_OK;
+    {
+        DeviceGuard g(s->ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto& st : s->stages) {
+            if (st.h_pairs) (void)hipHostFree(st.h_pairs);
+            if (st.h_inits) (void)hipHostFree(st.h_inits);
+            st.d_pairs.release();
+            st.d_inits.release();
+            st.d_dec.release();
+            if (st.done) (void)hipEventDestroy(st.done);
+        }
+        s->st.release();
+        s->acc.release();
+        s->slot_cfg.release();
+    }
+    delete s;
+    return MAGUS_OK;
+}
+
+uint32_t magus_server_capacity(const magus_server* s) { return s ? s->cap : 0; }
+
+uint32_t magus_server_open_count(const magus_server* s) {
+    return s ? s->cap - (uint32_t)s->free_slots.size() : 0;
+}
+
+int magus_stream_open(magus_server* s, const magus_config* h_cfg, uint32_t* slot_out) {
+    if (!s || !slot_out) return fail(MAGUS_EINVAL, "server/slot_out is NULL");
+    DevCfg d;
+    int rc = derive(h_cfg, &d);
+    if (rc != MAGUS_OK) return rc;
+    if (s->free_slots.empty())
+        return fail(MAGUS_ENOSLOT, "all %u slots are in use", s->cap);
+    const uint32_t slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    s->open[slot] = 1;
+    s->host_cfg[slot] = d;
+    s->pending[slot] = d;
+    *slot_out = slot;
+    return MAGUS_OK;
+}
+
+int magus_stream_close(magus_server* s, uint32_t slot) {
+    if (!s) return fail(MAGUS_EINVAL, "server is NULL");
+    if (slot >= s->cap || !s->open[slot]) return fail(MAGUS_EINVAL, "slot %u is not open", slot);
+    s->open[slot] = 0;
+    s->pending.erase(slot);
+    s->free_slots.push_back(slot);
+    return MAGUS_OK;
+}
+
+int magus_serve_step(magus_server* s, const uint32_t* h_slots, const uint32_t* h_samples,
+                     uint32_t n, uint8_t* h_decisions, hipStream_t stream) {
+    if (!s) return fail(MAGUS_EINVAL, "server is NULL");
+    if (n && (!h_slots || !h_samples || !h_decisions))
+        return fail(MAGUS_EINVAL, "slots/samples/decisions is NULL");
+    if (++s->epoch == 0) {
+        std::fill(s->mark.begin(), s->mark.end(), 0);
+        s->epoch = 1;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t slot = h_slots[i];
+        if (slot >= s->cap || !s->open[slot])
+            return fail(MAGUS_EINVAL, "pair %u: slot %u is not open", i, slot);
+        if (s->mark[slot] == s->epoch)
+            return fail(MAGUS_EINVAL, "pair %u: slot %u appears twice in one step", i, slot);
+        s->mark[slot] = s->epoch;
+    }
+    const uint32_t n_inits = (uint32_t)s->pending.size();
+    if (n == 0 && n_inits == 0) return MAGUS_OK;
+
+    DeviceGuard g(s->ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", s->ctx->device);
+    magus_server::Stage& st = s->stages[s->next_stage];
+    s->next_stage = (s->next_stage + 1) % magus_server::kStages;
+    if (st.used) HIP_TRY(hipEventSynchronize(st.done));   // staging buffers free again
+    if (st.cap_pairs < n) {
+        if (st.h_pairs) (void)hipHostFree(st.h_pairs);
+        st.h_pairs = nullptr;
+        st.cap_pairs = 0;
+        const uint32_t c = std::max<uint32_t>(n, 1024);
+        if (hipHostMalloc((void**)&st.h_pairs, (size_t)c * 8, hipHostMallocDefault) != hipSuccess)
+            return fail(MAGUS_ENOMEM, "hipHostMalloc(%zu) failed", (size_t)c * 8);
+        int rc;
+        if ((rc = st.d_pairs.ensure((size_t)c * 8)) || (rc = st.d_dec.ensure(c))) return rc;
+        st.cap_pairs = c;
+    }
+    if (st.cap_inits < n_inits) {
+        if (st.h_inits) (void)hipHostFree(st.h_inits);
+        st.h_inits = nullptr;
+        st.cap_inits = 0;
+        const uint32_t c = std::max<uint32_t>(n_inits, 256);
+        if (hipHostMalloc((void**)&st.h_inits, (size_t)c * sizeof(ServeInit),
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(MAGUS_ENOMEM, "hipHostMalloc failed");
+        int rc;
+        if ((rc = st.d_inits.ensure((size_t)c * sizeof(ServeInit)))) return rc;
+        st.cap_inits = c;
+    }
+    uint32_t k = 0;
+    for (const auto& kv : s->pending) {
+        st.h_inits[k].slot = kv.first;
+        st.h_inits[k].pad = 0;
+        st.h_inits[k].cfg = kv.second;
+        ++k;
+    }
+    std::memcpy(st.h_pairs, h_slots, (size_t)n * 4);
+    std::memcpy(st.h_pairs + n, h_samples, (size_t)n * 4);
+    if (n_inits)
+        HIP_TRY(hipMemcpyAsync(st.d_inits.p, st.h_inits, (size_t)n_inits * sizeof(ServeInit),
+                               hipMemcpyHostToDevice, stream));
+    if (n)
+        HIP_TRY(hipMemcpyAsync(st.d_pairs.p, st.h_pairs, (size_t)n * 8, hipMemcpyHostToDevice,
+                               stream));
+    const auto tp = s->ctx->timing_pair(MAGUS_KERNEL_SERVE);
+    HIP_TRY(launch_serve(s->st.as<SlotState>(), s->acc.as<SlotAcc>(), s->slot_cfg.as<DevCfg>(),
+                         st.d_inits.as<ServeInit>(), n_inits, st.d_pairs.as<uint32_t>(), n,
+                         st.d_dec.as<uint8_t>(), stream, tp.first, tp.second));
+    if (n)
+        HIP_TRY(hipMemcpyAsync(h_decisions, st.d_dec.p, n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipEventRecord(st.done, stream));
+    st.used = true;
+    s->pending.clear();
+    return MAGUS_OK;
+}
+
+int magus_stream_result(magus_server* s, uint32_t slot, magus_result* h_out) {
+    if (!s || !h_out) return fail(MAGUS_EINVAL, "server/out is NULL");
+    if (slot >= s->cap || !s->open[slot]) return fail(MAGUS_EINVAL, "slot %u is not open", slot);
+    if (s->pending.count(slot)) {       // opened, no step yet
+        std::memset(h_out, 0, sizeof *h_out);
+        return MAGUS_OK;
+    }
+    DeviceGuard g(s->ctx->device);
+    HIP_TRY(hipDeviceSynchronize());
+    SlotAcc a;
+    HIP_TRY(hipMemcpy(&a, s->acc.as<SlotAcc>() + slot, sizeof a, hipMemcpyDeviceToHost));
+    h_out->level_sum = a.level_sum;
+    h_out->transitions = a.transitions;
+    h_out->ticks_high = a.ticks_high;
+    h_out->score = a.level_sum + 1000ull * a.transitions;
+    return MAGUS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal types shared by the host side and the gfx950 kernels of libmagus.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "magus.h"
+
+namespace magus {
+
+constexpr int kWave = 64;
+
+// Controller parameters in the form the kernels use (derived on the host from
+// magus_config).  32 bytes.
+struct DevCfg {
+    uint32_t W;          // derivative window
+    uint32_t H;          // event FIFO length
+    uint32_t mu;         // W * inc_q16    (E1': (hi-lo) * 2^16 > lo * mu -> +1)
+    uint32_t md;         // W * |dec_q16|  (E1': (hi-lo) * 2^16 > lo * md -> -1)
+    int32_t inc_q;       // inc_q16 (sweep quotient form)
+    int32_t dec_q;       // dec_q16
+    uint32_t thr;        // ceil(hf_num * H / hf_den): high iff events >= thr
+    uint8_t lmin, lmax, linit, pad;
+};
+static_assert(sizeof(DevCfg) == 32, "DevCfg layout");
+
+// Summary of one time chunk of one trace, computed without knowing the level
+// entering the chunk (taken as level_min for the bit vector).  32 bytes.
+struct ChunkSum {
+    uint32_t len;        // steps in the chunk
+    uint32_t prefix;     // steps before the first decisive step (== len if none)
+    uint32_t first_up;   // the first decisive step sets level_max (1) or level_min (0)
+    uint32_t end_up;     // level after the last step is level_max (valid if prefix < len)
+    uint32_t cnt_max;    // steps at level_max
+    uint32_t trans0;     // level changes, counting the entering level as level_min
+    uint32_t ticks_high; // steps in the high state
+    uint32_t pad;
+};
+static_assert(sizeof(ChunkSum) == 32, "ChunkSum layout");
+
+// Per-chunk fix-up record for per-step output: the steps before the first
+// decisive step of a chunk take the level entering the chunk, known only after
+// the chunk summaries of the trace are folded.
+struct ChunkFix {
+    uint64_t start;      // absolute index of the chunk's first sample
+    uint32_t prefix;     // steps to fix
+    uint32_t level;      // level entering the chunk (written by the fold)
+};
+
+// Device error word bits.
+enum : uint32_t {
+    kErrOffsets = 1u,    // offsets not monotone / beyond n_samples
+    kErrTooLong = 2u,    // a trace longer than MAGUS_MAX_TRACE_LEN
+    kErrCfgIndex = 4u,   // cfg_of_trace out of range
+};
+
+// Kernel launchers (replay.hip / sweep.hip / serve.hip).  When ev0/ev1 are
+// not null they are recorded on `stream` right before and after the dominant
+// kernel of the call (the chunk, sweep or serve-step kernel).
+hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
+                         uint32_t n_traces, const DevCfg* cfgs, uint32_t n_cfgs,
+                         const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
+                         ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
+                         magus_result* results, uint8_t* levels, uint32_t* err,
+                         hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
+struct SweepPlan {
+    uint32_t n_blocks;        // config blocks of kSweepLanes lanes, one window each
+    const uint32_t* block_w;  // [n_blocks]
+    const int32_t* lane_inc;  // [n_blocks * kSweepLanes]
+    const int32_t* lane_dec;
+    const uint32_t* lane_hmask;
+    const uint32_t* lane_thr;
+    const uint32_t* lane_lv;  // lmin | lmax << 8 | linit << 16
+    const uint32_t* lane_orig;// original config index, 0xFFFFFFFF = padding
+};
+constexpr int kSweepLanes = 256;
+
+hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
+                        uint32_t n_traces, const SweepPlan& plan, uint32_t n_cfgs,
+                        uint64_t* scores, uint32_t* argmin, uint64_t* keys, uint32_t* err,
+                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
+// Serving slot state.
+struct SlotState {
+    uint32_t ring[31];   // last W-1 samples, sample k at ring[k % (W-1)]
+    uint32_t ticks;      // samples seen
+};
+static_assert(sizeof(SlotState) == 128, "SlotState layout");
+struct SlotAcc {
+    uint64_t level_sum;
+    uint64_t transitions;
+    uint64_t ticks_high;
+    uint32_t hist;       // event flags, newest in bit 0
+    uint32_t level;
+};
+static_assert(sizeof(SlotAcc) == 32, "SlotAcc layout");
+
+struct ServeInit {       // (re)initialises one slot
+    uint32_t slot;
+    uint32_t pad;
+    DevCfg cfg;
+};
+
+hipError_t launch_serve(SlotState* st, SlotAcc* acc, DevCfg* slot_cfg,
+                        const ServeInit* inits, uint32_t n_inits,
+                        const uint32_t* pairs /* slot[n] then sample[n] */, uint32_t n,
+                        uint8_t* decisions, hipStream_t stream, hipEvent_t ev0,
+                        hipEvent_t ev1);
+
+}  // namespace magus

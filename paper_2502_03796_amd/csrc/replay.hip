@@ -1,0 +1,410 @@
+// Batched replay of the MAGUS controller on gfx950.
+//
+// A trace is cut into time chunks; each 64-lane wavefront replays one chunk
+// with one lane per step.  The prediction (Alg. 1), the event flag, the event
+// count over the last H steps (Alg. 2) and the decisive steps are all pure
+// functions of the samples, so a wave evaluates 64 consecutive steps at once
+// and turns them into 64-bit lane masks.  Only the level is recurrent: with
+// jump-to-bound actuation (Sec. 6.1) the level after a step is level_max or
+// level_min as set by the most recent decisive step, which is a carry chain of
+// a 64-bit addition.  Per chunk the wave therefore produces a summary that does
+// not depend on the level entering the chunk, and a per-trace fold composes
+// the summaries in order.
+//
+// Kernels, in stream order:
+//   plan    prefix sum of chunks per trace + device-side data checks
+//   chunks  one wave per chunk -> ChunkSum (and decision bytes if asked)
+//   fold    one thread per trace -> magus_result
+//   fixup   (decision bytes only) level of the steps before the first
+//           decisive step of each chunk
+
+#include "magus_internal.h"
+
+namespace magus {
+
+__device__ int llvm_writelane(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+namespace {
+
+constexpr int kChunkWavesPerBlock = 4;
+constexpr int kPlanThreads = 1024;
+constexpr int kPrefetch = 8;          // blocks of 64 samples in flight per wave
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
+
+// Number of bits of `m` strictly below this lane.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m, uint32_t acc) {
+    return __builtin_amdgcn_mbcnt_hi(hi32(m), __builtin_amdgcn_mbcnt_lo(lo32(m), acc));
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
+    uint32_t l = __builtin_amdgcn_readlane((int)lo32(v), (int)lane);
+    uint32_t h = __builtin_amdgcn_readlane((int)hi32(v), (int)lane);
+    return ((uint64_t)h << 32) | l;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t low_mask(uint32_t n) {   // n in [0, 64]
+    return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+}
+
+// ------------------------------------------------------------------ plan
+
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(
+    const uint64_t* __restrict__ offsets, uint32_t n_traces, uint64_t n_samples,
+    const uint32_t* __restrict__ cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
+    uint32_t max_chunks, uint32_t* __restrict__ chunk_base, uint32_t* __restrict__ err)
+{
+    __shared__ uint32_t wave_sum[kPlanThreads / kWave];
+    __shared__ uint32_t s_running;
+    __shared__ uint32_t s_err;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) { s_running = 0; s_err = 0; }
+    __syncthreads();
+    for (uint32_t base = 0; base < n_traces; base += kPlanThreads) {
+        const uint32_t t = base + tid;
+        uint32_t nch = 0, e = 0;
+        if (t < n_traces) {
+            const uint64_t o0 = offsets[t], o1 = offsets[t + 1];
+            if (o1 < o0 || o1 > n_samples) {
+                e |= kErrOffsets;
+            } else if (o1 - o0 > MAGUS_MAX_TRACE_LEN) {
+                e |= kErrTooLong;
+            } else {
+                nch = (uint32_t)((o1 - o0 + chunk - 1) / chunk);
+            }
+            if (cfg_of_trace && cfg_of_trace[t] >= n_cfgs) e |= kErrCfgIndex;
+        }
+        if (e) atomicOr(&s_err, e);
+        // inclusive scan inside the wave
+        uint32_t v = nch;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            uint32_t o = __shfl_up(v, d, 64);
+            if (lane >= (uint32_t)d) v += o;
+        }
+        if (lane == 63) wave_sum[wv] = v;
+        __syncthreads();
+        if (wv == 0) {
+            uint32_t w = lane < kPlanThreads / kWave ? wave_sum[lane] : 0;
+#pragma unroll
+            for (int d = 1; d < kPlanThreads / kWave; d <<= 1) {
+                uint32_t o = __shfl_up(w, d, 64);
+                if (lane >= (uint32_t)d) w += o;
+            }
+            if (lane < kPlanThreads / kWave) wave_sum[lane] = w;   // inclusive
+        }
+        __syncthreads();
+        const uint32_t before = s_running + (wv ? wave_sum[wv - 1] : 0);
+        if (t < n_traces) chunk_base[t] = before + v - nch;
+        __syncthreads();
+        if (tid == 0) s_running += wave_sum[kPlanThreads / kWave - 1];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        uint32_t total = s_running;
+        uint32_t e = s_err;
+        if (total > max_chunks) e |= kErrOffsets;
+        chunk_base[n_traces] = e ? 0u : total;
+        chunk_base[n_traces + 1] = e;            // status of this call
+        if (e) atomicOr(err, e);
+    }
+}
+
+// ------------------------------------------------------------------ chunks
+
+// One wave replays one chunk [s, e) of trace t.
+template <bool kLevels>
+__global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
+    uint8_t* __restrict__ levels)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * kChunkWavesPerBlock + uniform(threadIdx.x >> 6);
+    const uint32_t total = chunk_base[n_traces];
+    if (g >= total) return;
+
+    // trace of this chunk: the last t with chunk_base[t] <= g
+    uint32_t lo = 0, hi = n_traces;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (chunk_base[mid] <= g) lo = mid; else hi = mid;
+    }
+    const uint32_t t = lo;
+    const uint64_t tbase = offsets[t];
+    const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
+    const uint32_t s = (g - chunk_base[t]) * chunk;
+    const uint32_t e = min(s + chunk, n);
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    const uint32_t W = c.W, H = c.H;
+
+    // Samples [wbeg, e) of the trace through a bounds-checked buffer
+    // descriptor: the warm-up block [s-64, s) feeds the FIFOs of the first
+    // steps of the chunk; loads past e return 0.
+    const uint32_t wbeg = s >= 64 ? s - 64 : 0;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(samples + tbase + wbeg), (short)0, (int)((e - wbeg) * 4u), 0x00020000);
+    const uint32_t nblk = (e - wbeg + 63) >> 6;          // blocks incl. warm-up
+    const uint32_t first_real = s >= 64 ? 1u : 0u;
+
+    // per-lane constants
+    const int bperm_addr = (int)(((lane - (W - 1)) & 63u) << 2);
+    const bool from_cur = lane >= W - 1;
+    const uint32_t thr_lane = c.thr + lane;
+
+    uint32_t xq[kPrefetch];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i)
+        xq[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((i * 64 + lane) * 4), 0, 0);
+
+    uint32_t xprev = 0;
+    uint64_t fps = 0;            // (previous block's flags) >> 1
+    uint32_t th = 0;             // steps in the high state
+    // group of up to 64 blocks, block j's masks held by lane j
+    uint32_t upL = 0, upH = 0, dnL = 0, dnH = 0;
+    uint32_t puL = 0, puH = 0, pdL = 0, pdH = 0, hmL = 0, hmH = 0;
+    uint32_t gi = 0;             // blocks in the current group
+    uint32_t g0 = s;             // first step of the current group
+    uint32_t gcarry = 0;         // level bit entering the group
+    uint32_t cnt_max = 0, trans0 = 0;   // per lane
+    bool found = false;
+    uint32_t prefix = e - s, first_up = 0;
+
+    auto flush_group = [&]() {
+        const bool act = lane < gi;
+        const uint64_t up = act ? (((uint64_t)upH << 32) | upL) : 0ull;
+        const uint64_t dn = act ? (((uint64_t)dnH << 32) | dnL) : 0ull;
+        const uint64_t d = up | dn;
+        const uint64_t HAS = ballot(d != 0);
+        const uint64_t LUP = ballot(up > dn);        // the last decisive step sets max
+        // level bit entering every block: carries of ~DNB + LUP + gcarry
+        const uint64_t ndnb = ~(HAS & ~LUP);
+        const uint64_t s1 = ndnb + LUP;
+        const uint32_t k1 = s1 < ndnb;
+        const uint64_t s2 = s1 + gcarry;
+        const uint32_t k2 = s2 < s1;
+        const uint64_t cin_mask = ~(s2 ^ HAS);
+        const uint32_t cin = (uint32_t)(cin_mask >> lane) & 1u;
+        // level bits inside block `lane`
+        const uint64_t nd = ~dn;
+        const uint64_t t1 = nd + up;
+        const uint64_t c1 = t1 < nd;
+        const uint64_t t2 = t1 + cin;
+        const uint64_t c2 = t2 < t1;
+        const uint64_t C = ~(t2 ^ d);                 // level bit before each step
+        const uint64_t L = (C >> 1) | ((c1 | c2) << 63);   // level bit after each step
+        const uint32_t bstart = g0 + lane * 64;
+        const uint32_t nvalid = act ? min(64u, e - bstart) : 0u;
+        const uint64_t vm = low_mask(nvalid);
+        cnt_max += __popcll(L & vm);
+        trans0 += __popcll((L ^ C) & vm);
+        if (!found && HAS) {
+            const uint32_t j0 = (uint32_t)__builtin_ctzll(HAS);
+            const uint64_t dj = readlane64(d, j0);
+            const uint64_t uj = readlane64(up, j0);
+            const uint32_t b0 = (uint32_t)__builtin_ctzll(dj);
+            prefix = g0 + j0 * 64 + b0 - s;
+            first_up = (uint32_t)(uj >> b0) & 1u;
+            found = true;
+        }
+        if constexpr (kLevels) {
+            const uint64_t pu = act ? (((uint64_t)puH << 32) | puL) : 0ull;
+            const uint64_t pd = act ? (((uint64_t)pdH << 32) | pdL) : 0ull;
+            const uint64_t hm = act ? (((uint64_t)hmH << 32) | hmL) : 0ull;
+            for (uint32_t j = 0; j < gi; ++j) {
+                const uint64_t Lj = readlane64(L, j), PUj = readlane64(pu, j);
+                const uint64_t PDj = readlane64(pd, j), HMj = readlane64(hm, j);
+                const uint32_t step = g0 + j * 64 + lane;
+                if (step < e) {
+                    const uint32_t lv = ((Lj >> lane) & 1) ? c.lmax : c.lmin;
+                    const uint32_t pr = ((PUj >> lane) & 1) ? 2u : (((PDj >> lane) & 1) ? 0u : 1u);
+                    const uint32_t hb = (uint32_t)(HMj >> lane) & 1u;
+                    levels[tbase + step] = (uint8_t)(lv | (hb << 5) | (pr << 6));
+                }
+            }
+        }
+        gcarry = k1 | k2;
+        g0 += gi * 64;
+        gi = 0;
+    };
+
+    for (uint32_t b0 = 0; b0 < nblk; b0 += kPrefetch) {
+#pragma unroll
+        for (int i = 0; i < kPrefetch; ++i) {
+            const uint32_t blk = b0 + i;
+            if (blk >= nblk) break;
+            const uint32_t x = xq[i];
+            xq[i] = __builtin_amdgcn_raw_buffer_load_b32(
+                rsrc, (int)(((blk + kPrefetch) * 64 + lane) * 4), 0, 0);
+            const uint32_t tb = wbeg + blk * 64;        // trace step of lane 0
+
+            // Alg. 1 on this step: a = x[t-W+1] (oldest), b = x[t] (newest)
+            const uint32_t a_cur = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)x);
+            const uint32_t a_prv = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)xprev);
+            const uint32_t a = from_cur ? a_cur : a_prv;
+            const uint32_t b = x;
+            const bool rising = b > a;
+            const uint32_t hiv = max(a, b), lov = min(a, b);
+            const uint32_t m = rising ? c.mu : c.md;
+            // r = (hi-lo)/(W lo) beyond the threshold q/2^16  <=>  (hi-lo) 2^16 > lo (W q)
+            bool ev = ((uint64_t)(hiv - lov) << 16) > (uint64_t)lov * m;
+            if (tb < W - 1) ev = ev && (lane >= W - 1 - tb);   // FIFO not yet full
+            uint64_t E = ballot(ev);
+            const uint64_t R = ballot(rising);
+            const uint32_t nvalid = min(64u, e - tb);
+            const uint64_t vm = low_mask(nvalid);
+            E &= vm;
+            xprev = x;
+
+            if (blk < first_real) {                       // warm-up block
+                fps = E >> 1;
+                continue;
+            }
+            // Alg. 2: events among the last H steps, for all 64 steps at once
+            const uint64_t B = fps >> (64 - H);           // last H-1 flags of the previous block
+            const uint64_t nG = ~((E << (H - 1)) | B);    // ~(flags H-1 steps back)
+            const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(E & 1ull);
+            const uint32_t cnt = mbcnt(nG, mbcnt(E >> 1, acc0));
+            const uint64_t HM = ballot(cnt >= thr_lane) & vm;
+            fps = E >> 1;
+
+            const uint64_t PU = E & R, PD = E & ~R;
+            const uint64_t UP = HM | PU;                  // high or +1 -> max
+            const uint64_t DN = PD & ~HM;                 // -1 executed -> min
+            th += (uint32_t)__popcll(HM);
+            upL = (uint32_t)llvm_writelane((int)lo32(UP), (int)gi, (int)upL);
+            upH = (uint32_t)llvm_writelane((int)hi32(UP), (int)gi, (int)upH);
+            dnL = (uint32_t)llvm_writelane((int)lo32(DN), (int)gi, (int)dnL);
+            dnH = (uint32_t)llvm_writelane((int)hi32(DN), (int)gi, (int)dnH);
+            if constexpr (kLevels) {
+                puL = (uint32_t)llvm_writelane((int)lo32(PU), (int)gi, (int)puL);
+                puH = (uint32_t)llvm_writelane((int)hi32(PU), (int)gi, (int)puH);
+                pdL = (uint32_t)llvm_writelane((int)lo32(PD), (int)gi, (int)pdL);
+                pdH = (uint32_t)llvm_writelane((int)hi32(PD), (int)gi, (int)pdH);
+                hmL = (uint32_t)llvm_writelane((int)lo32(HM), (int)gi, (int)hmL);
+                hmH = (uint32_t)llvm_writelane((int)hi32(HM), (int)gi, (int)hmH);
+            }
+            if (++gi == 64) flush_group();
+        }
+    }
+    if (gi) flush_group();
+
+    // wave sums of the per-lane counters
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        cnt_max += __shfl_xor(cnt_max, d, 64);
+        trans0 += __shfl_xor(trans0, d, 64);
+    }
+    if (lane == 0) {
+        ChunkSum r;
+        r.len = e - s;
+        r.prefix = prefix;
+        r.first_up = first_up;
+        r.end_up = gcarry;
+        r.cnt_max = cnt_max;
+        r.trans0 = trans0;
+        r.ticks_high = th;
+        r.pad = 0;
+        sums[g] = r;
+        if constexpr (kLevels) {
+            fix[g].start = tbase + s;
+            fix[g].prefix = prefix;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fold
+
+__global__ __launch_bounds__(256) void fold_kernel(
+    const uint64_t* __restrict__ offsets, uint32_t n_traces,
+    const uint32_t* __restrict__ chunk_base, const ChunkSum* __restrict__ sums,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    magus_result* __restrict__ results, ChunkFix* __restrict__ fix)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    uint64_t level = c.linit, level_sum = 0, trans = 0, th = 0;
+    for (uint32_t k = chunk_base[t]; k < chunk_base[t + 1]; ++k) {
+        const ChunkSum S = sums[k];
+        if (fix) fix[k].level = (uint32_t)level;
+        if (S.prefix >= S.len) {
+            level_sum += level * S.len;
+        } else {
+            const uint64_t first = S.first_up ? c.lmax : c.lmin;
+            level_sum += level * S.prefix + (uint64_t)c.lmax * S.cnt_max +
+                         (uint64_t)c.lmin * (S.len - S.prefix - S.cnt_max);
+            trans += S.trans0 - S.first_up + (first != level);
+            level = S.end_up ? c.lmax : c.lmin;
+        }
+        th += S.ticks_high;
+    }
+    magus_result r;
+    r.score = level_sum + 1000ull * trans;
+    r.level_sum = level_sum;
+    r.transitions = trans;
+    r.ticks_high = th;
+    results[t] = r;
+}
+
+// ------------------------------------------------------------------ fixup
+
+__global__ __launch_bounds__(256) void fixup_kernel(
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const ChunkFix* __restrict__ fix, uint8_t* __restrict__ levels)
+{
+    if (chunk_base[n_traces + 1] != 0) return;
+    const uint32_t total = chunk_base[n_traces];
+    for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
+        const ChunkFix f = fix[k];
+        for (uint32_t i = threadIdx.x; i < f.prefix; i += blockDim.x) {
+            uint8_t* p = levels + f.start + i;
+            *p = (uint8_t)((*p & 0xE0u) | f.level);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
+                         uint32_t n_traces, const DevCfg* cfgs, uint32_t n_cfgs,
+                         const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
+                         ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
+                         magus_result* results, uint8_t* levels, uint32_t* err,
+                         hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (n_traces == 0) return hipSuccess;
+    plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
+                                                n_cfgs, chunk, max_chunks, chunk_base, err);
+    const uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
+    if (ev0) (void)hipEventRecord(ev0, stream);
+    if (blocks) {
+        if (levels)
+            chunk_kernel<true><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
+                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, fix,
+                levels);
+        else
+            chunk_kernel<false><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
+                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums,
+                nullptr, nullptr);
+    }
+    if (ev1) (void)hipEventRecord(ev1, stream);
+    fold_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
+        offsets, n_traces, chunk_base, sums, cfgs, cfg_of_trace, results,
+        levels ? fix : nullptr);
+    if (levels && blocks)
+        fixup_kernel<<<min(max_chunks, 65535u), 256, 0, stream>>>(n_traces, chunk_base, fix,
+                                                                   levels);
+    return hipGetLastError();
+}
+
+}  // namespace magus

@@ -1,0 +1,230 @@
+"""GPU parity of magus_replay against the oracle: bit-exact per-step decision
+bytes and per-trace results, through the C ABI."""
+import ctypes
+import itertools
+
+import numpy as np
+import pytest
+
+import paper_2502_03796_amd as magus
+import synth
+from synth import default_config
+from tests.gpu_util import to_dev, results_np, describe_mismatch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = magus.Context(0)
+    yield c
+    c.close()
+
+
+def run_both(ctx, oracle_mod, traces, cfgs, cot=None, chunk=None, levels=True):
+    samples, offsets = synth.make_batch(traces)
+    want_res, want_b = oracle_mod.replay_batch(samples, offsets, cfgs, cot, want_bytes=levels)
+    s, o, c = to_dev(samples, offsets, cot)
+    if chunk is not None:
+        ctx.set_chunk(chunk)
+    try:
+        res, lv = ctx.replay(s, o, cfgs, c, levels=levels)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    got_res = results_np(res)
+    assert (got_res == want_res).all(), describe_mismatch(got_res[:, 0], want_res[:, 0])
+    if levels:
+        got_b = lv.cpu().numpy()
+        assert (got_b == want_b).all(), describe_mismatch(got_b, want_b, offsets)
+    return got_res
+
+
+def pin_traces():
+    return [
+        [777] * 300, [0] * 70, [2**32 - 1] * 65,
+        [10000] * 40 + [20000] * 60,
+        [65536] * 4 + [91752] * 4, [65536] * 4 + [91753] * 4,
+        [40000] * 40 + [10000] * 60,
+        [10000, 20000] * 50,
+        [10000, 20000] * 10 + [20000] * 30,
+        [30000] * 20 + [10000] * 20 + [40000] * 20 + [9000] * 20,
+        [1, 2], [5], [],
+    ]
+
+
+@pytest.mark.parametrize("cfg", [default_config(), default_config(window=16),
+                                 default_config(window=2), default_config(hold=1),
+                                 default_config(hf_num=0), default_config(level_init=7),
+                                 default_config(level_min=3, level_max=31, level_init=31)])
+def test_pin_traces(ctx, oracle_mod, cfg):
+    traces = [np.array(t, np.uint32) for t in pin_traces()]
+    run_both(ctx, oracle_mod, traces, [cfg])
+
+
+def test_brute_force_tiny_traces(ctx, oracle_mod):
+    traces = [np.array(t, np.uint32) for n in range(0, 6)
+              for t in itertools.product(range(5), repeat=n)]
+    for W, H, inc, dec in itertools.product((2, 3, 4), (1, 2, 3, 5), (0, 16384, 65536),
+                                            (0, -16384, -32768)):
+        cfg = default_config(window=W, hold=H, inc_q16=inc, dec_q16=dec)
+        run_both(ctx, oracle_mod, traces, [cfg])
+
+
+def mixed_traces(seed, lengths):
+    out = []
+    for i, n in enumerate(lengths):
+        key = synth.stream_key(seed, i)
+        kind = i % 3
+        if kind == 0:
+            out.append(synth.four_phase_trace(n, key))
+        elif kind == 1:
+            out.append(synth.geometric_phase_trace(n, key, mean=30.0, short_prob=0.3))
+        else:
+            out.append(synth.geometric_phase_trace(n, key, mean=200.0, short_prob=0.1))
+    return out
+
+
+LENGTHS = [0, 1, 2, 31, 32, 63, 64, 65, 127, 128, 129, 4095, 4096, 4097, 8191, 8192, 8193,
+           16383, 16384, 16385, 20000, 33333, 70001]
+
+
+@pytest.mark.parametrize("chunk", [64, 128, 192, 4096, 4160, 16384, 65536])
+def test_chunking_never_changes_results(ctx, oracle_mod, chunk):
+    """Chunk boundaries at every offset class, incl. chunks of one block."""
+    traces = mixed_traces(31 + chunk, LENGTHS)
+    grid = synth.sweep_grid()
+    rng = np.random.default_rng(chunk)
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), 40)] + [default_config()]
+    cot = rng.integers(0, len(cfgs), len(traces)).astype(np.uint32)
+    run_both(ctx, oracle_mod, traces, cfgs, cot, chunk=chunk)
+
+
+def test_random_configs_all_windows_and_holds(ctx, oracle_mod):
+    rng = np.random.default_rng(7)
+    cfgs = []
+    for W in range(2, 33):
+        for H in (1, 2, 7, 16, 31, 32):
+            lmin = int(rng.integers(0, 20))
+            lmax = int(rng.integers(lmin + 1, 32))
+            den = int(rng.integers(1, 10))
+            cfgs.append(default_config(window=W, hold=H,
+                                       inc_q16=int(rng.integers(0, 2**20 + 1)) >> int(rng.integers(0, 12)),
+                                       dec_q16=-(int(rng.integers(0, 2**20 + 1)) >> int(rng.integers(0, 12))),
+                                       hf_num=int(rng.integers(0, den + 1)), hf_den=den,
+                                       level_min=lmin, level_max=lmax,
+                                       level_init=int(rng.integers(lmin, lmax + 1))))
+    traces = mixed_traces(77, [int(v) for v in rng.integers(0, 3000, len(cfgs))])
+    cot = np.arange(len(traces), dtype=np.uint32)
+    for chunk in (64, 1024):
+        run_both(ctx, oracle_mod, traces, cfgs, cot, chunk=chunk)
+
+
+def test_extreme_sample_values(ctx, oracle_mod):
+    rng = np.random.default_rng(3)
+    traces = []
+    for i in range(40):
+        x = rng.integers(0, 2**32, size=int(rng.integers(1, 600)), dtype=np.uint64)
+        x[rng.random(len(x)) < 0.1] = 0
+        x[rng.random(len(x)) < 0.1] = 2**32 - 1
+        traces.append(x.astype(np.uint32))
+    for W, q in ((2, 2**20), (32, 2**20), (7, 1), (3, 12345), (16, 0)):
+        run_both(ctx, oracle_mod, traces, [default_config(window=W, hold=3, inc_q16=q,
+                                                          dec_q16=-q)], chunk=128)
+
+
+def test_small_workload(ctx, oracle_mod):
+    """One four-phase trace of 10,000 samples, default config: every step."""
+    samples, offsets = synth.workload_small()
+    run_both(ctx, oracle_mod, [samples], [default_config()])
+
+
+def test_run_twice_is_bitwise_identical(ctx):
+    samples, offsets = synth.make_batch(mixed_traces(5, [50000] * 64))
+    s, o, _ = to_dev(samples, offsets)
+    r1, l1 = ctx.replay(s, o, [default_config()], levels=True)
+    r2, l2 = ctx.replay(s, o, [default_config()], levels=True)
+    r3, _ = ctx.replay(s, o, [default_config()])
+    assert (r1 == r2).all() and (l1 == l2).all() and (r1 == r3).all()
+
+
+def test_offsets_not_starting_at_zero(ctx, oracle_mod):
+    """Traces are views into a larger sample array; samples before the first
+    and after the last trace are never read or written."""
+    traces = mixed_traces(9, [500, 700, 64, 1000])
+    offs = np.array([10, 510, 1210, 1274, 2274], np.uint64)
+    big = np.full(2400, 123456789, np.uint32)
+    for t, x in enumerate(traces):
+        big[int(offs[t]):int(offs[t + 1])] = x
+    s, o, _ = to_dev(big, offs)
+    res, lv = ctx.replay(s, o, [default_config()], levels=True)
+    ctx.check()
+    got = lv.cpu().numpy()
+    for t, x in enumerate(traces):
+        r, b = oracle_mod.replay_trace(x, default_config())
+        assert (got[int(offs[t]):int(offs[t + 1])] == b).all()
+        assert results_np(res)[t][0] == r["score"]
+    assert (got[:10] == 0).all() and (got[2274:] == 0).all()
+
+
+def test_device_data_faults_are_reported_not_run(ctx):
+    import torch
+    samples, offsets = synth.make_batch(mixed_traces(1, [100, 100]))
+    s, o, _ = to_dev(samples, offsets)
+    bad = torch.tensor([0, 150, 100], dtype=torch.int64, device="cuda")   # not monotone
+    ctx.replay(s, bad, [default_config()])
+    with pytest.raises(magus.MagusError) as ei:
+        ctx.check()
+    assert ei.value.code == magus.EDATA
+    beyond = torch.tensor([0, 100, 201], dtype=torch.int64, device="cuda")
+    ctx.replay(s, beyond, [default_config()])
+    with pytest.raises(magus.MagusError):
+        ctx.check()
+    cot = torch.tensor([0, 5], dtype=torch.int32, device="cuda")      # index out of range
+    ctx.replay(s, o, [default_config()], cfg_of_trace=cot)
+    with pytest.raises(magus.MagusError):
+        ctx.check()
+    # a trace longer than the maximum (claimed sizes; the kernels read nothing)
+    lib = magus.load()
+    huge = torch.tensor([0, 1 << 30], dtype=torch.int64, device="cuda")
+    res = torch.empty((1, 4), dtype=torch.int64, device="cuda")
+    arr = magus.config_array([default_config()])
+    rc = lib.magus_replay(ctx._h, ctypes.c_void_p(s.data_ptr()), 1 << 31,
+                          ctypes.c_void_p(huge.data_ptr()), 1, arr, 1, None,
+                          ctypes.c_void_p(res.data_ptr()), None,
+                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    with pytest.raises(magus.MagusError):
+        ctx.check()
+    ctx.check()                      # cleared
+    r, _ = ctx.replay(s, o, [default_config()])
+    ctx.check()
+
+
+@pytest.fixture(scope="module")
+def bulk():
+    return synth.workload_bulk()
+
+
+def test_bulk_workload_full_size_sampled(ctx, oracle_mod, bulk):
+    """4,096 x 100,000 samples, single default config, the benchmark's launch:
+    results of a sample of traces against the oracle, one by one."""
+    samples, offsets = bulk
+    s, o, _ = to_dev(samples, offsets)
+    res, _ = ctx.replay(s, o, [default_config()])
+    ctx.check()
+    got = results_np(res)
+    rng = np.random.default_rng(2)
+    pick = sorted(set(rng.integers(0, 4096, 48).tolist()) | {0, 4095})
+    for t in pick:
+        x = samples[int(offsets[t]):int(offsets[t + 1])]
+        r, _ = oracle_mod.replay_trace(x, default_config(), want_bytes=False)
+        assert list(got[t]) == [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]], t
+    # per-step bytes of the same launch for the first traces
+    _, lv = ctx.replay(s, o, [default_config()], levels=True)
+    head = int(offsets[8])
+    _, want = oracle_mod.replay_batch(samples[:head], offsets[:9], [default_config()],
+                                      want_bytes=True)
+    assert (lv[:head].cpu().numpy() == want).all()

@@ -1,0 +1,142 @@
+"""Serving: each stream's decisions are the same alone, in a mix with joins
+and leaves, and as a plain replay of its samples by the oracle (exact)."""
+import numpy as np
+import pytest
+
+import paper_2502_03796_amd as magus
+import synth
+from synth import default_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = magus.Context(0)
+    yield c
+    c.close()
+
+
+def oracle_bytes(oracle_mod, x, cfg):
+    r, b = oracle_mod.replay_trace(np.asarray(x, np.uint32), cfg)
+    return r, b
+
+
+def test_single_stream_matches_replay(ctx, oracle_mod):
+    srv = magus.Server(ctx, 1 << 20)
+    cfg = default_config()
+    x = synth.serve_stream_samples(0, 3000)
+    slot = srv.open(cfg)
+    got = np.array([srv.step([slot], [v])[0] for v in x], np.uint8)
+    r, want = oracle_bytes(oracle_mod, x, cfg)
+    assert (got == want).all()
+    assert srv.result(slot) == r
+    srv.close()
+
+
+def test_mix_with_joins_and_leaves_matches_alone(ctx, oracle_mod):
+    """64 streams with random configs join and leave over 400 ticks; at every
+    tick only a random subset of the live streams delivers a sample (jitter),
+    slots are reused after leaves, and admission is bounded by a memory budget
+    of 40 slots."""
+    rng = np.random.default_rng(12)
+    n_streams, n_ticks = 64, 400
+    grid = synth.sweep_grid()
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), n_streams)]
+    data = [synth.serve_stream_samples(100 + i, n_ticks) for i in range(n_streams)]
+    join = rng.integers(0, n_ticks // 2, n_streams)
+    leave = np.minimum(join + rng.integers(50, n_ticks, n_streams), n_ticks)
+    srv = magus.Server(ctx, 40 * magus.Server.slot_bytes())
+    assert srv.capacity == 40
+    slot_of = {}
+    pos = np.zeros(n_streams, np.int64)      # next sample of each stream
+    got = {i: [] for i in range(n_streams)}
+    refused = 0
+    for tick in range(n_ticks):
+        for i in range(n_streams):
+            if i in slot_of and leave[i] == tick:
+                srv.close_stream(slot_of.pop(i))
+        for i in range(n_streams):
+            if i not in slot_of and join[i] <= tick < leave[i] and pos[i] == 0:
+                s = srv.try_open(cfgs[i])
+                if s is None:
+                    refused += 1
+                else:
+                    slot_of[i] = s
+        live = [i for i in slot_of if rng.random() < 0.8 and pos[i] < n_ticks]
+        if not live:
+            continue
+        slots = [slot_of[i] for i in live]
+        samples = [data[i][pos[i]] for i in live]
+        dec = srv.step(slots, samples)
+        for i, d in zip(live, dec):
+            got[i].append(d)
+            pos[i] += 1
+    assert refused > 0                       # admission was exercised
+    checked = 0
+    for i in range(n_streams):
+        if not got[i]:
+            continue
+        x = data[i][:pos[i]]
+        _, want = oracle_bytes(oracle_mod, x, cfgs[i])
+        assert (np.array(got[i], np.uint8) == want).all(), i
+        checked += 1
+    assert checked > 30
+    srv.close()
+
+
+def test_step_rejects_bad_pairs(ctx):
+    srv = magus.Server(ctx, 4 * magus.Server.slot_bytes())
+    a = srv.open(default_config())
+    with pytest.raises(magus.MagusError) as ei:
+        srv.step([a, a], [1, 2])
+    assert ei.value.code == magus.EINVAL
+    with pytest.raises(magus.MagusError):
+        srv.step([3], [1])                   # not open
+    for _ in range(3):
+        srv.open(default_config())
+    assert srv.try_open(default_config()) is None
+    with pytest.raises(magus.MagusError) as ei:
+        srv.open(default_config())
+    assert ei.value.code == magus.ENOSLOT
+    srv.close_stream(a)
+    assert srv.try_open(default_config()) == a
+    srv.close()
+
+
+def test_reused_slot_starts_fresh(ctx, oracle_mod):
+    srv = magus.Server(ctx, 1 * magus.Server.slot_bytes())
+    cfg = default_config(window=2)
+    a = srv.open(cfg)
+    for v in [10000, 20000] * 20:
+        srv.step([a], [v])
+    srv.close_stream(a)
+    b = srv.open(cfg)
+    assert b == a
+    x = [5000] * 10 + [9000] * 10
+    got = np.array([srv.step([b], [v])[0] for v in x], np.uint8)
+    _, want = oracle_bytes(oracle_mod, x, cfg)
+    assert (got == want).all()
+    srv.close()
+
+
+def test_full_fleet_tick(ctx, oracle_mod):
+    """65,536 streams, 20 ticks, one batched step per tick; sampled streams
+    against the oracle."""
+    n, ticks = 65536, 20
+    srv = magus.Server(ctx, n * magus.Server.slot_bytes())
+    grid = synth.sweep_grid()
+    cfg_idx = (np.arange(n) * 2654435761) % len(grid)
+    slots = np.array([srv.open(grid[int(c)]) for c in cfg_idx], np.uint32)
+    rng = np.random.default_rng(1)
+    data = rng.integers(500, 400000, size=(ticks, n)).astype(np.uint32)
+    data[:, ::7] = data[0, ::7]                       # some steady streams
+    out = np.zeros((ticks, n), np.uint8)
+    for k in range(ticks):
+        out[k] = srv.step(slots, data[k])
+    for i in list(range(0, n, 4099)) + [n - 1]:
+        _, want = oracle_bytes(oracle_mod, data[:, i], grid[int(cfg_idx[i])])
+        assert (out[:, i] == want).all(), i
+    srv.close()

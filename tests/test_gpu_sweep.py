@@ -1,0 +1,108 @@
+"""GPU parity of magus_sweep: scores and arg-min against the oracle, and the
+sweep against the plain replay of each config on the same GPU."""
+import numpy as np
+import pytest
+
+import paper_2502_03796_amd as magus
+import synth
+from synth import default_config
+from tests.gpu_util import to_dev, results_np, describe_mismatch
+from tests.test_gpu_replay import mixed_traces
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = magus.Context(0)
+    yield c
+    c.close()
+
+
+def sweep_both(ctx, oracle_mod, traces, cfgs):
+    samples, offsets = synth.make_batch(traces)
+    want_scores, want_arg = oracle_mod.sweep(samples, offsets, cfgs)
+    s, o, _ = to_dev(samples, offsets)
+    sc, arg = ctx.sweep(s, o, cfgs, scores=True)
+    ctx.check()
+    got = sc.cpu().numpy().view(np.uint64)
+    assert (got == want_scores).all(), describe_mismatch(got.ravel(), want_scores.ravel())
+    assert (arg.cpu().numpy().astype(np.uint32) == want_arg).all()
+    return got
+
+
+def test_grid_sample_on_mixed_traces(ctx, oracle_mod):
+    grid = synth.sweep_grid()
+    idx = list(range(0, 16384, 37)) + [0, 1, 4095, 4096, 8191, 16383]
+    cfgs = [grid[i] for i in idx]
+    traces = mixed_traces(101, [0, 1, 5, 64, 255, 256, 257, 1000, 3000, 5000])
+    sweep_both(ctx, oracle_mod, traces, cfgs)
+
+
+def test_unsorted_windows_and_padding(ctx, oracle_mod):
+    """Configs in arbitrary window order, blocks that need padding lanes, and
+    every kind of initial level."""
+    rng = np.random.default_rng(4)
+    cfgs = []
+    for i in range(700):
+        lmin = int(rng.integers(0, 10))
+        lmax = int(rng.integers(lmin + 1, 32))
+        den = int(rng.integers(1, 8))
+        cfgs.append(default_config(window=int(rng.integers(2, 33)), hold=int(rng.integers(1, 33)),
+                                   inc_q16=int(rng.integers(0, 70000)),
+                                   dec_q16=-int(rng.integers(0, 70000)),
+                                   hf_num=int(rng.integers(0, den + 1)), hf_den=den,
+                                   level_min=lmin, level_max=lmax,
+                                   level_init=int(rng.choice([lmin, lmax,
+                                                              int(rng.integers(lmin, lmax + 1))]))))
+    traces = mixed_traces(202, [700, 2000, 1, 0, 333])
+    sweep_both(ctx, oracle_mod, traces, cfgs)
+
+
+def test_ties_take_the_lowest_index(ctx, oracle_mod):
+    """A constant trace scores 0 under every config: arg-min is config 0; with a
+    duplicated best config the lower index wins."""
+    traces = [np.full(500, 1234, np.uint32), np.array([10000, 20000] * 200, np.uint32)]
+    cfgs = [synth.sweep_config(i) for i in (5000, 77, 77, 16000, 9)]
+    got = sweep_both(ctx, oracle_mod, traces, cfgs)
+    assert (got[0] == 0).all()
+
+
+def test_sweep_equals_replay_on_the_gpu(ctx, oracle_mod):
+    """Cross-form parity: scores of the sweep == scores of the plain replay of
+    each config on the same traces."""
+    import torch
+    traces = mixed_traces(303, [4000] * 16)
+    samples, offsets = synth.make_batch(traces)
+    s, o, _ = to_dev(samples, offsets)
+    cfgs = [synth.sweep_config(i) for i in range(0, 16384, 211)]
+    sc, _ = ctx.sweep(s, o, cfgs, scores=True)
+    for j, c in enumerate(cfgs):
+        res, _ = ctx.replay(s, o, [c])
+        assert (res[:, 0] == sc[:, j]).all(), j
+    ctx.check()
+
+
+def test_sweep_workload_full_size_sampled(ctx, oracle_mod):
+    """1,024 traces x 50,000 samples x one window block of 4,096 configs (the
+    benchmark's sweep launch): arg-min of sampled traces and the scores of a
+    stratified config sample against the oracle."""
+    samples, offsets = synth.workload_sweep_traces()
+    grid = synth.sweep_grid()
+    for wblock in (0, 3):
+        cfgs = grid[wblock * 4096:(wblock + 1) * 4096]
+        s, o, _ = to_dev(samples, offsets)
+        sc, arg = ctx.sweep(s, o, cfgs, scores=True)
+        ctx.check()
+        sc = sc.cpu().numpy().view(np.uint64)
+        arg = arg.cpu().numpy()
+        rng = np.random.default_rng(wblock)
+        cpick = np.arange(int(rng.integers(0, 16)), 4096, 16)    # 1/16 of the configs
+        for t in (0, 511, 1023):
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            sub = synth.make_batch([x])
+            want, _ = oracle_mod.sweep(sub[0], sub[1], [cfgs[i] for i in cpick])
+            assert (sc[t, cpick] == want[0]).all(), t
+            assert sc[t].min() == sc[t, arg[t]] and (sc[t, :arg[t]] > sc[t, arg[t]]).all()
