@@ -63,6 +63,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip sweep/serve/fp64 reports")
     ap.add_argument("--serve-ticks", type=int, default=100)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain elementwise copy kernel over as many bytes as the "
+                         "bulk workload (read 4 B + write 4 B per sample), for scaling HBM "
+                         "counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -76,6 +80,16 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.traces * args.length
+        a = torch.zeros(n, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.bitwise_xor(a, 1, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "bitwise_xor int32", "elements": n,
+                          "read_bytes": 4 * n, "write_bytes": 4 * n, "launches": 3}))
+        return
     log(f"generating bulk workload {args.traces} x {args.length} ...")
     t0 = time.time()
     samples, offsets = synth.workload_bulk(args.traces, args.length)
