@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip sweep/serve/fp64 reports")
     ap.add_argument("--serve-ticks", type=int, default=100)
+    ap.add_argument("--chunk", type=int, default=0, help="time-chunk length (0: default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy kernel over as many bytes as the "
                          "bulk workload (read 4 B + write 4 B per sample), for scaling HBM "
@@ -99,6 +100,7 @@ def main():
     o = torch.from_numpy(offsets.view(np.int64)).to(dev)
     cfg = synth.default_config()
     ctx = magus.Context(0)
+    ctx.set_chunk(args.chunk)
     results = torch.empty((args.traces, 4), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
 

@@ -211,6 +211,60 @@ int magus_serve_step(magus_server* srv, const uint32_t* h_slots, const uint32_t*
                      uint32_t n, uint8_t* h_decisions, hipStream_t stream);
 int magus_stream_result(magus_server* srv, uint32_t slot, magus_result* h_out);
 
+/*
+ * Serving loop with continuous batching (one simulated fleet of nodes).
+ * Events are sorted by t_ns (nanoseconds from the start of the run):
+ *   MAGUS_EV_JOIN    node `stream` asks to be served with config
+ *                    h_cfgs[value]; it is admitted into a free slot at once,
+ *                    or waits (oldest first) until a leave frees one.
+ *   MAGUS_EV_SAMPLE  one throughput sample `value` of node `stream`; dropped
+ *                    unless the node is admitted.
+ *   MAGUS_EV_LEAVE   the node stops; its slot is freed once its pending
+ *                    samples are served.
+ * realtime != 0 ingests each event at its time and measures latency from that
+ * time; realtime == 0 runs flat out (latency from the start of the run).
+ * Every dispatch forms one batch of at most max_batch pairs (0: the server's
+ * capacity) from the oldest pending sample of each admitted node, and up to
+ * `depth` (1..4) batches are in flight: copies in, the state-update kernel and
+ * the copy out run on three server-owned streams, so one batch's copies
+ * overlap another's kernel; kernels run in arrival order.
+ * Per event i: h_decisions[i] = decision byte of a served sample (0xFF for
+ * other events and dropped samples), h_latency_ns[i] = event time to
+ * decision visible in host memory (UINT64_MAX if none).  Stream ids must be
+ * below n_streams.  The run admits its nodes into the server's free slots and
+ * closes them before it returns; streams opened outside the run keep their
+ * slots but are not stepped by it.
+ */
+#define MAGUS_EV_SAMPLE 0u
+#define MAGUS_EV_JOIN 1u
+#define MAGUS_EV_LEAVE 2u
+
+typedef struct magus_event {
+    uint64_t t_ns;
+    uint32_t kind;
+    uint32_t stream;
+    uint32_t value;
+    uint32_t reserved;
+} magus_event;
+
+typedef struct magus_run_stats {
+    uint64_t samples_served;
+    uint64_t samples_dropped;    /* samples of nodes not admitted at the time */
+    uint64_t batches;
+    uint64_t max_batch;          /* largest batch dispatched                    */
+    uint64_t max_in_flight;      /* most batches in flight at once              */
+    uint64_t deferred;           /* samples that waited for a later batch       */
+    uint64_t joins_admitted;     /* admitted on arrival                         */
+    uint64_t joins_waited;       /* admitted after waiting for a slot           */
+    uint64_t joins_refused;      /* left, or the run ended, while waiting       */
+    double wall_s;
+} magus_run_stats;
+
+int magus_server_run(magus_server* srv, const magus_event* h_events, uint64_t n_events,
+                     uint32_t n_streams, const magus_config* h_cfgs, uint32_t n_cfgs,
+                     int realtime, uint32_t max_batch, uint32_t depth,
+                     uint8_t* h_decisions, uint64_t* h_latency_ns, magus_run_stats* h_stats);
+
 #ifdef __cplusplus
 }
 #endif

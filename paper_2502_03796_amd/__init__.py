@@ -45,7 +45,20 @@ class MagusResult(ctypes.Structure):
                 ("transitions", ctypes.c_uint64), ("ticks_high", ctypes.c_uint64)]
 
 
+class MagusRunStats(ctypes.Structure):
+    _fields_ = [("samples_served", ctypes.c_uint64), ("samples_dropped", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("max_batch", ctypes.c_uint64),
+                ("max_in_flight", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("joins_admitted", ctypes.c_uint64), ("joins_waited", ctypes.c_uint64),
+                ("joins_refused", ctypes.c_uint64), ("wall_s", ctypes.c_double)]
+
+
+EV_SAMPLE, EV_JOIN, EV_LEAVE = 0, 1, 2
+EVENT_DTYPE = np.dtype([("t_ns", "<u8"), ("kind", "<u4"), ("stream", "<u4"),
+                        ("value", "<u4"), ("reserved", "<u4")])
+
 assert ctypes.sizeof(MagusConfig) == 20 and ctypes.sizeof(MagusResult) == 32
+assert EVENT_DTYPE.itemsize == 24
 
 _lib = None
 
@@ -76,6 +89,10 @@ SIGNATURES = {
     "magus_stream_close": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "magus_serve_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, _P]),
     "magus_stream_result": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(MagusResult)]),
+    "magus_server_run": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P,
+                                        ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
+                                        ctypes.c_uint32, _P, _P,
+                                        ctypes.POINTER(MagusRunStats)]),
 }
 
 
@@ -297,6 +314,26 @@ class Server:
             _torch().cuda.current_stream(self.ctx.device).synchronize() if stream is None \
                 else stream.synchronize()
         return decisions
+
+    def run(self, events, n_streams: int, cfgs, realtime: bool = True, max_batch: int = 0,
+            depth: int = 2):
+        """Serve a time-sorted fleet event list with continuous batching.
+
+        Returns (decisions uint8[n_events], latency_ns uint64[n_events], stats dict);
+        decisions are 0xFF and latencies 2^64-1 for non-sample events and for
+        samples of nodes that were not admitted.
+        """
+        ev = np.ascontiguousarray(events, dtype=EVENT_DTYPE)
+        arr = config_array(list(cfgs))
+        dec = np.empty(len(ev), np.uint8)
+        lat = np.empty(len(ev), np.uint64)
+        st = MagusRunStats()
+        _check(load().magus_server_run(self._h, ev.ctypes.data_as(_P), len(ev), int(n_streams),
+                                       arr, len(arr), int(bool(realtime)), int(max_batch),
+                                       int(depth), dec.ctypes.data_as(_P),
+                                       lat.ctypes.data_as(_P), ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in MagusRunStats._fields_}
+        return dec, lat, stats
 
     def result(self, slot: int) -> dict:
         r = MagusResult()

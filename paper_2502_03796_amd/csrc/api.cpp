@@ -4,23 +4,16 @@
 // owns per-context scratch memory and the serving slot pool, and enqueues the
 // kernels of replay.hip, sweep.hip and serve.hip on the caller's stream.
 
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <map>
-#include <string>
-#include <vector>
-
-#include "magus_internal.h"
+#include "host_internal.h"
 
 using namespace magus;
 
-namespace {
+namespace magus {
 
+namespace {
 thread_local std::string g_last_error;
+constexpr uint32_t kDefaultChunk = 8192;
+}  // namespace
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -32,16 +25,8 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(MAGUS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));        \
-    } while (0)
+const std::string& last_error() { return g_last_error; }
 
-constexpr uint32_t kDefaultChunk = 16384;
-
-// Derives the kernel form of a config; MAGUS_OK or MAGUS_EINVAL.
 int derive(const magus_config* c, DevCfg* d) {
     if (!c) return fail(MAGUS_EINVAL, "config is NULL");
     if (c->window < 2 || c->window > 32)
@@ -77,116 +62,108 @@ int derive(const magus_config* c, DevCfg* d) {
     return MAGUS_OK;
 }
 
-// Grow-only device buffer.
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-    int ensure(size_t bytes) {
-        if (bytes <= cap) return MAGUS_OK;
-        if (p) {
-            hipError_t e = hipFree(p);
-            p = nullptr;
-            cap = 0;
-            if (e != hipSuccess) return fail(MAGUS_EDEVICE, "hipFree: %s", hipGetErrorString(e));
-        }
-        size_t want = std::max(bytes, (size_t)256);
-        if (hipMalloc(&p, want) != hipSuccess) {
-            p = nullptr;
-            return fail(MAGUS_ENOMEM, "hipMalloc(%zu) failed", want);
-        }
-        cap = want;
-        return MAGUS_OK;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
+int DevBuf::ensure(size_t bytes) {
+    if (bytes <= cap) return MAGUS_OK;
+    if (p) {
+        hipError_t e = hipFree(p);
         p = nullptr;
         cap = 0;
+        if (e != hipSuccess) return fail(MAGUS_EDEVICE, "hipFree: %s", hipGetErrorString(e));
     }
-    template <class T> T* as() const { return static_cast<T*>(p); }
-};
-
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    size_t want = std::max(bytes, (size_t)256);
+    if (hipMalloc(&p, want) != hipSuccess) {
+        p = nullptr;
+        return fail(MAGUS_ENOMEM, "hipMalloc(%zu) failed", want);
     }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+    cap = want;
+    return MAGUS_OK;
+}
 
-}  // namespace
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
 
-struct magus_ctx {
-    int device = 0;
-    uint32_t chunk = kDefaultChunk;
-    DevBuf err;          // uint32 sticky error word
-    DevBuf chunk_base;   // replay: chunk prefix sum + status
-    DevBuf sums;         // replay: ChunkSum per chunk
-    DevBuf fix;          // replay: ChunkFix per chunk
-    DevBuf cfgs;         // replay: DevCfg table
-    std::vector<DevCfg> cfg_host;   // last uploaded table
-    DevBuf keys;         // sweep: arg-min keys + status
-    DevBuf sweep_tab;    // sweep: lane tables
-    std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
-    SweepPlan plan{};
-    // kernel timing: event pairs recorded around the dominant kernel of a call
-    bool prof = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> recorded[3];
+}  // namespace magus
 
-    // Returns a pair of events to record for `kernel`, or nulls when off.
-    std::pair<hipEvent_t, hipEvent_t> timing_pair(int kernel) {
-        if (!prof) return {nullptr, nullptr};
-        hipEvent_t e[2] = {nullptr, nullptr};
-        for (auto& ev : e) {
-            if (!ev_pool.empty()) {
-                ev = ev_pool.back();
-                ev_pool.pop_back();
-            } else if (hipEventCreate(&ev) != hipSuccess) {
-                ev = nullptr;
-            }
+std::pair<hipEvent_t, hipEvent_t> magus_ctx::timing_pair(int kernel) {
+    if (!prof) return {nullptr, nullptr};
+    hipEvent_t e[2] = {nullptr, nullptr};
+    for (auto& ev : e) {
+        if (!ev_pool.empty()) {
+            ev = ev_pool.back();
+            ev_pool.pop_back();
+        } else if (hipEventCreate(&ev) != hipSuccess) {
+            ev = nullptr;
         }
-        if (!e[0] || !e[1]) {
-            for (auto ev : e)
-                if (ev) ev_pool.push_back(ev);
-            return {nullptr, nullptr};
-        }
-        recorded[kernel].push_back({e[0], e[1]});
-        return {e[0], e[1]};
     }
-};
+    if (!e[0] || !e[1]) {
+        for (auto ev : e)
+            if (ev) ev_pool.push_back(ev);
+        return {nullptr, nullptr};
+    }
+    recorded[kernel].push_back({e[0], e[1]});
+    return {e[0], e[1]};
+}
 
-struct magus_server {
-    magus_ctx* ctx = nullptr;
-    uint32_t cap = 0;
-    DevBuf st, acc, slot_cfg;
-    std::vector<uint8_t> open;
-    std::vector<DevCfg> host_cfg;
-    std::vector<uint32_t> free_slots;
-    std::map<uint32_t, DevCfg> pending;     // slots to (re)initialise at the next step
-    std::vector<uint32_t> mark;              // duplicate detection per step
-    uint32_t epoch = 0;
-    struct Stage {
-        uint32_t* h_pairs = nullptr;
-        ServeInit* h_inits = nullptr;
-        uint32_t cap_pairs = 0, cap_inits = 0;
-        DevBuf d_pairs, d_inits, d_dec;
-        hipEvent_t done = nullptr;
-        bool used = false;
-    };
-    static constexpr int kStages = 3;
-    Stage stages[kStages];
-    uint32_t next_stage = 0;
-};
+int magus_server::Stage::ensure(uint32_t n_pairs, uint32_t n_inits, bool with_h_dec) {
+    using magus::fail;
+    if (cap_pairs < n_pairs) {
+        if (h_pairs) (void)hipHostFree(h_pairs);
+        if (h_dec) (void)hipHostFree(h_dec);
+        h_pairs = nullptr;
+        h_dec = nullptr;
+        cap_pairs = 0;
+        const uint32_t c = std::max<uint32_t>(n_pairs, 1024);
+        if (hipHostMalloc((void**)&h_pairs, (size_t)c * 8, hipHostMallocDefault) != hipSuccess)
+            return fail(MAGUS_ENOMEM, "hipHostMalloc(%zu) failed", (size_t)c * 8);
+        if (with_h_dec &&
+            hipHostMalloc((void**)&h_dec, (size_t)c, hipHostMallocDefault) != hipSuccess)
+            return fail(MAGUS_ENOMEM, "hipHostMalloc(%zu) failed", (size_t)c);
+        int rc;
+        if ((rc = d_pairs.ensure((size_t)c * 8)) || (rc = d_dec.ensure(c))) return rc;
+        cap_pairs = c;
+    }
+    if (cap_inits < n_inits) {
+        if (h_inits) (void)hipHostFree(h_inits);
+        h_inits = nullptr;
+        cap_inits = 0;
+        const uint32_t c = std::max<uint32_t>(n_inits, 256);
+        if (hipHostMalloc((void**)&h_inits, (size_t)c * sizeof(magus::ServeInit),
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(MAGUS_ENOMEM, "hipHostMalloc failed");
+        int rc;
+        if ((rc = d_inits.ensure((size_t)c * sizeof(magus::ServeInit)))) return rc;
+        cap_inits = c;
+    }
+    return MAGUS_OK;
+}
+
+void magus_server::Stage::release() {
+    if (h_pairs) (void)hipHostFree(h_pairs);
+    if (h_inits) (void)hipHostFree(h_inits);
+    if (h_dec) (void)hipHostFree(h_dec);
+    h_pairs = nullptr;
+    h_inits = nullptr;
+    h_dec = nullptr;
+    d_pairs.release();
+    d_inits.release();
+    d_dec.release();
+    for (hipEvent_t* e : {&done, &h2d, &kern})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    cap_pairs = cap_inits = 0;
+    used = false;
+}
 
 extern "C" {
 
 const char* magus_version(void) { return "magus-mi355x 0.1 (gfx950)"; }
 
-const char* magus_last_error(void) { return g_last_error.c_str(); }
+const char* magus_last_error(void) { return last_error().c_str(); }
 
 int magus_config_check(const magus_config* h_cfg) {
     DevCfg d;
@@ -307,7 +284,7 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     for (uint32_t i = 0; i < n_cfgs; ++i) {
         int rc = derive(&h_cfgs[i], &tab[i]);
         if (rc != MAGUS_OK)
-            return fail(rc, "config %u: %s", i, std::string(g_last_error).c_str());
+            return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
     }
     if (n_traces == 0) return MAGUS_OK;
     const uint64_t max_chunks64 = n_samples / ctx->chunk + n_traces + 1;
@@ -352,7 +329,7 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     for (uint32_t i = 0; i < n_cfgs; ++i) {
         int rc = derive(&h_cfgs[i], &tab[i]);
         if (rc != MAGUS_OK)
-            return fail(rc, "config %u: %s", i, std::string(g_last_error).c_str());
+            return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
     }
     if (n_traces == 0) return MAGUS_OK;
 
@@ -482,14 +459,13 @@ int magus_server_destroy(magus_server* s) {
     {
         DeviceGuard g(s->ctx->device);
         (void)hipDeviceSynchronize();
-        for (auto& st : s->stages) {
-            if (st.h_pairs) (void)hipHostFree(st.h_pairs);
-            if (st.h_inits) (void)hipHostFree(st.h_inits);
-            st.d_pairs.release();
-            st.d_inits.release();
-            st.d_dec.release();
-            if (st.done) (void)hipEventDestroy(st.done);
-        }
+        for (auto& st : s->stages) st.release();
+        for (auto& st : s->loop_stages) st.release();
+        for (hipStream_t* q : {&s->s_h2d, &s->s_comp, &s->s_d2h})
+            if (*q) {
+                (void)hipStreamDestroy(*q);
+                *q = nullptr;
+            }
         s->st.release();
         s->acc.release();
         s->slot_cfg.release();
@@ -554,29 +530,7 @@ int magus_serve_step(magus_server* s, const uint32_t* h_slots, const uint32_t* h
     magus_server::Stage& st = s->stages[s->next_stage];
     s->next_stage = (s->next_stage + 1) % magus_server::kStages;
     if (st.used) HIP_TRY(hipEventSynchronize(st.done));   // staging buffers free again
-    if (st.cap_pairs < n) {
-        if (st.h_pairs) (void)hipHostFree(st.h_pairs);
-        st.h_pairs = nullptr;
-        st.cap_pairs = 0;
-        const uint32_t c = std::max<uint32_t>(n, 1024);
-        if (hipHostMalloc((void**)&st.h_pairs, (size_t)c * 8, hipHostMallocDefault) != hipSuccess)
-            return fail(MAGUS_ENOMEM, "hipHostMalloc(%zu) failed", (size_t)c * 8);
-        int rc;
-        if ((rc = st.d_pairs.ensure((size_t)c * 8)) || (rc = st.d_dec.ensure(c))) return rc;
-        st.cap_pairs = c;
-    }
-    if (st.cap_inits < n_inits) {
-        if (st.h_inits) (void)hipHostFree(st.h_inits);
-        st.h_inits = nullptr;
-        st.cap_inits = 0;
-        const uint32_t c = std::max<uint32_t>(n_inits, 256);
-        if (hipHostMalloc((void**)&st.h_inits, (size_t)c * sizeof(ServeInit),
-                          hipHostMallocDefault) != hipSuccess)
-            return fail(MAGUS_ENOMEM, "hipHostMalloc failed");
-        int rc;
-        if ((rc = st.d_inits.ensure((size_t)c * sizeof(ServeInit)))) return rc;
-        st.cap_inits = c;
-    }
+    if (int rc = st.ensure(n, n_inits, false)) return rc;
     uint32_t k = 0;
     for (const auto& kv : s->pending) {
         st.h_inits[k].slot = kv.first;

@@ -1,0 +1,108 @@
+// Host-side internals of libmagus shared by the C ABI (api.cpp) and the
+// serving loop (server_loop.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "magus_internal.h"
+
+namespace magus {
+
+// Records `fmt` as this thread's last error message and returns `code`.
+int fail(int code, const char* fmt, ...);
+const std::string& last_error();
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::magus::fail(MAGUS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Derives the kernel form of a config; MAGUS_OK or MAGUS_EINVAL.
+int derive(const magus_config* c, DevCfg* d);
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace magus
+
+struct magus_ctx {
+    int device = 0;
+    uint32_t chunk = 8192;
+    magus::DevBuf err;          // uint32 sticky error word
+    magus::DevBuf chunk_base;   // replay: chunk prefix sum + status
+    magus::DevBuf sums;         // replay: ChunkSum per chunk
+    magus::DevBuf fix;          // replay: ChunkFix per chunk
+    magus::DevBuf cfgs;         // replay: DevCfg table
+    std::vector<magus::DevCfg> cfg_host;        // last uploaded table
+    magus::DevBuf keys;         // sweep: arg-min keys + status
+    magus::DevBuf sweep_tab;    // sweep: lane tables
+    std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
+    magus::SweepPlan plan{};
+    // kernel timing: event pairs recorded around the dominant kernel of a call
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> recorded[3];
+
+    // Returns a pair of events to record for `kernel`, or nulls when off.
+    std::pair<hipEvent_t, hipEvent_t> timing_pair(int kernel);
+};
+
+struct magus_server {
+    magus_ctx* ctx = nullptr;
+    uint32_t cap = 0;
+    magus::DevBuf st, acc, slot_cfg;
+    std::vector<uint8_t> open;
+    std::vector<magus::DevCfg> host_cfg;
+    std::vector<uint32_t> free_slots;
+    std::map<uint32_t, magus::DevCfg> pending;  // slots to (re)initialise at the next step
+    std::vector<uint32_t> mark;                  // duplicate detection per step
+    uint32_t epoch = 0;
+    struct Stage {
+        uint32_t* h_pairs = nullptr;
+        magus::ServeInit* h_inits = nullptr;
+        uint8_t* h_dec = nullptr;                // serving loop only
+        uint32_t cap_pairs = 0, cap_inits = 0;
+        magus::DevBuf d_pairs, d_inits, d_dec;
+        hipEvent_t done = nullptr;
+        hipEvent_t h2d = nullptr, kern = nullptr; // serving loop only
+        bool used = false;
+        int ensure(uint32_t n_pairs, uint32_t n_inits, bool with_h_dec);
+        void release();
+    };
+    static constexpr int kStages = 3;
+    Stage stages[kStages];
+    uint32_t next_stage = 0;
+    // serving loop
+    static constexpr int kLoopStages = 4;
+    Stage loop_stages[kLoopStages];
+    hipStream_t s_h2d = nullptr, s_comp = nullptr, s_d2h = nullptr;
+};

@@ -18,6 +18,8 @@
 //   fixup   (decision bytes only) level of the steps before the first
 //           decisive step of each chunk
 
+#include <type_traits>
+
 #include "magus_internal.h"
 
 namespace magus {
@@ -28,7 +30,6 @@ namespace {
 
 constexpr int kChunkWavesPerBlock = 4;
 constexpr int kPlanThreads = 1024;
-constexpr int kPrefetch = 8;          // blocks of 64 samples in flight per wave
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -119,7 +120,13 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
 
 // ------------------------------------------------------------------ chunks
 
-// One wave replays one chunk [s, e) of trace t.
+constexpr uint32_t kIter = 8;         // blocks of 64 steps per unrolled iteration
+
+// One wave replays one chunk [s, e) of trace t, 64 steps (one "block") at a
+// time, kIter blocks per iteration.  The samples of iteration i+1 are loaded
+// while iteration i is evaluated.  Blocks of a group of 64 consecutive blocks
+// leave their decisive-step masks in lane j = block index of VGPRs; at the end
+// of the group every lane resolves the level bits of its own block.
 template <bool kLevels>
 __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
@@ -148,29 +155,61 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
     const uint32_t W = c.W, H = c.H;
 
     // Samples [wbeg, e) of the trace through a bounds-checked buffer
-    // descriptor: the warm-up block [s-64, s) feeds the FIFOs of the first
-    // steps of the chunk; loads past e return 0.
+    // descriptor (loads outside return 0).  When the chunk does not start the
+    // trace, block 0 of the descriptor is the warm-up block [s-64, s) that
+    // fills the two FIFOs for the first steps of the chunk.
     const uint32_t wbeg = s >= 64 ? s - 64 : 0;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(samples + tbase + wbeg), (short)0, (int)((e - wbeg) * 4u), 0x00020000);
-    const uint32_t nblk = (e - wbeg + 63) >> 6;          // blocks incl. warm-up
     const uint32_t first_real = s >= 64 ? 1u : 0u;
+    const uint32_t nreal = (e - s + 63) >> 6;            // real blocks, last may be partial
+    const uint32_t nfull = (e - s) >> 6;                 // real blocks with 64 valid steps
+    const uint32_t n_iter = (nreal + kIter - 1) / kIter;
 
     // per-lane constants
-    const int bperm_addr = (int)(((lane - (W - 1)) & 63u) << 2);
+    const int bperm_addr = (int)(((lane - (W - 1)) & 63u) << 2);  // lane of x[t-W+1]
     const bool from_cur = lane >= W - 1;
     const uint32_t thr_lane = c.thr + lane;
+    // thresholds as per-lane registers: a select between a VGPR and an SGPR
+    // operand needs no copy inside the loop
+    uint32_t mu;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(mu) : "s"(c.mu));
+    const uint32_t md = c.md;
 
-    uint32_t xq[kPrefetch];
+    auto load_block = [&](uint32_t desc_blk) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((desc_blk * 64 + lane) * 4), 0, 0);
+    };
+    // Alg. 1 for the 64 steps of a block: event and rising masks.
+    auto events = [&](uint32_t a, uint32_t b, uint64_t& E, uint64_t& R) {
+        const bool rising = b > a;
+        const uint32_t lov = min(a, b);
+        const uint32_t d = max(a, b) - lov;
+        const uint32_t m = rising ? mu : md;
+        // r = d / (W lo) beyond q / 2^16  <=>  d 2^16 > lo (W q)
+        const bool ev = ((uint64_t)d << 16) > (uint64_t)lov * m;
+        E = ballot(ev);
+        R = ballot(rising);
+    };
+
+    uint32_t xp = 0;             // samples of the block before the current one
+    uint64_t fps = 0;            // (flags of the block before) >> 1
+    if (first_real) {
+        const uint32_t x0 = load_block(0);
+        const uint32_t ac = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)x0);
+        uint64_t E, R;
+        events(from_cur ? ac : 0u, x0, E, R);
+        const uint32_t tb = s - 64;
+        if (tb < W - 1) E &= ~low_mask(W - 1 - tb);       // FIFO not yet full
+        fps = E >> 1;
+        xp = x0;
+    }
+
+    uint32_t bufA[kIter], bufB[kIter];
 #pragma unroll
-    for (int i = 0; i < kPrefetch; ++i)
-        xq[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((i * 64 + lane) * 4), 0, 0);
+    for (uint32_t j = 0; j < kIter; ++j) bufA[j] = load_block(first_real + j);
 
-    uint32_t xprev = 0;
-    uint64_t fps = 0;            // (previous block's flags) >> 1
     uint32_t th = 0;             // steps in the high state
-    // group of up to 64 blocks, block j's masks held by lane j
-    uint32_t upL = 0, upH = 0, dnL = 0, dnH = 0;
+    uint32_t upL = 0, upH = 0, dnL = 0, dnH = 0;          // group masks, lane j = block j
     uint32_t puL = 0, puH = 0, pdL = 0, pdH = 0, hmL = 0, hmH = 0;
     uint32_t gi = 0;             // blocks in the current group
     uint32_t g0 = s;             // first step of the current group
@@ -186,7 +225,7 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
         const uint64_t d = up | dn;
         const uint64_t HAS = ballot(d != 0);
         const uint64_t LUP = ballot(up > dn);        // the last decisive step sets max
-        // level bit entering every block: carries of ~DNB + LUP + gcarry
+        // level bit entering every block: the carries of ~DNB + LUP + gcarry
         const uint64_t ndnb = ~(HAS & ~LUP);
         const uint64_t s1 = ndnb + LUP;
         const uint32_t k1 = s1 < ndnb;
@@ -194,7 +233,7 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
         const uint32_t k2 = s2 < s1;
         const uint64_t cin_mask = ~(s2 ^ HAS);
         const uint32_t cin = (uint32_t)(cin_mask >> lane) & 1u;
-        // level bits inside block `lane`
+        // level bits inside block `lane`: the carries of ~dn + up + cin
         const uint64_t nd = ~dn;
         const uint64_t t1 = nd + up;
         const uint64_t c1 = t1 < nd;
@@ -203,7 +242,7 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
         const uint64_t C = ~(t2 ^ d);                 // level bit before each step
         const uint64_t L = (C >> 1) | ((c1 | c2) << 63);   // level bit after each step
         const uint32_t bstart = g0 + lane * 64;
-        const uint32_t nvalid = act ? min(64u, e - bstart) : 0u;
+        const uint32_t nvalid = (act && bstart < e) ? min(64u, e - bstart) : 0u;
         const uint64_t vm = low_mask(nvalid);
         cnt_max += __popcll(L & vm);
         trans0 += __popcll((L ^ C) & vm);
@@ -237,64 +276,78 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
         gi = 0;
     };
 
-    for (uint32_t b0 = 0; b0 < nblk; b0 += kPrefetch) {
+    // One iteration: blocks it*kIter .. it*kIter+kIter-1 (real-block index).
+    auto iteration = [&](uint32_t it, uint32_t (&cur)[kIter], uint32_t (&nxt)[kIter],
+                         auto generic_tag) {
+        constexpr bool generic = decltype(generic_tag)::value;
+        if (it + 1 < n_iter) {
 #pragma unroll
-        for (int i = 0; i < kPrefetch; ++i) {
-            const uint32_t blk = b0 + i;
-            if (blk >= nblk) break;
-            const uint32_t x = xq[i];
-            xq[i] = __builtin_amdgcn_raw_buffer_load_b32(
-                rsrc, (int)(((blk + kPrefetch) * 64 + lane) * 4), 0, 0);
-            const uint32_t tb = wbeg + blk * 64;        // trace step of lane 0
-
-            // Alg. 1 on this step: a = x[t-W+1] (oldest), b = x[t] (newest)
-            const uint32_t a_cur = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)x);
-            const uint32_t a_prv = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)xprev);
-            const uint32_t a = from_cur ? a_cur : a_prv;
-            const uint32_t b = x;
-            const bool rising = b > a;
-            const uint32_t hiv = max(a, b), lov = min(a, b);
-            const uint32_t m = rising ? c.mu : c.md;
-            // r = (hi-lo)/(W lo) beyond the threshold q/2^16  <=>  (hi-lo) 2^16 > lo (W q)
-            bool ev = ((uint64_t)(hiv - lov) << 16) > (uint64_t)lov * m;
-            if (tb < W - 1) ev = ev && (lane >= W - 1 - tb);   // FIFO not yet full
-            uint64_t E = ballot(ev);
-            const uint64_t R = ballot(rising);
-            const uint32_t nvalid = min(64u, e - tb);
-            const uint64_t vm = low_mask(nvalid);
-            E &= vm;
-            xprev = x;
-
-            if (blk < first_real) {                       // warm-up block
-                fps = E >> 1;
-                continue;
+            for (uint32_t j = 0; j < kIter; ++j)
+                nxt[j] = load_block(first_real + (it + 1) * kIter + j);
+        }
+        // x[t-W+1] of every step, from this block or the one before
+        uint32_t ac[kIter], ap[kIter];
+#pragma unroll
+        for (uint32_t j = 0; j < kIter; ++j) {
+            ac[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)cur[j]);
+            ap[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)(j ? cur[j - 1] : xp));
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kIter; ++j) {
+            uint64_t E, R;
+            events(from_cur ? ac[j] : ap[j], cur[j], E, R);
+            uint64_t vm = ~0ull;
+            if constexpr (generic) {
+                const uint32_t tb = s + (it * kIter + j) * 64;     // trace step of lane 0
+                vm = low_mask(tb < e ? min(64u, e - tb) : 0u);
+                if (tb < W - 1) vm &= ~low_mask(W - 1 - tb);
+                E &= vm;
             }
             // Alg. 2: events among the last H steps, for all 64 steps at once
-            const uint64_t B = fps >> (64 - H);           // last H-1 flags of the previous block
-            const uint64_t nG = ~((E << (H - 1)) | B);    // ~(flags H-1 steps back)
+            const uint64_t B = fps >> (64 - H);           // last H-1 flags of the block before
+            const uint64_t nG = ~((E << (H - 1)) | B);    // ~(flag H-1 steps back)
             const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(E & 1ull);
             const uint32_t cnt = mbcnt(nG, mbcnt(E >> 1, acc0));
-            const uint64_t HM = ballot(cnt >= thr_lane) & vm;
+            uint64_t HM = ballot(cnt >= thr_lane);
+            if constexpr (generic) {
+                const uint32_t tb = s + (it * kIter + j) * 64;
+                HM &= low_mask(tb < e ? min(64u, e - tb) : 0u);
+            }
             fps = E >> 1;
-
             const uint64_t PU = E & R, PD = E & ~R;
             const uint64_t UP = HM | PU;                  // high or +1 -> max
             const uint64_t DN = PD & ~HM;                 // -1 executed -> min
             th += (uint32_t)__popcll(HM);
-            upL = (uint32_t)llvm_writelane((int)lo32(UP), (int)gi, (int)upL);
-            upH = (uint32_t)llvm_writelane((int)hi32(UP), (int)gi, (int)upH);
-            dnL = (uint32_t)llvm_writelane((int)lo32(DN), (int)gi, (int)dnL);
-            dnH = (uint32_t)llvm_writelane((int)hi32(DN), (int)gi, (int)dnH);
+            const int li = (int)(gi + j);
+            upL = (uint32_t)llvm_writelane((int)lo32(UP), li, (int)upL);
+            upH = (uint32_t)llvm_writelane((int)hi32(UP), li, (int)upH);
+            dnL = (uint32_t)llvm_writelane((int)lo32(DN), li, (int)dnL);
+            dnH = (uint32_t)llvm_writelane((int)hi32(DN), li, (int)dnH);
             if constexpr (kLevels) {
-                puL = (uint32_t)llvm_writelane((int)lo32(PU), (int)gi, (int)puL);
-                puH = (uint32_t)llvm_writelane((int)hi32(PU), (int)gi, (int)puH);
-                pdL = (uint32_t)llvm_writelane((int)lo32(PD), (int)gi, (int)pdL);
-                pdH = (uint32_t)llvm_writelane((int)hi32(PD), (int)gi, (int)pdH);
-                hmL = (uint32_t)llvm_writelane((int)lo32(HM), (int)gi, (int)hmL);
-                hmH = (uint32_t)llvm_writelane((int)hi32(HM), (int)gi, (int)hmH);
+                puL = (uint32_t)llvm_writelane((int)lo32(PU), li, (int)puL);
+                puH = (uint32_t)llvm_writelane((int)hi32(PU), li, (int)puH);
+                pdL = (uint32_t)llvm_writelane((int)lo32(PD), li, (int)pdL);
+                pdH = (uint32_t)llvm_writelane((int)hi32(PD), li, (int)pdH);
+                hmL = (uint32_t)llvm_writelane((int)lo32(HM), li, (int)hmL);
+                hmH = (uint32_t)llvm_writelane((int)hi32(HM), li, (int)hmH);
             }
-            if (++gi == 64) flush_group();
         }
+        xp = cur[kIter - 1];
+        gi += kIter;
+        if (gi == 64) flush_group();
+    };
+
+    // The first iteration of a trace and the iterations reaching past the last
+    // full block need per-step masks; all others take the unmasked path.
+    auto run = [&](uint32_t it, uint32_t (&cur)[kIter], uint32_t (&nxt)[kIter]) {
+        if ((it == 0 && first_real == 0) || (it + 1) * kIter > nfull)
+            iteration(it, cur, nxt, std::true_type{});
+        else
+            iteration(it, cur, nxt, std::false_type{});
+    };
+    for (uint32_t it = 0; it < n_iter; it += 2) {
+        run(it, bufA, bufB);
+        if (it + 1 < n_iter) run(it + 1, bufB, bufA);
     }
     if (gi) flush_group();
 

@@ -194,3 +194,82 @@ def serve_schedule(n_streams: int, n_ticks: int, period_ms: float = 100.0,
     jit = (uniform01(purpose_key(key, 1), 0, n_streams * n_ticks) * 2.0 - 1.0) * jitter_ms
     t = np.arange(n_ticks, dtype=np.float64)[None, :] * period_ms + phase[:, None]
     return t + jit.reshape(n_streams, n_ticks)
+
+
+EVENT_DTYPE = np.dtype([("t_ns", "<u8"), ("kind", "<u4"), ("stream", "<u4"),
+                        ("value", "<u4"), ("reserved", "<u4")])
+EV_SAMPLE, EV_JOIN, EV_LEAVE = 0, 1, 2
+
+
+def serve_fleet_events(n_initial: int, n_ticks: int, period_ms: float = 100.0,
+                       jitter_ms: float = 10.0, join_rate: float = 50.0,
+                       leave_rate: float = 50.0, n_cfgs: int = 16384,
+                       seed: int = SEED_BASE + 5):
+    """A fleet of simulated nodes as a time-sorted event list.
+
+    n_initial nodes join at time 0; new nodes join as a Poisson process of
+    `join_rate` per second and uniformly chosen live nodes leave at
+    `leave_rate` per second.  Every live node emits one sample per period at
+    its own phase offset plus U[-jitter, +jitter].  Each node gets a config
+    index drawn uniformly from [0, n_cfgs).
+
+    Returns (events: EVENT_DTYPE array sorted by time, n_streams, cfg_of_stream).
+    """
+    dur_ms = n_ticks * period_ms
+    key = stream_key(seed, 1 << 42)
+    # Poisson joins and leaves
+    def poisson_times(pk, rate):
+        if rate <= 0:
+            return np.zeros(0)
+        n_max = int(rate * dur_ms / 1000.0 * 3 + 20)
+        gaps = -np.log1p(-uniform01(purpose_key(key, pk), 0, n_max)) / rate * 1000.0
+        t = np.cumsum(gaps)
+        return t[t < dur_ms]
+    join_t = poisson_times(0, join_rate)
+    leave_t = poisson_times(1, leave_rate)
+    n_streams = n_initial + len(join_t)
+    start = np.concatenate([np.zeros(n_initial), join_t])
+    end = np.full(n_streams, np.inf)
+    # each leave picks a uniformly random live node
+    pick = uniform01(purpose_key(key, 2), 0, max(1, len(leave_t)))
+    order = np.argsort(start, kind="stable")
+    for i, tl in enumerate(leave_t):
+        live = np.nonzero((start <= tl) & (end > tl))[0]
+        if len(live):
+            end[live[min(int(pick[i] * len(live)), len(live) - 1)]] = tl
+    cfg_of_stream = np.minimum(np.floor(uniform01(purpose_key(key, 3), 0, n_streams) * n_cfgs),
+                               n_cfgs - 1).astype(np.uint32)
+    phase = uniform01(purpose_key(key, 4), 0, n_streams) * period_ms
+    chunks = []
+    for sid in range(n_streams):
+        first = int(np.ceil((start[sid] - phase[sid] + jitter_ms) / period_ms))
+        first = max(first, 0)
+        ticks = np.arange(first, n_ticks)
+        jit = (uniform01(purpose_key(stream_key(seed, sid), 9), 0, n_ticks)[ticks] * 2.0
+               - 1.0) * jitter_ms
+        t = ticks * period_ms + phase[sid] + jit
+        keep = (t > start[sid]) & (t < end[sid]) & (t < dur_ms)
+        t = t[keep]
+        if len(t) == 0:
+            continue
+        vals = serve_stream_samples(sid, len(t), seed=seed)
+        ev = np.zeros(len(t), EVENT_DTYPE)
+        ev["t_ns"] = np.round(t * 1e6).astype(np.uint64)
+        ev["kind"] = EV_SAMPLE
+        ev["stream"] = sid
+        ev["value"] = vals
+        chunks.append(ev)
+    jn = np.zeros(n_streams, EVENT_DTYPE)
+    jn["t_ns"] = np.round(start * 1e6).astype(np.uint64)
+    jn["kind"] = EV_JOIN
+    jn["stream"] = np.arange(n_streams)
+    jn["value"] = cfg_of_stream
+    left = np.nonzero(np.isfinite(end))[0]
+    lv = np.zeros(len(left), EVENT_DTYPE)
+    lv["t_ns"] = np.round(end[left] * 1e6).astype(np.uint64)
+    lv["kind"] = EV_LEAVE
+    lv["stream"] = left
+    ev = np.concatenate([jn] + chunks + [lv])
+    rank = np.where(ev["kind"] == EV_JOIN, 0, np.where(ev["kind"] == EV_SAMPLE, 1, 2))
+    ev = ev[np.lexsort((rank, ev["t_ns"]))]
+    return ev, n_streams, cfg_of_stream

@@ -140,3 +140,66 @@ def test_full_fleet_tick(ctx, oracle_mod):
         _, want = oracle_bytes(oracle_mod, data[:, i], grid[int(cfg_idx[i])])
         assert (out[:, i] == want).all(), i
     srv.close()
+
+
+def check_fleet(oracle_mod, ev, n_streams, cfg_of_stream, grid, dec):
+    """Every stream's served samples, replayed alone by the oracle, give the
+    decisions the fleet run produced for it in the mix."""
+    is_s = ev["kind"] == synth.EV_SAMPLE
+    served = is_s & (dec != 0xFF)
+    checked = 0
+    for sid in np.unique(ev["stream"][served]):
+        m = served & (ev["stream"] == sid)
+        x = ev["value"][m]
+        _, want = oracle_bytes(oracle_mod, x, grid[int(cfg_of_stream[sid])])
+        assert (dec[m] == want).all(), sid
+        checked += 1
+    return checked
+
+
+def test_fleet_flat_out_with_churn_matches_oracle(ctx, oracle_mod):
+    """Continuous batching under churn: 300 nodes, joins and leaves at 200/s,
+    a memory budget of 310 slots (joins wait for leaves), small batches so a
+    node's samples spread over many in-flight batches."""
+    grid = synth.sweep_grid()
+    ev, n_streams, cfg_of_stream = synth.serve_fleet_events(
+        300, 80, join_rate=200.0, leave_rate=200.0)
+    srv = magus.Server(ctx, 310 * magus.Server.slot_bytes())
+    dec, lat, st = srv.run(ev, n_streams, grid, realtime=False, max_batch=97, depth=3)
+    n_samples = int((ev["kind"] == synth.EV_SAMPLE).sum())
+    assert st["samples_served"] + st["samples_dropped"] == n_samples
+    assert st["joins_waited"] > 0 and st["max_in_flight"] >= 2 and st["deferred"] > 0
+    assert check_fleet(oracle_mod, ev, n_streams, cfg_of_stream, grid, dec) > 300
+    assert srv.open_count <= srv.capacity
+    srv.close()
+
+
+def test_fleet_stream_alone_equals_in_mix(ctx, oracle_mod):
+    grid = synth.sweep_grid()
+    ev, n_streams, cfg_of_stream = synth.serve_fleet_events(64, 60, join_rate=0.0,
+                                                            leave_rate=0.0)
+    srv = magus.Server(ctx, 64 * magus.Server.slot_bytes())
+    dec_mix, _, _ = srv.run(ev, n_streams, grid, realtime=False, max_batch=50, depth=2)
+    for sid in (0, 17, 63):
+        alone = ev[ev["stream"] == sid]
+        dec_alone, _, st = srv.run(alone, n_streams, grid, realtime=False, depth=1)
+        assert st["samples_served"] == int((alone["kind"] == synth.EV_SAMPLE).sum())
+        m = (ev["stream"] == sid) & (ev["kind"] == synth.EV_SAMPLE)
+        assert (dec_mix[m] == dec_alone[alone["kind"] == synth.EV_SAMPLE]).all()
+    srv.close()
+
+
+def test_fleet_realtime_latency(ctx, oracle_mod):
+    """One simulated second of 4,096 nodes in real time: every sample of an
+    admitted node is served, with finite arrival-to-decision latency."""
+    grid = synth.sweep_grid()
+    ev, n_streams, cfg_of_stream = synth.serve_fleet_events(4096, 10)
+    srv = magus.Server(ctx, (4096 + 64) * magus.Server.slot_bytes())
+    dec, lat, st = srv.run(ev, n_streams, grid, realtime=True, depth=2)
+    is_s = ev["kind"] == synth.EV_SAMPLE
+    served = is_s & (dec != 0xFF)
+    assert served.sum() == st["samples_served"] > 0.95 * is_s.sum()
+    l = lat[served].astype(np.float64) * 1e-6
+    assert np.isfinite(l).all() and np.percentile(l, 50) < 50.0
+    check_fleet(oracle_mod, ev, n_streams, cfg_of_stream, grid, dec)
+    srv.close()
