@@ -125,6 +125,46 @@ int magus_ctx_set_chunk(magus_ctx* ctx, uint32_t chunk_steps);
 uint32_t magus_ctx_get_chunk(const magus_ctx* ctx);
 
 /*
+ * Launch shape of the replay chunk kernel: 0 launches one wavefront per time
+ * chunk; N > 0 launches N workgroups of 4 wavefronts that take chunks from a
+ * device-side counter until none is left (a persistent grid).  Results never
+ * depend on it.
+ */
+int magus_ctx_set_persistent(magus_ctx* ctx, uint32_t workgroups);
+uint32_t magus_ctx_get_persistent(const magus_ctx* ctx);
+
+/*
+ * hipGraph replay.  While enabled, magus_replay captures its kernels into a
+ * graph the first time it sees a given set of arguments (pointers, sizes,
+ * config count, chunk and launch shape) and relaunches that graph on later
+ * calls with the same set; the config table is uploaded outside the graph.
+ * Up to 8 graphs are kept per context.
+ */
+int magus_ctx_set_graphs(magus_ctx* ctx, int enable);
+
+/*
+ * Autotuner for magus_replay: times every candidate time-chunk length
+ * (2,048..32,768 steps) and launch shape (one wave per chunk, or a persistent
+ * grid of 4 or 8 workgroups per compute unit) on the given batch, checks that
+ * every candidate produces exactly the same results as the first (else
+ * MAGUS_EDEVICE and the context is left unchanged), and sets the fastest on
+ * the context.  d_results receives the replay results.  Synchronizes `stream`.
+ */
+typedef struct magus_tune_result {
+    uint32_t chunk_steps;        /* chosen chunk length                     */
+    uint32_t persistent_blocks;  /* chosen launch shape (0 = one wave/chunk) */
+    uint32_t candidates;         /* candidates timed                        */
+    uint32_t reserved;
+    double best_ms;              /* time per call of the chosen candidate   */
+    double default_ms;           /* time per call of the default shape      */
+} magus_tune_result;
+int magus_autotune_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                          const uint64_t* d_offsets, uint32_t n_traces,
+                          const magus_config* h_cfgs, uint32_t n_cfgs,
+                          const uint32_t* d_cfg_of_trace, magus_result* d_results,
+                          uint32_t reps, hipStream_t stream, magus_tune_result* h_out);
+
+/*
  * Kernel timing.  While enabled, every call records a pair of HIP events on
  * its stream right before and after its dominant kernel (MAGUS_KERNEL_REPLAY:
  * the chunk kernel of magus_replay; MAGUS_KERNEL_SWEEP: the sweep kernel;

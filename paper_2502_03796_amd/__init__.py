@@ -53,6 +53,12 @@ class MagusRunStats(ctypes.Structure):
                 ("joins_refused", ctypes.c_uint64), ("wall_s", ctypes.c_double)]
 
 
+class MagusTuneResult(ctypes.Structure):
+    _fields_ = [("chunk_steps", ctypes.c_uint32), ("persistent_blocks", ctypes.c_uint32),
+                ("candidates", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+
 EV_SAMPLE, EV_JOIN, EV_LEAVE = 0, 1, 2
 EVENT_DTYPE = np.dtype([("t_ns", "<u8"), ("kind", "<u4"), ("stream", "<u4"),
                         ("value", "<u4"), ("reserved", "<u4")])
@@ -73,6 +79,12 @@ SIGNATURES = {
     "magus_ctx_set_chunk": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "magus_ctx_get_chunk": (ctypes.c_uint32, [_P]),
     "magus_ctx_check": (ctypes.c_int, [_P, _P]),
+    "magus_ctx_set_persistent": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "magus_ctx_get_persistent": (ctypes.c_uint32, [_P]),
+    "magus_ctx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "magus_autotune_replay": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
+                                             ctypes.c_uint32, _P, _P, ctypes.c_uint32, _P,
+                                             ctypes.POINTER(MagusTuneResult)]),
     "magus_ctx_set_profiling": (ctypes.c_int, [_P, ctypes.c_int]),
     "magus_ctx_kernel_time": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_uint64)]),
@@ -185,6 +197,36 @@ class Context:
 
     def set_chunk(self, steps: int) -> None:
         _check(load().magus_ctx_set_chunk(self._h, int(steps)))
+
+    @property
+    def persistent(self) -> int:
+        return int(load().magus_ctx_get_persistent(self._h))
+
+    def set_persistent(self, workgroups: int) -> None:
+        _check(load().magus_ctx_set_persistent(self._h, int(workgroups)))
+
+    def set_graphs(self, enable: bool) -> None:
+        _check(load().magus_ctx_set_graphs(self._h, int(bool(enable))))
+
+    def autotune_replay(self, samples, offsets, cfgs, cfg_of_trace=None, reps: int = 3,
+                        results=None, stream=None) -> dict:
+        """Time every chunk length / launch shape on this batch (results must agree),
+        keep the fastest on the context and return what was chosen."""
+        torch = _torch()
+        cfgs = [cfgs] if isinstance(cfgs, dict) else list(cfgs)
+        n_traces = offsets.numel() - 1
+        if results is None:
+            results = torch.empty((n_traces, 4), dtype=torch.int64, device=samples.device)
+        cp = None if cfg_of_trace is None else _dev_ptr(cfg_of_trace, "cfg_of_trace",
+                                                        (torch.int32, torch.uint32))
+        arr = config_array(cfgs)
+        r = MagusTuneResult()
+        _check(load().magus_autotune_replay(
+            self._h, _dev_ptr(samples, "samples", (torch.int32, torch.uint32)), samples.numel(),
+            _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64)), n_traces, arr, len(cfgs),
+            cp, _dev_ptr(results, "results", (torch.int64,)), int(reps),
+            _stream_handle(stream, self.device), ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in MagusTuneResult._fields_ if f != "reserved"}
 
     def set_profiling(self, enable: bool) -> None:
         _check(load().magus_ctx_set_profiling(self._h, int(bool(enable))))

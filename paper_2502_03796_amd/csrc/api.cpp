@@ -107,6 +107,12 @@ std::pair<hipEvent_t, hipEvent_t> magus_ctx::timing_pair(int kernel) {
     return {e[0], e[1]};
 }
 
+void magus_ctx::drop_graphs() {
+    for (auto& e : graphs)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    graphs.clear();
+}
+
 int magus_server::Stage::ensure(uint32_t n_pairs, uint32_t n_inits, bool with_h_dec) {
     using magus::fail;
     if (cap_pairs < n_pairs) {
@@ -206,6 +212,8 @@ int magus_ctx_destroy(magus_ctx* ctx) {
                 (void)hipEventDestroy(pr.second);
             }
         for (auto ev : ctx->ev_pool) (void)hipEventDestroy(ev);
+        ctx->drop_graphs();
+        if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     }
     delete ctx;
     return MAGUS_OK;
@@ -293,12 +301,15 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
 
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    const void* before[4] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p};
     int rc;
-    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
+    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4)) ||
         (rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum))) ||
         (rc = ctx->cfgs.ensure((size_t)n_cfgs * sizeof(DevCfg))))
         return rc;
     if (d_levels && (rc = ctx->fix.ensure((size_t)max_chunks * sizeof(ChunkFix)))) return rc;
+    const void* after[4] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p};
+    if (std::memcmp(before, after, sizeof before) != 0) ctx->drop_graphs();
     const bool same = ctx->cfg_host.size() == tab.size() &&
                       std::memcmp(ctx->cfg_host.data(), tab.data(), tab.size() * sizeof(DevCfg)) == 0;
     if (!same) {
@@ -307,12 +318,160 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                hipMemcpyHostToDevice, stream));
         ctx->cfg_host = tab;
     }
+    auto launch = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
+        return launch_replay(d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(),
+                             n_cfgs, d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(),
+                             ctx->sums.as<ChunkSum>(), max_chunks,
+                             d_levels ? ctx->fix.as<ChunkFix>() : nullptr, d_results, d_levels,
+                             ctx->err.as<uint32_t>(), ctx->persistent_blocks, q, e0, e1);
+    };
     const auto tp = ctx->timing_pair(MAGUS_KERNEL_REPLAY);
-    HIP_TRY(launch_replay(d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(),
-                          n_cfgs, d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(),
-                          ctx->sums.as<ChunkSum>(), max_chunks,
-                          d_levels ? ctx->fix.as<ChunkFix>() : nullptr, d_results, d_levels,
-                          ctx->err.as<uint32_t>(), stream, tp.first, tp.second));
+    if (!ctx->use_graphs) {
+        HIP_TRY(launch(stream, tp.first, tp.second));
+        return MAGUS_OK;
+    }
+    // hipGraph path: the kernels of a call with these exact arguments are
+    // captured once and relaunched (timing events then bracket the graph)
+    const std::vector<uint64_t> key = {
+        (uint64_t)d_samples, n_samples, (uint64_t)d_offsets, n_traces, n_cfgs,
+        (uint64_t)d_cfg_of_trace, (uint64_t)d_results, (uint64_t)d_levels, ctx->chunk,
+        ctx->persistent_blocks, (uint64_t)ctx->cfgs.p, (uint64_t)ctx->chunk_base.p,
+        (uint64_t)ctx->sums.p, (uint64_t)ctx->fix.p};
+    hipGraphExec_t exec = nullptr;
+    for (size_t i = 0; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].key == key) {
+            exec = ctx->graphs[i].exec;
+            std::rotate(ctx->graphs.begin() + i, ctx->graphs.begin() + i + 1, ctx->graphs.end());
+            break;
+        }
+    if (!exec) {
+        if (!ctx->cap_stream)
+            HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = launch(ctx->cap_stream, nullptr, nullptr);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(MAGUS_EDEVICE, "graph capture: %s",
+                        hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(MAGUS_EDEVICE, "hipGraphInstantiate: %s",
+                                          hipGetErrorString(ie));
+        if (ctx->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back({key, exec});
+    }
+    if (tp.first) HIP_TRY(hipEventRecord(tp.first, stream));
+    HIP_TRY(hipGraphLaunch(exec, stream));
+    if (tp.second) HIP_TRY(hipEventRecord(tp.second, stream));
+    return MAGUS_OK;
+}
+
+int magus_ctx_set_persistent(magus_ctx* ctx, uint32_t blocks) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (blocks > (1u << 20)) return fail(MAGUS_EINVAL, "too many persistent workgroups");
+    ctx->persistent_blocks = blocks;
+    return MAGUS_OK;
+}
+
+uint32_t magus_ctx_get_persistent(const magus_ctx* ctx) { return ctx ? ctx->persistent_blocks : 0; }
+
+int magus_ctx_set_graphs(magus_ctx* ctx, int enable) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    ctx->use_graphs = enable != 0;
+    if (!ctx->use_graphs) {
+        DeviceGuard g(ctx->device);
+        ctx->drop_graphs();
+    }
+    return MAGUS_OK;
+}
+
+int magus_autotune_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                          const uint64_t* d_offsets, uint32_t n_traces,
+                          const magus_config* h_cfgs, uint32_t n_cfgs,
+                          const uint32_t* d_cfg_of_trace, magus_result* d_results,
+                          uint32_t reps, hipStream_t stream, magus_tune_result* out) {
+    if (!ctx || !out) return fail(MAGUS_EINVAL, "ctx/out is NULL");
+    if (n_traces == 0) return fail(MAGUS_EINVAL, "nothing to tune on");
+    if (reps == 0) reps = 3;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    int n_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const uint32_t chunks[] = {2048, 4096, 8192, 16384, 32768};
+    const uint32_t pers[] = {0, (uint32_t)n_cu * 4, (uint32_t)n_cu * 8};
+    const uint32_t keep_chunk = ctx->chunk, keep_pers = ctx->persistent_blocks;
+    const bool keep_graphs = ctx->use_graphs;
+    ctx->use_graphs = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::vector<magus_result> ref(n_traces), got(n_traces);
+    magus_tune_result best{};
+    best.best_ms = 1e300;
+    int rc = MAGUS_OK;
+    uint32_t cand = 0;
+    for (uint32_t ch : chunks) {
+        for (uint32_t pb : pers) {
+            ctx->chunk = ch;
+            ctx->persistent_blocks = pb;
+            // warm-up call, then the results of every candidate must agree
+            rc = magus_replay(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
+                              d_cfg_of_trace, d_results, nullptr, stream);
+            if (rc) break;
+            if ((rc = magus_ctx_check(ctx, stream))) break;
+            if (hipMemcpy(cand ? got.data() : ref.data(), d_results,
+                          (size_t)n_traces * sizeof(magus_result),
+                          hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(MAGUS_EDEVICE, "result copy failed");
+                break;
+            }
+            if (cand && std::memcmp(got.data(), ref.data(),
+                                    (size_t)n_traces * sizeof(magus_result)) != 0) {
+                rc = fail(MAGUS_EDEVICE, "autotune: candidate chunk %u / persistent %u changed "
+                                         "the results", ch, pb);
+                break;
+            }
+            (void)hipEventRecord(e0, stream);
+            for (uint32_t r = 0; r < reps && rc == MAGUS_OK; ++r)
+                rc = magus_replay(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
+                                  d_cfg_of_trace, d_results, nullptr, stream);
+            if (rc) break;
+            (void)hipEventRecord(e1, stream);
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(MAGUS_EDEVICE, "autotune timing failed");
+                break;
+            }
+            const double per = ms / reps;
+            if (ch == kDefaultChunk && pb == 0) best.default_ms = per;
+            if (per < best.best_ms) {
+                best.best_ms = per;
+                best.chunk_steps = ch;
+                best.persistent_blocks = pb;
+            }
+            ++cand;
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->use_graphs = keep_graphs;
+    if (rc) {
+        ctx->chunk = keep_chunk;
+        ctx->persistent_blocks = keep_pers;
+        return rc;
+    }
+    best.candidates = cand;
+    ctx->chunk = best.chunk_steps;
+    ctx->persistent_blocks = best.persistent_blocks;
+    *out = best;
     return MAGUS_OK;
 }
 

@@ -67,6 +67,17 @@ struct magus_ctx {
     magus::DevBuf sweep_tab;    // sweep: lane tables
     std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
     magus::SweepPlan plan{};
+    // launch shape of the replay chunk kernel (0 = one wave per chunk)
+    uint32_t persistent_blocks = 0;
+    // hipGraph cache of replay calls
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;          // most recent last
+    void drop_graphs();
     // kernel timing: event pairs recorded around the dominant kernel of a call
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;

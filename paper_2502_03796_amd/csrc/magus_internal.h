@@ -62,7 +62,8 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
                          ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
                          magus_result* results, uint8_t* levels, uint32_t* err,
-                         hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+                         uint32_t persistent_blocks, hipStream_t stream, hipEvent_t ev0,
+                         hipEvent_t ev1);
 
 struct SweepPlan {
     uint32_t n_blocks;        // config blocks of kSweepLanes lanes, one window each

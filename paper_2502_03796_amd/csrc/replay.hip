@@ -114,13 +114,18 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
         if (total > max_chunks) e |= kErrOffsets;
         chunk_base[n_traces] = e ? 0u : total;
         chunk_base[n_traces + 1] = e;            // status of this call
+        chunk_base[n_traces + 2] = 0;            // work counter of the persistent grid
         if (e) atomicOr(err, e);
     }
 }
 
 // ------------------------------------------------------------------ chunks
 
-constexpr uint32_t kIter = 8;         // blocks of 64 steps per unrolled iteration
+#ifndef MAGUS_REPLAY_ITER
+#define MAGUS_REPLAY_ITER 8
+#endif
+constexpr uint32_t kIter = MAGUS_REPLAY_ITER;   // blocks of 64 steps per unrolled iteration
+static_assert(64 % kIter == 0, "an iteration must not straddle a group of 64 blocks");
 
 // One wave replays one chunk [s, e) of trace t, 64 steps (one "block") at a
 // time, kIter blocks per iteration.  The samples of iteration i+1 are loaded
@@ -128,18 +133,13 @@ constexpr uint32_t kIter = 8;         // blocks of 64 steps per unrolled iterati
 // leave their decisive-step masks in lane j = block index of VGPRs; at the end
 // of the group every lane resolves the level bits of its own block.
 template <bool kLevels>
-__global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
+__device__ __forceinline__ void replay_chunk(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
     uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
-    uint8_t* __restrict__ levels)
+    uint8_t* __restrict__ levels, const uint32_t g, const uint32_t lane)
 {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t g = blockIdx.x * kChunkWavesPerBlock + uniform(threadIdx.x >> 6);
-    const uint32_t total = chunk_base[n_traces];
-    if (g >= total) return;
-
     // trace of this chunk: the last t with chunk_base[t] <= g
     uint32_t lo = 0, hi = n_traces;
     while (hi - lo > 1) {
@@ -159,8 +159,13 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
     // trace, block 0 of the descriptor is the warm-up block [s-64, s) that
     // fills the two FIFOs for the first steps of the chunk.
     const uint32_t wbeg = s >= 64 ? s - 64 : 0;
+    // (the base and size are wave-uniform; readfirstlane lets the compiler
+    // keep the descriptor in SGPRs)
+    const uint64_t base = (uint64_t)(samples + tbase + wbeg);
+    const uint64_t base_u = ((uint64_t)uniform((uint32_t)(base >> 32)) << 32) |
+                            uniform((uint32_t)base);
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(samples + tbase + wbeg), (short)0, (int)((e - wbeg) * 4u), 0x00020000);
+        (void*)base_u, (short)0, (int)uniform((e - wbeg) * 4u), 0x00020000);
     const uint32_t first_real = s >= 64 ? 1u : 0u;
     const uint32_t nreal = (e - s + 63) >> 6;            // real blocks, last may be partial
     const uint32_t nfull = (e - s) >> 6;                 // real blocks with 64 valid steps
@@ -375,6 +380,44 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
     }
 }
 
+// One wave per chunk.
+template <bool kLevels>
+__global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
+    uint8_t* __restrict__ levels)
+{
+    const uint32_t g = blockIdx.x * kChunkWavesPerBlock + uniform(threadIdx.x >> 6);
+    if (g >= chunk_base[n_traces]) return;
+    replay_chunk<kLevels>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk,
+                          sums, fix, levels, g, threadIdx.x & 63);
+}
+
+// Persistent grid: every wave takes chunks from a device counter until none
+// is left (the counter is cleared by the plan kernel of the same call).
+template <bool kLevels>
+__global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel_persistent(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
+    uint8_t* __restrict__ levels)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t total = chunk_base[n_traces];
+    uint32_t* counter = chunk_base + n_traces + 2;
+    for (;;) {
+        uint32_t g = 0;
+        if (lane == 0) g = atomicAdd(counter, 1u);
+        g = uniform(__shfl(g, 0, 64));
+        if (g >= total) break;
+        replay_chunk<kLevels>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk,
+                              sums, fix, levels, g, lane);
+    }
+}
+
 // ------------------------------------------------------------------ fold
 
 __global__ __launch_bounds__(256) void fold_kernel(
@@ -433,14 +476,25 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
                          ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
                          magus_result* results, uint8_t* levels, uint32_t* err,
-                         hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
+                         uint32_t persistent_blocks, hipStream_t stream, hipEvent_t ev0,
+                         hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
     plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
                                                 n_cfgs, chunk, max_chunks, chunk_base, err);
-    const uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
+    uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
     if (ev0) (void)hipEventRecord(ev0, stream);
-    if (blocks) {
+    if (blocks && persistent_blocks) {
+        blocks = min(blocks, persistent_blocks);
+        if (levels)
+            chunk_kernel_persistent<true><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
+                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, fix,
+                levels);
+        else
+            chunk_kernel_persistent<false><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
+                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums,
+                nullptr, nullptr);
+    } else if (blocks) {
         if (levels)
             chunk_kernel<true><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
                 samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, fix,

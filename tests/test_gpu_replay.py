@@ -228,3 +228,75 @@ def test_bulk_workload_full_size_sampled(ctx, oracle_mod, bulk):
     _, want = oracle_mod.replay_batch(samples[:head], offsets[:9], [default_config()],
                                       want_bytes=True)
     assert (lv[:head].cpu().numpy() == want).all()
+
+
+def test_persistent_grid_and_graph_replays_match(ctx, oracle_mod):
+    """The persistent launch shape and hipGraph relaunches give the eager
+    results; every graph replay is checked, with eager work in between."""
+    import torch
+    traces = mixed_traces(404, LENGTHS * 3)
+    grid = synth.sweep_grid()
+    rng = np.random.default_rng(404)
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), 30)]
+    cot = rng.integers(0, len(cfgs), len(traces)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    want_res, want_b = oracle_mod.replay_batch(samples, offsets, cfgs, cot, want_bytes=True)
+    s, o, c = to_dev(samples, offsets, cot)
+    try:
+        for pers in (0, 7, 512):
+            ctx.set_persistent(pers)
+            res, lv = ctx.replay(s, o, cfgs, c, levels=True)
+            ctx.check()
+            assert (results_np(res) == want_res).all() and (lv.cpu().numpy() == want_b).all()
+        ctx.set_graphs(True)
+        res = torch.zeros((len(traces), 4), dtype=torch.int64, device="cuda")
+        lv = torch.zeros(len(samples), dtype=torch.uint8, device="cuda")
+        for rep in range(4):
+            res.zero_()
+            lv.zero_()
+            ctx.replay(s, o, cfgs, c, levels=True, results=res, levels_out=lv)
+            ctx.check()
+            assert (results_np(res) == want_res).all(), rep
+            assert (lv.cpu().numpy() == want_b).all(), rep
+            # eager work of the program between replays
+            ctx.set_graphs(False)
+            r2, _ = ctx.replay(s, o, [default_config()])
+            ctx.set_graphs(True)
+            torch.cuda.synchronize()
+    finally:
+        ctx.set_graphs(False)
+        ctx.set_persistent(0)
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    return synth.workload_uneven()
+
+
+def test_uneven_workload_full_size_sampled_with_autotune(ctx, oracle_mod, uneven):
+    """20,000 bursty traces of log-normal length with a grid config each (the
+    benchmark's uneven launch): autotuned shape, graph relaunch, sampled traces
+    against the oracle."""
+    samples, offsets, cot = uneven
+    grid = synth.sweep_grid()
+    s, o, c = to_dev(samples, offsets, cot)
+    chosen = ctx.autotune_replay(s, o, grid, c, reps=2)
+    assert chosen["candidates"] == 15 and chosen["best_ms"] <= chosen["default_ms"]
+    try:
+        ctx.set_graphs(True)
+        for _ in range(2):
+            res, _ = ctx.replay(s, o, grid, c)
+            ctx.check()
+        got = results_np(res)
+        lens = np.diff(offsets.astype(np.int64))
+        pick = sorted(set(np.random.default_rng(8).integers(0, len(lens), 24).tolist())
+                      | {int(np.argmax(lens)), int(np.argmin(lens))})
+        for t in pick:
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            r, _ = oracle_mod.replay_trace(x, grid[int(cot[t])], want_bytes=False)
+            assert list(got[t]) == [r["score"], r["level_sum"], r["transitions"],
+                                    r["ticks_high"]], t
+    finally:
+        ctx.set_graphs(False)
+        ctx.set_chunk(0)
+        ctx.set_persistent(0)
