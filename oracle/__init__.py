@@ -10,7 +10,8 @@ silent.
 
 Configs are passed as plain dicts with the keys
 ``window, hold, inc_q16, dec_q16, hf_num, hf_den, level_min, level_max,
-level_init`` (integers; thresholds in Q16.16).
+level_init`` and optionally ``up_step, down_step`` (integers; thresholds in
+Q16.16; steps 0 = jump to the bound).
 """
 from __future__ import annotations
 
@@ -43,7 +44,8 @@ class _Cfg(ctypes.Structure):
                 ("inc_q", ctypes.c_int32), ("dec_q", ctypes.c_int32),
                 ("hf_num", ctypes.c_uint32), ("hf_den", ctypes.c_uint32),
                 ("level_min", ctypes.c_uint32), ("level_max", ctypes.c_uint32),
-                ("level_init", ctypes.c_uint32)]
+                ("level_init", ctypes.c_uint32), ("up_step", ctypes.c_uint32),
+                ("down_step", ctypes.c_uint32)]
 
 
 class _Res(ctypes.Structure):
@@ -72,7 +74,8 @@ def _load():
 def _cfg(d: dict) -> _Cfg:
     return _Cfg(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
                 int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
-                int(d["level_max"]), int(d["level_init"]))
+                int(d["level_max"]), int(d["level_init"]), int(d.get("up_step", 0)),
+                int(d.get("down_step", 0)))
 
 
 def _cfg_array(cfgs):

@@ -39,6 +39,11 @@
  *   - high_freq_threshold is the fraction hf_num / hf_den and the test
  *     sum/len >= num/den is evaluated as sum * den >= num * len.
  *   - The flag logged is (temporary decision != 0), also while high.
+ *   - Stepped actuation (the gradual alternative that Sec. 6.1 contrasts with
+ *     MAGUS's jump to the bound, and the "how much to increase or decrease"
+ *     question of Sec. 2): with up_step / down_step > 0 an executed +1 / -1
+ *     moves the level by that many rungs, clamped to [level_min, level_max];
+ *     0 keeps the jump to the bound.  The high state still goes to the max.
  *   - Per step the tick is accounted after the decision:
  *       transitions += (new level != old level); level_sum += new level;
  *     score = level_sum + 1000 * transitions.
@@ -67,6 +72,7 @@ int oracle_config_valid(const oracle_config* c)
     if (c->hf_den < 1 || c->hf_num > c->hf_den) return 0;
     if (c->level_min >= c->level_max || c->level_max > 31) return 0;
     if (c->level_init < c->level_min || c->level_init > c->level_max) return 0;
+    if (c->up_step > 31 || c->down_step > 31) return 0;
     return 1;
 }
 
@@ -158,9 +164,15 @@ static void run_trace(const uint32_t* x, uint64_t n, const oracle_config* c,
 
         /* 5. decide */
         uint32_t next = level;
-        if (high) next = c->level_max;
-        else if (pred == 1) next = c->level_max;
-        else if (pred == -1) next = c->level_min;
+        if (high) {
+            next = c->level_max;
+        } else if (pred == 1) {
+            next = c->up_step == 0 ? c->level_max
+                 : (level + c->up_step > c->level_max ? c->level_max : level + c->up_step);
+        } else if (pred == -1) {
+            next = c->down_step == 0 ? c->level_min
+                 : (level < c->level_min + c->down_step ? c->level_min : level - c->down_step);
+        }
 
         transitions += (next != level);
         level = next;

@@ -19,6 +19,8 @@ typedef struct oracle_config {
     uint32_t level_min;     /* uncore ladder index of the lower bound      */
     uint32_t level_max;     /* ... of the upper bound (<= 31)              */
     uint32_t level_init;    /* level before the first step                 */
+    uint32_t up_step;       /* 0: an executed increase goes to level_max;  */
+    uint32_t down_step;     /*    else the level moves by this many rungs  */
 } oracle_config;
 
 typedef struct oracle_result {

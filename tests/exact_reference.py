@@ -56,12 +56,13 @@ def run(trace, cfg):
         uncore_tune_ls.pop(0)
         uncore_tune_ls.append(1 if pred != 0 else 0)
         high = high_freq_detection(hft, uncore_tune_ls)
+        up, down = cfg.get("up_step", 0), cfg.get("down_step", 0)
         if high:
             new = cfg["level_max"]
         elif pred == 1:
-            new = cfg["level_max"]
+            new = cfg["level_max"] if up == 0 else min(level + up, cfg["level_max"])
         elif pred == -1:
-            new = cfg["level_min"]
+            new = cfg["level_min"] if down == 0 else max(level - down, cfg["level_min"])
         else:
             new = level
         if new != level:

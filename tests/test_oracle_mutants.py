@@ -31,13 +31,19 @@ MUTANTS = [
      "if (lhs < -(int64_t)dec_q * den) return -1;"),
     ("Alg. 2 with > instead of >=", "return (uint64_t)sum * hf_den >= (uint64_t)hf_num * len;",
      "return (uint64_t)sum * hf_den > (uint64_t)hf_num * len;"),
-    ("high state does not override", "if (high) next = c->level_max;",
-     "if (0) next = c->level_max;"),
+    ("high state does not override", "        if (high) {\n            next = c->level_max;",
+     "        if (0) {\n            next = c->level_max;"),
     ("only increases are logged", "uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
      "uncore_tune_ls[H - 1] = (uint8_t)(pred == 1);"),
     ("decrease by one step instead of to the bound",
-     "else if (pred == -1) next = c->level_min;",
-     "else if (pred == -1) next = level > c->level_min ? level - 1 : level;"),
+     "next = c->down_step == 0 ? c->level_min",
+     "next = c->down_step == 0 ? (level > c->level_min ? level - 1 : level)"),
+    ("stepped increase not clamped to the maximum",
+     ": (level + c->up_step > c->level_max ? c->level_max : level + c->up_step);",
+     ": level + c->up_step;"),
+    ("stepped decrease ignores the step size",
+     ": (level < c->level_min + c->down_step ? c->level_min : level - c->down_step);",
+     ": (level < c->level_min + 1 ? c->level_min : level - 1);"),
     ("first transition from idle not counted", "transitions += (next != level);",
      "transitions += (t > 0 && next != level);"),
     ("transition weight wrong", "res->score = level_sum + 1000u * transitions;",
@@ -67,6 +73,9 @@ def _checks():
         lambda: pins.test_up_by_k_and_down_by_k_are_symmetric(om),
         lambda: [pins.test_decision_rule_invariants(om, i) for i in (0, 4096 + 77, 16383)],
         lambda: pins.test_large_values_against_transliteration(om),
+        lambda: [pins.test_stepped_staircase(om, u) for u in (1, 3, 5)],
+        lambda: [pins.test_stepped_descent(om, d) for d in (2, 4)],
+        lambda: pins.test_brute_force_stepped_actuation(om),
         lambda: pins.test_brute_force_against_exact_rational_transliteration(om),
     ]
 

@@ -372,3 +372,68 @@ def test_large_values_against_transliteration(oracle_mod):
             steps, score, *_ = ref.run([int(v) for v in x], cfg)
             r, b = oracle_mod.replay_trace(x.astype(np.uint32), cfg)
             assert b.tobytes() == ref.encode(steps) and r["score"] == score
+
+
+# ---------------------------------------------------------------- stepped actuation
+
+def _doubling(n, start=1000):
+    return [start * 2 ** k for k in range(n)]
+
+
+@pytest.mark.parametrize("u", [1, 3, 5])
+def test_stepped_staircase(oracle_mod, u):
+    """W = 2 on a trace that doubles every step: r = 1/2 > 0.1, so every step
+    after the first predicts +1.  With H = 32 and threshold 1/1 the high state
+    needs 32 events and never comes within 20 steps; each executed +1 raises
+    the level by u rungs, clamped at 16: level(t) = min(u t, 16)."""
+    cfg = default_config(window=2, hold=32, hf_num=1, hf_den=1, up_step=u)
+    n = 20
+    res, lv, hi, pr = run(oracle_mod, _doubling(n), cfg)
+    assert (hi == 0).all() and (pr[1:] == 1).all()
+    want = [min(u * t, 16) for t in range(n)]
+    assert list(lv) == want
+    assert res["level_sum"] == sum(want)
+    assert res["transitions"] == sum(1 for t in range(1, n) if want[t] != want[t - 1])
+
+
+@pytest.mark.parametrize("d", [2, 4])
+def test_stepped_descent(oracle_mod, d):
+    """Starting at the top (level_init = 16) on a trace that halves every step:
+    every step after the first predicts -1 and the level falls by d rungs,
+    clamped at 0: level(t) = max(16 - d t, 0)."""
+    cfg = default_config(window=2, hold=32, hf_num=1, hf_den=1, down_step=d, level_init=16)
+    n = 20
+    x = [2 ** (30 - k) for k in range(n)]
+    res, lv, hi, pr = run(oracle_mod, x, cfg)
+    assert (pr[1:] == -1).all()
+    assert list(lv) == [max(16 - d * t, 0) for t in range(n)]
+
+
+def test_stepped_high_state_still_locks_at_max(oracle_mod):
+    """Stepped actuation does not soften the Sec. 3.2 lock: 6 of 10 events go
+    straight to 16 whatever the step size."""
+    cfg = default_config(window=2, up_step=1, down_step=1)
+    res, lv, hi, pr = run(oracle_mod, [10000, 20000] * 20, cfg)
+    assert list(lv[:7]) == [0, 1, 0, 1, 0, 1, 16] and (lv[6:] == 16).all()
+
+
+def test_brute_force_stepped_actuation(oracle_mod):
+    """Stepped configs against the exact-rational transliteration."""
+    traces = [t for n in range(1, 7) for t in itertools.product((0, 1, 3, 4), repeat=n)]
+    rng = np.random.default_rng(21)
+    for _ in range(40):
+        lmin = int(rng.integers(0, 6))
+        lmax = int(rng.integers(lmin + 1, 20))
+        cfg = default_config(window=int(rng.integers(2, 4)), hold=int(rng.integers(1, 8)),
+                             inc_q16=int(rng.choice([0, 16384, 40000])),
+                             dec_q16=-int(rng.choice([0, 16384, 40000])),
+                             hf_num=int(rng.integers(1, 6)), hf_den=5,
+                             level_min=lmin, level_max=lmax,
+                             level_init=int(rng.integers(lmin, lmax + 1)),
+                             up_step=int(rng.integers(0, 5)), down_step=int(rng.integers(0, 5)))
+        for t in traces[::5]:
+            steps, score, ls, tr, th = ref.run(t, cfg)
+            r, b = oracle_mod.replay_trace(np.array(t, np.uint32), cfg)
+            assert b.tobytes() == ref.encode(steps), (cfg, t)
+            assert [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]] == \
+                [score, ls, tr, th]
