@@ -17,7 +17,8 @@
  *     (0.6 = 3/5 in Sec. 3.2).
  *   - Decision (Sec. 3.2, Sec. 4, Sec. 6.1): high or +1 -> level_max; else -1
  *     -> level_min (straight to the lower bound); else keep.  Streams start at
- *     level_init (idle nodes sit at the minimum, Sec. 4).
+ *     level_init (idle nodes sit at the minimum, Sec. 4).  Optionally an
+ *     executed +1 / -1 moves by up_step / down_step rungs instead.
  *   - Accounting per step, after the decision: transitions += (level changed);
  *     level_sum += level; score = level_sum + 1000 * transitions.
  *
@@ -68,8 +69,15 @@ extern "C" {
  *   level_min   lower bound on the uncore ladder (level i = 800 + 100 i MHz on
  *   level_max   the 17-level 0.8-2.4 GHz ladder); min < max <= 31.
  *   level_init  level before the first step, min <= init <= max (Sec. 4: min).
- *   up_step,    0 = jump to the bound (Sec. 6.1).  Other values are rejected.
- *   down_step
+ *   up_step,    0 = an executed +1 / -1 jumps to level_max / level_min (the
+ *   down_step   paper's policy, Sec. 6.1); 1..31 = it moves the level by that
+ *               many rungs, clamped to [level_min, level_max] (the gradual
+ *               policy Sec. 6.1 contrasts with; "how much to increase or
+ *               decrease", Sec. 2).  The high state always goes to level_max.
+ *   base        derivative base: 0 = min(oldest, newest) (the default reading:
+ *               symmetric for rises and falls), 1 = the oldest sample, 2 = the
+ *               newest sample (alternative readings of Alg. 1 kept for
+ *               sensitivity sweeps).
  */
 typedef struct magus_config {
     uint16_t window;
@@ -80,7 +88,7 @@ typedef struct magus_config {
     uint8_t level_min, level_max;
     uint8_t level_init;
     uint8_t up_step, down_step;
-    uint8_t reserved;           /* must be 0 */
+    uint8_t base;
 } magus_config;
 
 /* Per-trace replay result. */
@@ -218,6 +226,27 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 const uint64_t* d_offsets, uint32_t n_traces,
                 const magus_config* h_cfgs, uint32_t n_cfgs,
                 uint64_t* d_scores, uint32_t* d_argmin, hipStream_t stream);
+
+/*
+ * Monitor front end (Sec. 3, Sec. 4: memory throughput is read periodically
+ * through a counter API).  Turns cumulative traffic-counter readings into the
+ * MB/s samples that magus_replay / magus_sweep / serving consume:
+ *   d_counts, d_ts_ns  n_readings uint64 each: counter value and time (ns) of
+ *                      every reading; the counter has counter_bits bits
+ *                      (1..64) and wraps; each count is bytes_per_count bytes.
+ *   d_offsets          n_traces+1 uint64, strictly increasing (every trace has
+ *                      at least one reading), offsets[n_traces] <= n_readings.
+ *   d_samples          receives trace t's samples at [offsets[t] - t,
+ *                      offsets[t+1] - t - 1): one per pair of consecutive
+ *                      readings, floor(delta mod 2^bits * bytes_per_count *
+ *                      1000 / delta_ns) MB/s (bytes per microsecond), 0 for a
+ *                      zero interval, saturated at 2^32-1 (exact).
+ * Offsets that break the rules produce no output; magus_ctx_check reports them.
+ */
+int magus_counters_to_mbps(magus_ctx* ctx, const uint64_t* d_counts, const uint64_t* d_ts_ns,
+                           uint64_t n_readings, const uint64_t* d_offsets, uint32_t n_traces,
+                           uint32_t counter_bits, uint32_t bytes_per_count,
+                           uint32_t* d_samples, hipStream_t stream);
 
 /*
  * Serving: a pool of slots, one per live telemetry stream, whose controller

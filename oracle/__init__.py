@@ -10,8 +10,9 @@ silent.
 
 Configs are passed as plain dicts with the keys
 ``window, hold, inc_q16, dec_q16, hf_num, hf_den, level_min, level_max,
-level_init`` and optionally ``up_step, down_step`` (integers; thresholds in
-Q16.16; steps 0 = jump to the bound).
+level_init`` and optionally ``up_step, down_step`` (steps; 0 = jump to the
+bound) and ``base`` (derivative base: 0 min of the two samples, 1 oldest,
+2 newest) -- integers; thresholds in Q16.16.
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ class _Cfg(ctypes.Structure):
                 ("hf_num", ctypes.c_uint32), ("hf_den", ctypes.c_uint32),
                 ("level_min", ctypes.c_uint32), ("level_max", ctypes.c_uint32),
                 ("level_init", ctypes.c_uint32), ("up_step", ctypes.c_uint32),
-                ("down_step", ctypes.c_uint32)]
+                ("down_step", ctypes.c_uint32), ("base", ctypes.c_uint32)]
 
 
 class _Res(ctypes.Structure):
@@ -67,6 +68,8 @@ def _load():
                                                  ctypes.POINTER(_Res)]
         lib.oracle_replay_batch.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint32, P, P, P]
         lib.oracle_sweep.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint32, P, P]
+        lib.oracle_counters_to_mbps.argtypes = [P, P, ctypes.c_uint64, ctypes.c_uint32,
+                                                ctypes.c_uint32, P]
         _lib = lib
     return _lib
 
@@ -75,7 +78,7 @@ def _cfg(d: dict) -> _Cfg:
     return _Cfg(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
                 int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
                 int(d["level_max"]), int(d["level_init"]), int(d.get("up_step", 0)),
-                int(d.get("down_step", 0)))
+                int(d.get("down_step", 0)), int(d.get("base", 0)))
 
 
 def _cfg_array(cfgs):
@@ -158,6 +161,18 @@ def sweep(samples, offsets, cfgs, want_scores=True):
     if rc != 0:
         raise ValueError("oracle: invalid sweep")
     return scores, argmin
+
+
+def counters_to_mbps(counts, ts_ns, counter_bits=48, bytes_per_count=64):
+    """Monitor front end: cumulative counter readings to MB/s samples (n-1 of them)."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    ts_ns = np.ascontiguousarray(ts_ns, dtype=np.uint64)
+    out = np.zeros(max(len(counts) - 1, 0), dtype=np.uint32)
+    rc = _load().oracle_counters_to_mbps(_ptr(counts), _ptr(ts_ns), len(counts),
+                                         int(counter_bits), int(bytes_per_count), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle: invalid counter arguments")
+    return out
 
 
 def decode(byte_arr):

@@ -44,6 +44,9 @@
  *     question of Sec. 2): with up_step / down_step > 0 an executed +1 / -1
  *     moves the level by that many rungs, clamped to [level_min, level_max];
  *     0 keeps the jump to the bound.  The high state still goes to the max.
+ *   - The derivative's base is a reading as well; besides the default
+ *     min(oldest, newest) two alternatives are kept for sensitivity studies:
+ *     the oldest sample (r = (b - a) / (W a)) and the newest (W b).
  *   - Per step the tick is accounted after the decision:
  *       transitions += (new level != old level); level_sum += new level;
  *     score = level_sum + 1000 * transitions.
@@ -73,6 +76,7 @@ int oracle_config_valid(const oracle_config* c)
     if (c->level_min >= c->level_max || c->level_max > 31) return 0;
     if (c->level_init < c->level_min || c->level_init > c->level_max) return 0;
     if (c->up_step > 31 || c->down_step > 31) return 0;
+    if (c->base > 2) return 0;
     return 1;
 }
 
@@ -82,12 +86,19 @@ int oracle_config_valid(const oracle_config* c)
  * MEM_THROUGHPUT_TREND_PREDICTION (Alg. 1) with the relative derivative and
  * Q16.16 thresholds.  ls holds direv_length samples, ls[0] oldest.
  */
+static int64_t derivative_base(int64_t first, int64_t last, uint32_t which)
+{
+    if (which == 1) return first;
+    if (which == 2) return last;
+    return first < last ? first : last;
+}
+
 static int predict_exact(int32_t inc_q, int32_t dec_q,
-                         const uint32_t* ls, uint32_t direv_length)
+                         const uint32_t* ls, uint32_t direv_length, uint32_t which)
 {
     int64_t first = ls[0];
     int64_t last = ls[direv_length - 1];
-    int64_t base = first < last ? first : last;
+    int64_t base = derivative_base(first, last, which);
     int64_t delta = last - first;
     /* derivative = delta / (direv_length * base); compare with q / 65536
        by cross-multiplying with the positive (or zero) denominator.       */
@@ -101,11 +112,11 @@ static int predict_exact(int32_t inc_q, int32_t dec_q,
 /* ------------------------------------------------------ Alg. 1, FP64 form */
 
 static int predict_fp64(double inc_threshold, double dec_threshold,
-                        const uint32_t* ls, uint32_t direv_length)
+                        const uint32_t* ls, uint32_t direv_length, uint32_t which)
 {
     double first = (double)ls[0];
     double last = (double)ls[direv_length - 1];
-    double base = first < last ? first : last;
+    double base = which == 1 ? first : which == 2 ? last : (first < last ? first : last);
     double derivative = (last - first) / ((double)direv_length * base);
     if (derivative > inc_threshold) return 1;
     if (derivative < dec_threshold) return -1;
@@ -151,8 +162,9 @@ static void run_trace(const uint32_t* x, uint64_t n, const oracle_config* c,
         /* 2. predict (temporary decision) */
         int pred = 0;
         if (filled == W) {
-            pred = use_fp64 ? predict_fp64(inc_threshold, dec_threshold, mem_throughput_ls, W)
-                            : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W);
+            pred = use_fp64 ? predict_fp64(inc_threshold, dec_threshold, mem_throughput_ls, W,
+                                           c->base)
+                            : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W, c->base);
         }
 
         /* 3. log whether a frequency change would be triggered */
@@ -245,6 +257,26 @@ int oracle_sweep(const uint32_t* samples, const uint64_t* offsets, uint32_t n_tr
             if (r.score < best) { best = r.score; best_c = c; }
         }
         if (argmin) argmin[t] = best_c;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ monitor front end */
+
+int oracle_counters_to_mbps(const uint64_t* counts, const uint64_t* ts_ns, uint64_t n,
+                            uint32_t counter_bits, uint32_t bytes_per_count, uint32_t* out)
+{
+    if (counter_bits < 1 || counter_bits > 64 || (n > 1 && (!counts || !ts_ns || !out)))
+        return -1;
+    for (uint64_t i = 0; i + 1 < n; ++i) {
+        unsigned __int128 delta = (unsigned __int128)counts[i + 1] - counts[i];
+        if (counter_bits < 64) delta &= (((unsigned __int128)1) << counter_bits) - 1;
+        else delta &= (unsigned __int128)UINT64_MAX;
+        uint64_t dt = ts_ns[i + 1] - ts_ns[i];
+        if (dt == 0) { out[i] = 0; continue; }
+        /* bytes per microsecond = MB/s */
+        unsigned __int128 mbps = delta * bytes_per_count * 1000u / dt;
+        out[i] = mbps > UINT32_MAX ? UINT32_MAX : (uint32_t)mbps;
     }
     return 0;
 }

@@ -21,6 +21,8 @@ typedef struct oracle_config {
     uint32_t level_init;    /* level before the first step                 */
     uint32_t up_step;       /* 0: an executed increase goes to level_max;  */
     uint32_t down_step;     /*    else the level moves by this many rungs  */
+    uint32_t base;          /* derivative base: 0 min(oldest, newest),     */
+                            /* 1 oldest sample, 2 newest sample            */
 } oracle_config;
 
 typedef struct oracle_result {
@@ -44,4 +46,14 @@ int oracle_replay_batch(const uint32_t* samples, const uint64_t* offsets, uint32
 int oracle_sweep(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
                  const oracle_config* cfgs, uint32_t n_cfgs,
                  uint64_t* scores, uint32_t* argmin);
+/*
+ * Memory-throughput monitor front end: cumulative traffic counter readings
+ * (counts[i] at time ts_ns[i], a counter of counter_bits bits that wraps,
+ * bytes_per_count bytes per count) to throughput samples in MB/s:
+ *   out[i] = floor(((counts[i+1] - counts[i]) mod 2^bits) * bytes_per_count
+ *                  * 1000 / (ts_ns[i+1] - ts_ns[i])),
+ * 0 when the interval is 0, saturated at 2^32-1.  n readings give n-1 samples.
+ */
+int oracle_counters_to_mbps(const uint64_t* counts, const uint64_t* ts_ns, uint64_t n,
+                            uint32_t counter_bits, uint32_t bytes_per_count, uint32_t* out);
 #endif

@@ -8,7 +8,7 @@ built, every entry point raises.
 
 Configs are dicts with the keys ``window, hold, inc_q16, dec_q16, hf_num,
 hf_den, level_min, level_max, level_init`` and optionally ``up_step,
-down_step`` (see ``include/magus.h`` for meaning and ranges).
+down_step, base`` (see ``include/magus.h`` for meaning and ranges).
 """
 from __future__ import annotations
 
@@ -37,7 +37,7 @@ class MagusConfig(ctypes.Structure):
                 ("hf_num", ctypes.c_uint8), ("hf_den", ctypes.c_uint8),
                 ("level_min", ctypes.c_uint8), ("level_max", ctypes.c_uint8),
                 ("level_init", ctypes.c_uint8), ("up_step", ctypes.c_uint8),
-                ("down_step", ctypes.c_uint8), ("reserved", ctypes.c_uint8)]
+                ("down_step", ctypes.c_uint8), ("base", ctypes.c_uint8)]
 
 
 class MagusResult(ctypes.Structure):
@@ -92,6 +92,8 @@ SIGNATURES = {
                                     ctypes.c_uint32, _P, _P, _P, _P]),
     "magus_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
                                    ctypes.c_uint32, _P, _P, _P]),
+    "magus_counters_to_mbps": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint32,
+                                              ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "magus_server_slot_bytes": (ctypes.c_size_t, []),
     "magus_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(_P)]),
     "magus_server_destroy": (ctypes.c_int, [_P]),
@@ -133,7 +135,7 @@ def make_config(d: dict) -> MagusConfig:
     return MagusConfig(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
                        int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
                        int(d["level_max"]), int(d["level_init"]), int(d.get("up_step", 0)),
-                       int(d.get("down_step", 0)), 0)
+                       int(d.get("down_step", 0)), int(d.get("base", 0)))
 
 
 def config_array(cfgs) -> ctypes.Array:
@@ -269,6 +271,26 @@ class Context:
         _check(load().magus_replay(self._h, sp, samples.numel(), op, n_traces, arr, len(cfgs),
                                    cp, rp, lp, _stream_handle(stream, self.device)))
         return results, (levels_out if levels else None)
+
+    def counters_to_mbps(self, counts, ts_ns, offsets, counter_bits: int = 48,
+                         bytes_per_count: int = 64, stream=None):
+        """Monitor front end: counter readings (CSR, >= 1 per trace) to MB/s samples.
+
+        Returns (samples int32 tensor viewed as uint32, sample offsets int64 tensor).
+        """
+        torch = _torch()
+        n_traces = offsets.numel() - 1
+        out = torch.zeros(max(counts.numel() - n_traces, 0), dtype=torch.int32,
+                          device=counts.device)
+        _check(load().magus_counters_to_mbps(
+            self._h, _dev_ptr(counts, "counts", (torch.int64, torch.uint64)),
+            _dev_ptr(ts_ns, "ts_ns", (torch.int64, torch.uint64)), counts.numel(),
+            _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64)), n_traces,
+            int(counter_bits), int(bytes_per_count), _dev_ptr(out, "samples", (torch.int32,)),
+            _stream_handle(stream, self.device)))
+        sample_offsets = offsets - torch.arange(n_traces + 1, device=offsets.device,
+                                                dtype=offsets.dtype)
+        return out, sample_offsets
 
     def sweep(self, samples, offsets, cfgs, scores: bool = False, stream=None):
         """Every trace against every config; returns (scores int64[T, C] or None, argmin int32[T])."""

@@ -45,20 +45,23 @@ int derive(const magus_config* c, DevCfg* d) {
                     (unsigned)c->level_min, (unsigned)c->level_max);
     if (c->level_init < c->level_min || c->level_init > c->level_max)
         return fail(MAGUS_EINVAL, "level_init %u outside [min, max]", (unsigned)c->level_init);
-    if (c->up_step || c->down_step)
-        return fail(MAGUS_EINVAL, "only jump-to-bound actuation (steps 0) is supported");
-    if (c->reserved) return fail(MAGUS_EINVAL, "reserved byte must be 0");
+    if (c->up_step > 31 || c->down_step > 31)
+        return fail(MAGUS_EINVAL, "step sizes must be 0..31 (got %u, %u)",
+                    (unsigned)c->up_step, (unsigned)c->down_step);
+    if (c->base > 2) return fail(MAGUS_EINVAL, "base %u is not 0, 1 or 2", (unsigned)c->base);
     d->W = c->window;
     d->H = c->hold;
     d->mu = (uint32_t)c->window * (uint32_t)c->inc_q16;
     d->md = (uint32_t)c->window * (uint32_t)(-c->dec_q16);
     d->inc_q = c->inc_q16;
     d->dec_q = c->dec_q16;
-    d->thr = ((uint32_t)c->hf_num * c->hold + c->hf_den - 1) / c->hf_den;
+    d->thr = (uint16_t)(((uint32_t)c->hf_num * c->hold + c->hf_den - 1) / c->hf_den);
+    d->up = c->up_step;
+    d->down = c->down_step;
     d->lmin = c->level_min;
     d->lmax = c->level_max;
     d->linit = c->level_init;
-    d->pad = 0;
+    d->base = c->base;
     return MAGUS_OK;
 }
 
@@ -204,7 +207,8 @@ int magus_ctx_destroy(magus_ctx* ctx) {
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
         for (DevBuf* b : {&ctx->err, &ctx->chunk_base, &ctx->sums, &ctx->fix, &ctx->cfgs,
-                          &ctx->keys, &ctx->sweep_tab})
+                          &ctx->keys, &ctx->sweep_tab, &ctx->step_funcs, &ctx->step_enter,
+                          &ctx->step_sums, &ctx->status})
             b->release();
         for (auto& r : ctx->recorded)
             for (auto& pr : r) {
@@ -301,14 +305,28 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
 
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
-    const void* before[4] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p};
+    bool stepped = false, any_base = false;
+    for (const DevCfg& d : tab) {
+        stepped |= d.up || d.down;
+        any_base |= d.base != 0;
+    }
+    const void* before[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p,
+                             ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
     int rc;
     if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4)) ||
-        (rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum))) ||
         (rc = ctx->cfgs.ensure((size_t)n_cfgs * sizeof(DevCfg))))
         return rc;
-    if (d_levels && (rc = ctx->fix.ensure((size_t)max_chunks * sizeof(ChunkFix)))) return rc;
-    const void* after[4] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p};
+    if (stepped) {
+        if ((rc = ctx->step_funcs.ensure((size_t)max_chunks * sizeof(ClampAdd))) ||
+            (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
+            (rc = ctx->step_sums.ensure((size_t)max_chunks * sizeof(StepSum))))
+            return rc;
+    } else {
+        if ((rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum)))) return rc;
+        if (d_levels && (rc = ctx->fix.ensure((size_t)max_chunks * sizeof(ChunkFix)))) return rc;
+    }
+    const void* after[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p,
+                            ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
     if (std::memcmp(before, after, sizeof before) != 0) ctx->drop_graphs();
     const bool same = ctx->cfg_host.size() == tab.size() &&
                       std::memcmp(ctx->cfg_host.data(), tab.data(), tab.size() * sizeof(DevCfg)) == 0;
@@ -319,11 +337,19 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         ctx->cfg_host = tab;
     }
     auto launch = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
+        if (stepped)
+            return launch_replay_stepped(
+                d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(), n_cfgs,
+                d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(), max_chunks,
+                ctx->step_funcs.as<ClampAdd>(), ctx->step_enter.as<uint32_t>(),
+                ctx->step_sums.as<StepSum>(), d_results, d_levels, ctx->err.as<uint32_t>(), q,
+                e0, e1);
         return launch_replay(d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(),
                              n_cfgs, d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(),
                              ctx->sums.as<ChunkSum>(), max_chunks,
                              d_levels ? ctx->fix.as<ChunkFix>() : nullptr, d_results, d_levels,
-                             ctx->err.as<uint32_t>(), ctx->persistent_blocks, q, e0, e1);
+                             ctx->err.as<uint32_t>(), ctx->persistent_blocks, any_base, q, e0,
+                             e1);
     };
     const auto tp = ctx->timing_pair(MAGUS_KERNEL_REPLAY);
     if (!ctx->use_graphs) {
@@ -336,7 +362,8 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         (uint64_t)d_samples, n_samples, (uint64_t)d_offsets, n_traces, n_cfgs,
         (uint64_t)d_cfg_of_trace, (uint64_t)d_results, (uint64_t)d_levels, ctx->chunk,
         ctx->persistent_blocks, (uint64_t)ctx->cfgs.p, (uint64_t)ctx->chunk_base.p,
-        (uint64_t)ctx->sums.p, (uint64_t)ctx->fix.p};
+        (uint64_t)ctx->sums.p, (uint64_t)ctx->fix.p, (uint64_t)stepped, (uint64_t)any_base,
+        (uint64_t)ctx->step_funcs.p, (uint64_t)ctx->step_enter.p, (uint64_t)ctx->step_sums.p};
     hipGraphExec_t exec = nullptr;
     for (size_t i = 0; i < ctx->graphs.size(); ++i)
         if (ctx->graphs[i].key == key) {
@@ -501,17 +528,19 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         // Group configs by window into blocks of kSweepLanes lanes.
         std::vector<uint32_t> order(n_cfgs);
         for (uint32_t i = 0; i < n_cfgs; ++i) order[i] = i;
+        auto wkey = [&](uint32_t i) { return tab[i].W | ((uint32_t)tab[i].base << 8); };
         std::stable_sort(order.begin(), order.end(),
-                         [&](uint32_t a, uint32_t b) { return tab[a].W < tab[b].W; });
+                         [&](uint32_t a, uint32_t b) { return wkey(a) < wkey(b); });
         std::vector<uint32_t> bw;
         std::vector<int32_t> inc, dec;
-        std::vector<uint32_t> hmask, thr, lv, orig;
+        std::vector<uint32_t> hmask, thr, lv, orig, steps, bstep;
         size_t i = 0;
         while (i < order.size()) {
-            const uint32_t W = tab[order[i]].W;
+            const uint32_t W = wkey(order[i]);
             bw.push_back(W);
+            uint32_t any_step = 0;
             for (int l = 0; l < kSweepLanes; ++l) {
-                if (i < order.size() && tab[order[i]].W == W) {
+                if (i < order.size() && wkey(order[i]) == W) {
                     const DevCfg& d = tab[order[i]];
                     inc.push_back(d.inc_q);
                     dec.push_back(d.dec_q);
@@ -519,6 +548,8 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                     thr.push_back(d.thr);
                     lv.push_back(d.lmin | (d.lmax << 8) | (d.linit << 16));
                     orig.push_back(order[i]);
+                    steps.push_back(d.up | ((uint32_t)d.down << 8));
+                    any_step |= d.up | d.down;
                     ++i;
                 } else {   // padding lane: never predicts, never reported
                     inc.push_back(INT32_MAX);
@@ -527,14 +558,16 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                     thr.push_back(1u);
                     lv.push_back(0u | (1u << 8));
                     orig.push_back(0xFFFFFFFFu);
+                    steps.push_back(0u);
                 }
             }
+            bstep.push_back(any_step ? 1u : 0u);
         }
         const uint32_t nb = (uint32_t)bw.size();
         if ((uint64_t)nb * n_traces >= (1ull << 31))
             return fail(MAGUS_EINVAL, "traces x config blocks too large for one call");
         const size_t nl = (size_t)nb * kSweepLanes;
-        const size_t bytes = nb * 4 + nl * 4 * 6 + 6 * 256;
+        const size_t bytes = nb * 4 * 2 + nl * 4 * 7 + 9 * 256;
         int rc;
         if ((rc = ctx->sweep_tab.ensure(bytes))) return rc;
         std::vector<uint8_t> host(bytes, 0);
@@ -548,7 +581,8 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         size_t o_bw = put(bw.data(), nb * 4), o_inc = put(inc.data(), nl * 4),
                o_dec = put(dec.data(), nl * 4), o_hm = put(hmask.data(), nl * 4),
                o_thr = put(thr.data(), nl * 4), o_lv = put(lv.data(), nl * 4),
-               o_orig = put(orig.data(), nl * 4);
+               o_orig = put(orig.data(), nl * 4), o_steps = put(steps.data(), nl * 4),
+               o_bstep = put(bstep.data(), nb * 4);
         HIP_TRY(hipMemcpyAsync(ctx->sweep_tab.p, host.data(), off, hipMemcpyHostToDevice, stream));
         char* base = ctx->sweep_tab.as<char>();
         ctx->plan.n_blocks = nb;
@@ -559,6 +593,8 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         ctx->plan.lane_thr = reinterpret_cast<const uint32_t*>(base + o_thr);
         ctx->plan.lane_lv = reinterpret_cast<const uint32_t*>(base + o_lv);
         ctx->plan.lane_orig = reinterpret_cast<const uint32_t*>(base + o_orig);
+        ctx->plan.lane_steps = reinterpret_cast<const uint32_t*>(base + o_steps);
+        ctx->plan.block_stepped = reinterpret_cast<const uint32_t*>(base + o_bstep);
         ctx->sweep_cfg_host.assign(h_cfgs, h_cfgs + n_cfgs);
     }
     if ((uint64_t)ctx->plan.n_blocks * n_traces >= (1ull << 31))
@@ -569,6 +605,26 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     HIP_TRY(launch_sweep(d_samples, n_samples, d_offsets, n_traces, ctx->plan, n_cfgs, d_scores,
                          d_argmin, ctx->keys.as<uint64_t>(), ctx->err.as<uint32_t>(), stream,
                          tp.first, tp.second));
+    return MAGUS_OK;
+}
+
+int magus_counters_to_mbps(magus_ctx* ctx, const uint64_t* d_counts, const uint64_t* d_ts_ns,
+                           uint64_t n_readings, const uint64_t* d_offsets, uint32_t n_traces,
+                           uint32_t counter_bits, uint32_t bytes_per_count,
+                           uint32_t* d_samples, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (counter_bits < 1 || counter_bits > 64)
+        return fail(MAGUS_EINVAL, "counter_bits %u outside 1..64", counter_bits);
+    if (n_traces && (!d_offsets || !d_samples || !d_counts || !d_ts_ns))
+        return fail(MAGUS_EINVAL, "NULL argument");
+    if (n_traces == 0 || n_readings == 0) return MAGUS_OK;
+    if (n_readings / 256 >= 0xFFFFFFFFull) return fail(MAGUS_EINVAL, "too many readings");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    if (int rc = ctx->status.ensure(256)) return rc;
+    HIP_TRY(launch_counters(d_counts, d_ts_ns, d_offsets, n_traces, n_readings, counter_bits,
+                            bytes_per_count, ctx->status.as<uint32_t>(), ctx->err.as<uint32_t>(),
+                            d_samples, stream));
     return MAGUS_OK;
 }
 

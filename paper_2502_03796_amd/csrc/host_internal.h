@@ -62,8 +62,12 @@ struct magus_ctx {
     magus::DevBuf sums;         // replay: ChunkSum per chunk
     magus::DevBuf fix;          // replay: ChunkFix per chunk
     magus::DevBuf cfgs;         // replay: DevCfg table
+    magus::DevBuf step_funcs;   // stepped replay: ClampAdd per chunk
+    magus::DevBuf step_enter;   // stepped replay: entering level per chunk
+    magus::DevBuf step_sums;    // stepped replay: StepSum per chunk
     std::vector<magus::DevCfg> cfg_host;        // last uploaded table
     magus::DevBuf keys;         // sweep: arg-min keys + status
+    magus::DevBuf status;       // front end: per-call status word
     magus::DevBuf sweep_tab;    // sweep: lane tables
     std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
     magus::SweepPlan plan{};

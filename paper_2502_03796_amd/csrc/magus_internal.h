@@ -19,10 +19,21 @@ struct DevCfg {
     uint32_t md;         // W * |dec_q16|  (E1': (hi-lo) * 2^16 > lo * md -> -1)
     int32_t inc_q;       // inc_q16 (sweep quotient form)
     int32_t dec_q;       // dec_q16
-    uint32_t thr;        // ceil(hf_num * H / hf_den): high iff events >= thr
-    uint8_t lmin, lmax, linit, pad;
+    uint16_t thr;        // ceil(hf_num * H / hf_den): high iff events >= thr
+    uint8_t up, down;    // step sizes of an executed +1 / -1 (0 = to the bound)
+    uint8_t lmin, lmax, linit;
+    uint8_t base;        // derivative base: 0 min(oldest, newest), 1 oldest, 2 newest
 };
 static_assert(sizeof(DevCfg) == 32, "DevCfg layout");
+
+// Base of the relative derivative of Alg. 1 for one step: the smaller of the
+// two samples, or (alternative readings) the oldest or the newest.
+__device__ __forceinline__ uint32_t derivative_base(uint32_t a, uint32_t b, uint32_t base) {
+    // masking the excluded sample to all-ones turns min() into a selection
+    const uint32_t mo = base == 2 ? 0xFFFFFFFFu : 0u;
+    const uint32_t mn = base == 1 ? 0xFFFFFFFFu : 0u;
+    return min(a | mo, b | mn);
+}
 
 // Summary of one time chunk of one trace, computed without knowing the level
 // entering the chunk (taken as level_min for the bit vector).  32 bytes.
@@ -54,6 +65,19 @@ enum : uint32_t {
     kErrCfgIndex = 4u,   // cfg_of_trace out of range
 };
 
+// Clamp-add map of levels, f(x) = min(max(x + a, lo), hi) with lo <= hi: the
+// effect of one step (or of a run of steps) of the decision rule on the level.
+struct ClampAdd {
+    int32_t a, lo, hi;
+};
+
+// Per-chunk partial sums of the stepped-actuation replay (entering level known).
+struct StepSum {
+    uint64_t level_sum;
+    uint32_t transitions;
+    uint32_t ticks_high;
+};
+
 // Kernel launchers (replay.hip / sweep.hip / serve.hip).  When ev0/ev1 are
 // not null they are recorded on `stream` right before and after the dominant
 // kernel of the call (the chunk, sweep or serve-step kernel).
@@ -62,18 +86,36 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
                          ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
                          magus_result* results, uint8_t* levels, uint32_t* err,
-                         uint32_t persistent_blocks, hipStream_t stream, hipEvent_t ev0,
-                         hipEvent_t ev1);
+                         uint32_t persistent_blocks, bool any_base, hipStream_t stream,
+                         hipEvent_t ev0, hipEvent_t ev1);
+
+// Replay for configs with stepped actuation (stepped.hip): two passes over
+// each chunk, the first composing the chunk's clamp-add map, the second
+// accumulating with the entering level that the per-trace fold derived.
+hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
+                                 const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
+                                 uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
+                                 uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
+                                 uint32_t* entering, StepSum* sums, magus_result* results,
+                                 uint8_t* levels, uint32_t* err, hipStream_t stream,
+                                 hipEvent_t ev0, hipEvent_t ev1);
+
+// Counter readings to MB/s samples (frontend.hip).
+hipError_t launch_counters(const uint64_t* counts, const uint64_t* ts, const uint64_t* offsets,
+                           uint32_t n_traces, uint64_t n_readings, uint32_t bits, uint32_t bpc,
+                           uint32_t* status, uint32_t* err, uint32_t* out, hipStream_t stream);
 
 struct SweepPlan {
     uint32_t n_blocks;        // config blocks of kSweepLanes lanes, one window each
-    const uint32_t* block_w;  // [n_blocks]
+    const uint32_t* block_w;  // [n_blocks] window | base << 8
     const int32_t* lane_inc;  // [n_blocks * kSweepLanes]
     const int32_t* lane_dec;
     const uint32_t* lane_hmask;
     const uint32_t* lane_thr;
     const uint32_t* lane_lv;  // lmin | lmax << 8 | linit << 16
     const uint32_t* lane_orig;// original config index, 0xFFFFFFFF = padding
+    const uint32_t* lane_steps;   // up_step | down_step << 8
+    const uint32_t* block_stepped;// [n_blocks] 1 if any lane has a step size
 };
 constexpr int kSweepLanes = 256;
 

@@ -132,7 +132,7 @@ static_assert(64 % kIter == 0, "an iteration must not straddle a group of 64 blo
 // while iteration i is evaluated.  Blocks of a group of 64 consecutive blocks
 // leave their decisive-step masks in lane j = block index of VGPRs; at the end
 // of the group every lane resolves the level bits of its own block.
-template <bool kLevels>
+template <bool kLevels, bool kAnyBase>
 __device__ __forceinline__ void replay_chunk(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -187,8 +187,9 @@ __device__ __forceinline__ void replay_chunk(
     // Alg. 1 for the 64 steps of a block: event and rising masks.
     auto events = [&](uint32_t a, uint32_t b, uint64_t& E, uint64_t& R) {
         const bool rising = b > a;
-        const uint32_t lov = min(a, b);
+        uint32_t lov = min(a, b);
         const uint32_t d = max(a, b) - lov;
+        if constexpr (kAnyBase) lov = derivative_base(a, b, c.base);
         const uint32_t m = rising ? mu : md;
         // r = d / (W lo) beyond q / 2^16  <=>  d 2^16 > lo (W q)
         const bool ev = ((uint64_t)d << 16) > (uint64_t)lov * m;
@@ -381,7 +382,7 @@ __device__ __forceinline__ void replay_chunk(
 }
 
 // One wave per chunk.
-template <bool kLevels>
+template <bool kLevels, bool kAnyBase>
 __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -391,13 +392,13 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
 {
     const uint32_t g = blockIdx.x * kChunkWavesPerBlock + uniform(threadIdx.x >> 6);
     if (g >= chunk_base[n_traces]) return;
-    replay_chunk<kLevels>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk,
-                          sums, fix, levels, g, threadIdx.x & 63);
+    replay_chunk<kLevels, kAnyBase>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
+                                    chunk, sums, fix, levels, g, threadIdx.x & 63);
 }
 
 // Persistent grid: every wave takes chunks from a device counter until none
 // is left (the counter is cleared by the plan kernel of the same call).
-template <bool kLevels>
+template <bool kLevels, bool kAnyBase>
 __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel_persistent(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, uint32_t* __restrict__ chunk_base,
@@ -413,8 +414,8 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel_pers
         if (lane == 0) g = atomicAdd(counter, 1u);
         g = uniform(__shfl(g, 0, 64));
         if (g >= total) break;
-        replay_chunk<kLevels>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk,
-                              sums, fix, levels, g, lane);
+        replay_chunk<kLevels, kAnyBase>(samples, offsets, n_traces, chunk_base, cfgs,
+                                        cfg_of_trace, chunk, sums, fix, levels, g, lane);
     }
 }
 
@@ -471,38 +472,49 @@ __global__ __launch_bounds__(256) void fixup_kernel(
 
 }  // namespace
 
+hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,
+                       const uint32_t* cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
+                       uint32_t max_chunks, uint32_t* chunk_base, uint32_t* err,
+                       hipStream_t stream)
+{
+    plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
+                                                n_cfgs, chunk, max_chunks, chunk_base, err);
+    return hipGetLastError();
+}
+
 hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
                          uint32_t n_traces, const DevCfg* cfgs, uint32_t n_cfgs,
                          const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
                          ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
                          magus_result* results, uint8_t* levels, uint32_t* err,
-                         uint32_t persistent_blocks, hipStream_t stream, hipEvent_t ev0,
-                         hipEvent_t ev1)
+                         uint32_t persistent_blocks, bool any_base, hipStream_t stream,
+                         hipEvent_t ev0, hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
     plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
                                                 n_cfgs, chunk, max_chunks, chunk_base, err);
     uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
     if (ev0) (void)hipEventRecord(ev0, stream);
-    if (blocks && persistent_blocks) {
-        blocks = min(blocks, persistent_blocks);
-        if (levels)
-            chunk_kernel_persistent<true><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
-                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, fix,
-                levels);
+    auto go = [&](auto levels_tag, auto base_tag) {
+        constexpr bool kL = decltype(levels_tag)::value, kB = decltype(base_tag)::value;
+        ChunkFix* f = kL ? fix : nullptr;
+        uint8_t* lv = kL ? levels : nullptr;
+        if (persistent_blocks)
+            chunk_kernel_persistent<kL, kB>
+                <<<min(blocks, persistent_blocks), kChunkWavesPerBlock * kWave, 0, stream>>>(
+                    samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, f, lv);
         else
-            chunk_kernel_persistent<false><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
-                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums,
-                nullptr, nullptr);
-    } else if (blocks) {
-        if (levels)
-            chunk_kernel<true><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
-                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, fix,
-                levels);
-        else
-            chunk_kernel<false><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
-                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums,
-                nullptr, nullptr);
+            chunk_kernel<kL, kB><<<blocks, kChunkWavesPerBlock * kWave, 0, stream>>>(
+                samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, sums, f, lv);
+    };
+    if (blocks) {
+        if (levels) {
+            if (any_base) go(std::true_type{}, std::true_type{});
+            else go(std::true_type{}, std::false_type{});
+        } else {
+            if (any_base) go(std::false_type{}, std::true_type{});
+            else go(std::false_type{}, std::false_type{});
+        }
     }
     if (ev1) (void)hipEventRecord(ev1, stream);
     fold_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(

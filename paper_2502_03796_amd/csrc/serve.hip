@@ -48,10 +48,11 @@ __global__ __launch_bounds__(256) void serve_step_kernel(
     int pred = 0;
     if (k >= w1) {
         const uint32_t a = st[slot].ring[pos];                  // sample k-W+1
-        const uint32_t hiv = max(a, b), lov = min(a, b);
+        const uint32_t d = max(a, b) - min(a, b);
+        const uint32_t lov = derivative_base(a, b, c.base);
         const bool rising = b > a;
         const uint32_t m = rising ? c.mu : c.md;
-        if (((uint64_t)(hiv - lov) << 16) > (uint64_t)lov * m) pred = rising ? 1 : -1;
+        if (((uint64_t)d << 16) > (uint64_t)lov * m) pred = rising ? 1 : -1;
     }
     st[slot].ring[pos] = b;
     st[slot].ticks = k + 1;
@@ -60,8 +61,11 @@ __global__ __launch_bounds__(256) void serve_step_kernel(
     A.hist = ((A.hist << 1) | (uint32_t)(pred != 0)) & hmask;
     const bool high = (uint32_t)__popc(A.hist) >= c.thr;
     uint32_t next = A.level;
-    if (high || pred == 1) next = c.lmax;
-    else if (pred == -1) next = c.lmin;
+    if (high) next = c.lmax;
+    else if (pred == 1) next = c.up ? min(A.level + c.up, (uint32_t)c.lmax) : c.lmax;
+    else if (pred == -1)
+        next = c.down ? (A.level < (uint32_t)c.lmin + c.down ? c.lmin : A.level - c.down)
+                      : c.lmin;
     A.transitions += (next != A.level);
     A.level = next;
     A.level_sum += next;

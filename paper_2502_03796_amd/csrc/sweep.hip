@@ -25,24 +25,29 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// Quotients of step t (t >= W-1) of trace x.
-__device__ __forceinline__ int2 step_quotients(uint32_t a, uint32_t b, uint32_t W) {
+// Quotients of step t (t >= W-1) of trace x.  The derivative's base is the
+// smaller sample by default (a for a rise, b for a fall), or always the
+// oldest (base 1) or always the newest (base 2) sample.
+__device__ __forceinline__ int2 step_quotients(uint32_t a, uint32_t b, uint32_t W,
+                                               uint32_t base) {
     int2 r = make_int2(0, 0);
     if (b > a) {
-        if (a == 0) {
+        const uint32_t bu = base == 2 ? b : a;
+        if (bu == 0) {
             r.x = INT32_MAX;
         } else {
             const uint64_t num = (uint64_t)(b - a) << 16;
-            const uint64_t den = (uint64_t)W * a;
+            const uint64_t den = (uint64_t)W * bu;
             const uint64_t q = (num + den - 1) / den;
             r.x = q > (uint64_t)INT32_MAX ? INT32_MAX : (int32_t)q;
         }
     } else if (b < a) {
-        if (b == 0) {
+        const uint32_t bd = base == 1 ? a : b;
+        if (bd == 0) {
             r.y = INT32_MIN;
         } else {
             const uint64_t num = (uint64_t)(a - b) << 16;
-            const uint64_t den = (uint64_t)W * b;
+            const uint64_t den = (uint64_t)W * bd;
             const uint64_t q = (num + den - 1) / den;     // ceil of |R'|
             r.y = q >= (uint64_t)1 << 31 ? INT32_MIN : -(int32_t)q;
         }
@@ -56,7 +61,8 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     const uint32_t* __restrict__ block_w, const int32_t* __restrict__ lane_inc,
     const int32_t* __restrict__ lane_dec, const uint32_t* __restrict__ lane_hmask,
     const uint32_t* __restrict__ lane_thr, const uint32_t* __restrict__ lane_lv,
-    const uint32_t* __restrict__ lane_orig, uint32_t n_cfgs,
+    const uint32_t* __restrict__ lane_orig, const uint32_t* __restrict__ lane_steps,
+    const uint32_t* __restrict__ block_stepped, uint32_t n_cfgs,
     uint64_t* __restrict__ scores, uint64_t* __restrict__ keys)
 {
     __shared__ int2 ud[2][kTile];
@@ -72,7 +78,7 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     const uint32_t t = work / n_blocks, blk = work % n_blocks;
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t W = block_w[blk];
+    const uint32_t W = block_w[blk] & 255u, base = block_w[blk] >> 8;
     const uint32_t li = blk * kSweepLanes + tid;
     const int32_t inc = lane_inc[li], dec = lane_dec[li];
     const uint32_t hmask = lane_hmask[li], thr = lane_thr[li];
@@ -87,11 +93,17 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     uint32_t hist = 0, trans = 0, cmax = 0, cinit = 0;
     bool lvl = linit == lmax;                       // level bit (1 = max)
     bool at_init = linit != lmin && linit != lmax;  // still at a middle initial level
+    // stepped actuation (integer level) for blocks holding such configs
+    const bool stepped = block_stepped[blk] != 0;
+    const uint32_t st = lane_steps[li];
+    const uint32_t ustep = st & 255u, dstep = (st >> 8) & 255u;
+    uint32_t ilvl = linit;
+    uint64_t isum = 0;
 
     auto prepass = [&](uint32_t tile0, int buf) {
         const uint32_t step = tile0 + tid;
         int2 q = make_int2(0, 0);
-        if (step < n && step + 1 >= W) q = step_quotients(x[step + 1 - W], x[step], W);
+        if (step < n && step + 1 >= W) q = step_quotients(x[step + 1 - W], x[step], W, base);
         ud[buf][tid] = q;
     };
 
@@ -101,7 +113,21 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     for (uint32_t tile0 = 0; tile0 < n; tile0 += kTile) {
         const uint32_t nt = min((uint32_t)kTile, n - tile0);
         const int2* q = ud[buf];
-        if (__ballot(at_init) != 0) {
+        if (stepped) {
+            for (uint32_t i = 0; i < nt; ++i) {
+                const int2 v = q[i];
+                const bool up = inc < v.x, dn = dec > v.y;
+                hist = ((hist << 1) | (uint32_t)(up | dn)) & hmask;
+                const bool high = (uint32_t)__popc(hist) >= thr;
+                uint32_t nl = ilvl;
+                if (high) nl = lmax;
+                else if (up) nl = ustep ? min(ilvl + ustep, lmax) : lmax;
+                else if (dn) nl = dstep ? (ilvl < lmin + dstep ? lmin : ilvl - dstep) : lmin;
+                trans += (uint32_t)(nl != ilvl);
+                isum += nl;
+                ilvl = nl;
+            }
+        } else if (__ballot(at_init) != 0) {
             for (uint32_t i = 0; i < nt; ++i) {
                 const int2 v = q[i];
                 const bool up = inc < v.x, dn = dec > v.y;
@@ -150,8 +176,9 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
         buf ^= 1;
     }
 
-    const uint64_t level_sum = (uint64_t)lmin * (n - cmax - cinit) + (uint64_t)lmax * cmax +
-                               (uint64_t)linit * cinit;
+    const uint64_t level_sum = stepped ? isum
+                                       : (uint64_t)lmin * (n - cmax - cinit) +
+                                             (uint64_t)lmax * cmax + (uint64_t)linit * cinit;
     const uint64_t score = level_sum + 1000ull * trans;
     uint64_t key = ~0ull;
     if (orig != 0xFFFFFFFFu) {
@@ -222,8 +249,8 @@ hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint6
     if (ev0) (void)hipEventRecord(ev0, stream);
     sweep_kernel<<<grid, kSweepLanes, 0, stream>>>(
         samples, offsets, n_traces, plan.n_blocks, status, plan.block_w, plan.lane_inc,
-        plan.lane_dec, plan.lane_hmask, plan.lane_thr, plan.lane_lv, plan.lane_orig, n_cfgs,
-        scores, keys);
+        plan.lane_dec, plan.lane_hmask, plan.lane_thr, plan.lane_lv, plan.lane_orig,
+        plan.lane_steps, plan.block_stepped, n_cfgs, scores, keys);
     if (ev1) (void)hipEventRecord(ev1, stream);
     argmin_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(keys, n_traces, status, argmin);
     return hipGetLastError();

@@ -13,10 +13,12 @@ from fractions import Fraction
 INF = float("inf")
 
 
-def trend_prediction(inc_threshold, dec_threshold, mem_throughput_ls, direv_length):
-    """Alg. 1 with the derivative taken relative to the smaller end sample."""
+def trend_prediction(inc_threshold, dec_threshold, mem_throughput_ls, direv_length,
+                     which_base=0):
+    """Alg. 1 with the derivative taken relative to the smaller end sample
+    (or, as alternatives, the oldest or the newest)."""
     first, last = mem_throughput_ls[0], mem_throughput_ls[-1]
-    base = min(first, last)
+    base = (min(first, last), first, last)[which_base]
     if base == 0:
         if last == first:
             return 0                      # 0/0: no trend
@@ -51,7 +53,7 @@ def run(trace, cfg):
         mem_throughput_ls.append(int(x))
         if len(mem_throughput_ls) > W:
             mem_throughput_ls.pop(0)
-        pred = trend_prediction(inc, dec, mem_throughput_ls, W) \
+        pred = trend_prediction(inc, dec, mem_throughput_ls, W, cfg.get("base", 0)) \
             if len(mem_throughput_ls) == W else 0
         uncore_tune_ls.pop(0)
         uncore_tune_ls.append(1 if pred != 0 else 0)

@@ -48,7 +48,7 @@ def test_config_validation_on_host():
                 dict(inc_q16=-1), dict(dec_q16=1), dict(inc_q16=2**20 + 1),
                 dict(dec_q16=-2**20 - 1), dict(hf_den=0), dict(hf_num=6, hf_den=5),
                 dict(level_min=16, level_max=16), dict(level_max=32),
-                dict(level_init=17), dict(up_step=1), dict(down_step=2)):
+                dict(level_init=17), dict(up_step=32), dict(down_step=40)):
         with pytest.raises(magus.MagusError) as ei:
             magus.config_check(default_config(**bad))
         assert ei.value.code == magus.EINVAL

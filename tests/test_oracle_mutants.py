@@ -23,8 +23,16 @@ MUTANTS = [
      "if (lhs <= (int64_t)dec_q * den) return -1;"),
     ("derivative not divided by the window", "int64_t den = (int64_t)direv_length * base;",
      "int64_t den = base;"),
-    ("oldest sample as the base", "int64_t base = first < last ? first : last;",
-     "int64_t base = first;"),
+    ("oldest sample as the base", "    return first < last ? first : last;",
+     "    return first;"),
+    ("base variants swapped", "    if (which == 1) return first;\n    if (which == 2) return last;",
+     "    if (which == 1) return last;\n    if (which == 2) return first;"),
+    ("front end ignores the counter wrap",
+     "        if (counter_bits < 64) delta &= (((unsigned __int128)1) << counter_bits) - 1;\n"
+     "        else delta &= (unsigned __int128)UINT64_MAX;",
+     "        delta &= (unsigned __int128)UINT64_MAX;"),
+    ("front end rounds up", "        unsigned __int128 mbps = delta * bytes_per_count * 1000u / dt;",
+     "        unsigned __int128 mbps = (delta * bytes_per_count * 1000u + dt - 1) / dt;"),
     ("newest sample taken one step early", "int64_t last = ls[direv_length - 1];",
      "int64_t last = ls[direv_length - 2];"),
     ("sign of dec_threshold flipped", "if (lhs < (int64_t)dec_q * den) return -1;",
@@ -76,6 +84,11 @@ def _checks():
         lambda: [pins.test_stepped_staircase(om, u) for u in (1, 3, 5)],
         lambda: [pins.test_stepped_descent(om, d) for d in (2, 4)],
         lambda: pins.test_brute_force_stepped_actuation(om),
+        lambda: pins.test_oldest_sample_base_bounds_falls(om),
+        lambda: pins.test_newest_sample_base_bounds_rises(om),
+        lambda: pins.test_counters_wrap_zero_interval_and_saturation(om),
+        lambda: pins.test_counters_against_exact_rationals(om),
+        lambda: pins.test_brute_force_base_variants(om),
         lambda: pins.test_brute_force_against_exact_rational_transliteration(om),
     ]
 

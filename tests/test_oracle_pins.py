@@ -437,3 +437,76 @@ def test_brute_force_stepped_actuation(oracle_mod):
             assert b.tobytes() == ref.encode(steps), (cfg, t)
             assert [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]] == \
                 [score, ls, tr, th]
+
+
+# ---------------------------------------------------------------- derivative base variants
+
+def test_oldest_sample_base_bounds_falls(oracle_mod):
+    """With the oldest sample as the base a fall can never go below -1/W: the
+    W = 16 fall 40,000 -> 10,000 gives r = -30000 / (16 * 40000) = -0.047,
+    above dec = -0.1, so nothing happens (the min base gives -0.1875, see the
+    stuck-at-max pin)."""
+    x = [40000] * 40 + [10000] * 60
+    res, lv, hi, pr = run(oracle_mod, x, default_config(window=16, base=1))
+    assert (pr == 0).all() and res["score"] == 0
+    # ... while a rise by the same factor, r = 30000 / (16 * 10000) = 0.1875, fires
+    res, lv, hi, pr = run(oracle_mod, x[::-1], default_config(window=16, base=1))
+    assert (pr[60:75] == 1).all()
+
+
+def test_newest_sample_base_bounds_rises(oracle_mod):
+    """With the newest sample as the base a rise stays below 1/W: at W = 16,
+    10,000 -> 40,000 gives r = 0.047 < 0.1 (no event); the fall fires."""
+    x = [10000] * 40 + [40000] * 60
+    res, _, _, pr = run(oracle_mod, x, default_config(window=16, base=2))
+    assert (pr == 0).all() and res["score"] == 0
+    _, _, _, pr = run(oracle_mod, x[::-1], default_config(window=16, base=2))
+    assert (pr[60:75] == -1).all()
+
+
+def test_brute_force_base_variants(oracle_mod):
+    traces = [t for n in range(1, 6) for t in itertools.product(range(5), repeat=n)]
+    for which in (1, 2):
+        for W, inc, dec in itertools.product((2, 3, 4), (0, 16384, 32768), (0, -16384)):
+            cfg = default_config(window=W, hold=3, inc_q16=inc, dec_q16=dec, base=which)
+            for t in traces[::3]:
+                steps, score, *_ = ref.run(t, cfg)
+                r, b = oracle_mod.replay_trace(np.array(t, np.uint32), cfg)
+                assert b.tobytes() == ref.encode(steps), (which, W, inc, dec, t)
+
+
+# ---------------------------------------------------------------- monitor front end
+
+def test_counters_constant_rate(oracle_mod):
+    """1,000,000 bytes every 100 ms = 10 MB/s; 64-byte counts scale by 64."""
+    ts = np.arange(50, dtype=np.uint64) * 100_000_000
+    c = np.arange(50, dtype=np.uint64) * 1_000_000
+    assert (oracle_mod.counters_to_mbps(c, ts, 48, 1) == 10).all()
+    assert (oracle_mod.counters_to_mbps(c, ts, 48, 64) == 640).all()
+
+
+def test_counters_wrap_zero_interval_and_saturation(oracle_mod):
+    ts = np.array([0, 100, 200, 200, 300], np.uint64)
+    c = np.array([2**32 - 10, 5, 20, 30, 2**31], np.uint64)
+    out = oracle_mod.counters_to_mbps(c, ts, 32, 1)
+    # 15 B / 100 ns = 150 MB/s across the 32-bit wrap; 15 B / 100 ns; dt = 0 -> 0;
+    # ~2^31 B / 100 ns saturates
+    assert list(out) == [150, 150, 0, 2**32 - 1]
+
+
+def test_counters_against_exact_rationals(oracle_mod):
+    from fractions import Fraction
+    rng = np.random.default_rng(3)
+    for bits in (16, 32, 48, 64):
+        n = 200
+        ts = np.cumsum(rng.integers(0, 10**9, n, dtype=np.uint64)).astype(np.uint64)
+        c = rng.integers(0, 2**63, n, dtype=np.uint64)
+        if bits < 64:
+            c &= np.uint64((1 << bits) - 1)
+        for bpc in (1, 64):
+            out = oracle_mod.counters_to_mbps(c, ts, bits, bpc)
+            for i in range(n - 1):
+                d = (int(c[i + 1]) - int(c[i])) % (1 << bits)
+                dt = int(ts[i + 1]) - int(ts[i])
+                want = 0 if dt == 0 else min(int(Fraction(d * bpc * 1000, dt)), 2**32 - 1)
+                assert out[i] == want, (bits, bpc, i)
