@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip sweep/serve/fp64 reports")
     ap.add_argument("--serve-ticks", type=int, default=50)
     ap.add_argument("--chunk", type=int, default=0, help="time-chunk length (0: default)")
+    ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy kernel over as many bytes as the "
                          "bulk workload (read 4 B + write 4 B per sample), for scaling HBM "
@@ -104,8 +105,21 @@ def main():
     results = torch.empty((args.traces, 4), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    cfg_arr = magus.config_array([cfg])
+    # eager launches (plan, chunk and fold kernels per call), for reference
+    for _ in range(max(args.warmup, 1)):
+        ctx.replay(s, o, cfg_arr, results=results)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.replay(s, o, cfg_arr, results=results)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ctx.check()
+    # timed steps: the same call relaunched as a captured hipGraph
+    ctx.set_graphs(not args.no_graphs)
     for _ in range(args.warmup):
-        ctx.replay(s, o, [cfg], results=results)
+        ctx.replay(s, o, cfg_arr, results=results)
     ctx.check()
 
     torch.cuda.synchronize()
@@ -113,19 +127,30 @@ def main():
     ctx.kernel_time(magus.KERNEL_REPLAY)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.replay(s, o, [cfg], results=results)
+        ctx.replay(s, o, cfg_arr, results=results)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_profiling(False)
     kms, launches = ctx.kernel_time(magus.KERNEL_REPLAY)
     ctx.check()
+    ctx.set_graphs(False)
+    # the chunk kernel alone, timed with events around it on its stream
+    ctx.set_profiling(True)
+    ctx.kernel_time(magus.KERNEL_REPLAY)
+    for _ in range(args.steps):
+        ctx.replay(s, o, cfg_arr, results=results)
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    kchunk, nchunk = ctx.kernel_time(magus.KERNEL_REPLAY)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n_samples / (ms_per_step * 1e-3)
-    avg_kernel_ms = kms / max(launches, 1)
+    graph_ms = kms / max(launches, 1)
+    avg_kernel_ms = kchunk / max(nchunk, 1)
     bytes_per_launch = 4.0 * n_samples            # one read of every uint32 sample
     achieved = bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9
-    log(f"replay: {ms_per_step:.4f} ms/step, chunk kernel {avg_kernel_ms:.4f} ms "
-        f"({achieved:.0f} GB/s), {value:.3e} samples/s")
+    log(f"replay: {ms_per_step:.4f} ms/step (graph {graph_ms:.4f} ms on the stream, eager "
+        f"{eager_ms:.4f} ms/step), chunk kernel {avg_kernel_ms:.4f} ms ({achieved:.0f} GB/s), "
+        f"{value:.3e} samples/s")
 
     # parity spot check of the timed launch against the oracle
     import oracle
@@ -155,7 +180,9 @@ def main():
         "config": {"workload": f"bulk replay: {args.traces} traces x {args.length} uint32 "
                                "samples, 1 default config (W=4, +-0.1, H=10, 0.6)",
                    "traces": args.traces, "samples_per_trace": args.length, "configs": 1,
-                   "chunk_steps": ctx.chunk},
+                   "chunk_steps": ctx.chunk,
+                   "launch": "hipGraph" if not args.no_graphs else "eager",
+                   "eager_ms_per_step": eager_ms},
         "parity": parity,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -196,14 +223,15 @@ def main():
         ss = torch.from_numpy(ssmp.view(np.int32)).to(dev)
         so = torch.from_numpy(soff.view(np.int64)).to(dev)
         grid = synth.sweep_grid()
-        ctx.sweep(ss, so, grid)
+        grid_arr = magus.config_array(grid)      # marshalled once
+        ctx.sweep(ss, so, grid_arr)
         torch.cuda.synchronize()
         ctx.set_profiling(True)
         ctx.kernel_time(magus.KERNEL_SWEEP)
         reps = 3
         t0 = time.perf_counter()
         for _ in range(reps):
-            _, arg = ctx.sweep(ss, so, grid)
+            _, arg = ctx.sweep(ss, so, grid_arr)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         ctx.set_profiling(False)
@@ -227,15 +255,15 @@ def main():
         uc = torch.from_numpy(ucot.view(np.int32)).to(dev)
         uctx = magus.Context(0)
         ures = torch.empty((len(uoff) - 1, 4), dtype=torch.int64, device=dev)
-        chosen = uctx.autotune_replay(us, uo, grid, uc, reps=3, results=ures)
+        chosen = uctx.autotune_replay(us, uo, grid_arr, uc, reps=3, results=ures)
         uctx.set_graphs(True)
         for _ in range(3):
-            uctx.replay(us, uo, grid, uc, results=ures)
+            uctx.replay(us, uo, grid_arr, uc, results=ures)
         torch.cuda.synchronize()
         reps = 10
         t0 = time.perf_counter()
         for _ in range(reps):
-            uctx.replay(us, uo, grid, uc, results=ures)
+            uctx.replay(us, uo, grid_arr, uc, results=ures)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         uctx.check()
@@ -266,7 +294,7 @@ def main():
         n_ev_samples = int((ev["kind"] == synth.EV_SAMPLE).sum())
         log(f"  {len(ev)} events ({n_ev_samples} samples) generated in {time.time() - t0:.1f} s")
         srv = magus.Server(ctx, (65536 + 256) * magus.Server.slot_bytes())
-        dec, lat, st = srv.run(ev, n_streams, grid, realtime=True, depth=2)
+        dec, lat, st = srv.run(ev, n_streams, grid_arr, realtime=True, depth=2)
         served = (ev["kind"] == synth.EV_SAMPLE) & (dec != 0xFF)
         lat_ms = lat[served].astype(np.float64) * 1e-6
         # parity of sampled nodes against the oracle replay of their served samples
@@ -276,7 +304,7 @@ def main():
             _, want = oracle.replay_trace(ev["value"][m], grid[int(cfg_of_stream[sid])])
             if not (dec[m] == want).all():
                 raise SystemExit(f"serving parity failure on node {sid}")
-        dec2, lat2, st2 = srv.run(ev, n_streams, grid, realtime=False, depth=3)
+        dec2, lat2, st2 = srv.run(ev, n_streams, grid_arr, realtime=False, depth=3)
         srv.close()
         extra["serve"] = {
             "workload": f"65,536 nodes + Poisson joins/leaves 50/s, {args.serve_ticks} ticks of "

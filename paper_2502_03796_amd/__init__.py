@@ -139,6 +139,11 @@ def make_config(d: dict) -> MagusConfig:
 
 
 def config_array(cfgs) -> ctypes.Array:
+    """Marshal configs (a dict, a list of dicts, or an already built array)."""
+    if isinstance(cfgs, ctypes.Array):
+        return cfgs
+    if isinstance(cfgs, dict):
+        cfgs = [cfgs]
     arr = (MagusConfig * len(cfgs))()
     for i, d in enumerate(cfgs):
         arr[i] = make_config(d)
@@ -215,17 +220,16 @@ class Context:
         """Time every chunk length / launch shape on this batch (results must agree),
         keep the fastest on the context and return what was chosen."""
         torch = _torch()
-        cfgs = [cfgs] if isinstance(cfgs, dict) else list(cfgs)
+        arr = config_array(cfgs)
         n_traces = offsets.numel() - 1
         if results is None:
             results = torch.empty((n_traces, 4), dtype=torch.int64, device=samples.device)
         cp = None if cfg_of_trace is None else _dev_ptr(cfg_of_trace, "cfg_of_trace",
                                                         (torch.int32, torch.uint32))
-        arr = config_array(cfgs)
         r = MagusTuneResult()
         _check(load().magus_autotune_replay(
             self._h, _dev_ptr(samples, "samples", (torch.int32, torch.uint32)), samples.numel(),
-            _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64)), n_traces, arr, len(cfgs),
+            _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64)), n_traces, arr, len(arr),
             cp, _dev_ptr(results, "results", (torch.int64,)), int(reps),
             _stream_handle(stream, self.device), ctypes.byref(r)))
         return {f: getattr(r, f) for f, _ in MagusTuneResult._fields_ if f != "reserved"}
@@ -252,7 +256,7 @@ class Context:
         results columns: score, level_sum, transitions, ticks_high.
         """
         torch = _torch()
-        cfgs = [cfgs] if isinstance(cfgs, dict) else list(cfgs)
+        arr = config_array(cfgs)
         sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
         op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
         n_traces = offsets.numel() - 1
@@ -267,8 +271,7 @@ class Context:
             if levels_out is None:
                 levels_out = torch.zeros(samples.numel(), dtype=torch.uint8, device=samples.device)
             lp = _dev_ptr(levels_out, "levels", (torch.uint8,))
-        arr = config_array(cfgs)
-        _check(load().magus_replay(self._h, sp, samples.numel(), op, n_traces, arr, len(cfgs),
+        _check(load().magus_replay(self._h, sp, samples.numel(), op, n_traces, arr, len(arr),
                                    cp, rp, lp, _stream_handle(stream, self.device)))
         return results, (levels_out if levels else None)
 
@@ -295,7 +298,7 @@ class Context:
     def sweep(self, samples, offsets, cfgs, scores: bool = False, stream=None):
         """Every trace against every config; returns (scores int64[T, C] or None, argmin int32[T])."""
         torch = _torch()
-        cfgs = list(cfgs)
+        arr = config_array(cfgs)
         sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
         op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
         n_traces = offsets.numel() - 1
@@ -303,10 +306,9 @@ class Context:
         sc = None
         scp = None
         if scores:
-            sc = torch.empty((n_traces, len(cfgs)), dtype=torch.int64, device=samples.device)
+            sc = torch.empty((n_traces, len(arr)), dtype=torch.int64, device=samples.device)
             scp = _dev_ptr(sc, "scores", (torch.int64,))
-        arr = config_array(cfgs)
-        _check(load().magus_sweep(self._h, sp, samples.numel(), op, n_traces, arr, len(cfgs),
+        _check(load().magus_sweep(self._h, sp, samples.numel(), op, n_traces, arr, len(arr),
                                   scp, _dev_ptr(argmin, "argmin", (torch.int32,)),
                                   _stream_handle(stream, self.device)))
         return sc, argmin
@@ -388,7 +390,7 @@ class Server:
         samples of nodes that were not admitted.
         """
         ev = np.ascontiguousarray(events, dtype=EVENT_DTYPE)
-        arr = config_array(list(cfgs))
+        arr = config_array(cfgs)
         dec = np.empty(len(ev), np.uint8)
         lat = np.empty(len(ev), np.uint64)
         st = MagusRunStats()

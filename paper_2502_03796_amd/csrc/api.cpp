@@ -292,12 +292,21 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         return fail(MAGUS_EINVAL, "offsets and results are required");
     if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
     if (n_traces > (1u << 30)) return fail(MAGUS_EINVAL, "too many traces");
-    std::vector<DevCfg> tab(n_cfgs);
-    for (uint32_t i = 0; i < n_cfgs; ++i) {
-        int rc = derive(&h_cfgs[i], &tab[i]);
-        if (rc != MAGUS_OK)
-            return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
+    // configs identical to the previous call's are neither re-validated nor
+    // re-uploaded
+    const bool same = ctx->cfg_raw.size() == n_cfgs &&
+                      std::memcmp(ctx->cfg_raw.data(), h_cfgs,
+                                  (size_t)n_cfgs * sizeof(magus_config)) == 0;
+    std::vector<DevCfg> fresh;
+    if (!same) {
+        fresh.resize(n_cfgs);
+        for (uint32_t i = 0; i < n_cfgs; ++i) {
+            int rc = derive(&h_cfgs[i], &fresh[i]);
+            if (rc != MAGUS_OK)
+                return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
+        }
     }
+    const std::vector<DevCfg>& tab = same ? ctx->cfg_host : fresh;
     if (n_traces == 0) return MAGUS_OK;
     const uint64_t max_chunks64 = n_samples / ctx->chunk + n_traces + 1;
     if (max_chunks64 > 0xFFFFFFF0ull) return fail(MAGUS_EINVAL, "batch too large for one call");
@@ -328,13 +337,14 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     const void* after[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p,
                             ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
     if (std::memcmp(before, after, sizeof before) != 0) ctx->drop_graphs();
-    const bool same = ctx->cfg_host.size() == tab.size() &&
-                      std::memcmp(ctx->cfg_host.data(), tab.data(), tab.size() * sizeof(DevCfg)) == 0;
-    if (!same) {
+    if (!same || before[2] != after[2]) {
         // pageable source: the runtime stages it before returning
         HIP_TRY(hipMemcpyAsync(ctx->cfgs.p, tab.data(), tab.size() * sizeof(DevCfg),
                                hipMemcpyHostToDevice, stream));
-        ctx->cfg_host = tab;
+        if (!same) {
+            ctx->cfg_host = fresh;
+            ctx->cfg_raw.assign(h_cfgs, h_cfgs + n_cfgs);
+        }
     }
     auto launch = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
         if (stepped)
@@ -511,19 +521,23 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     if (n_traces && (!d_offsets || !d_argmin))
         return fail(MAGUS_EINVAL, "offsets and argmin are required");
     if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
-    std::vector<DevCfg> tab(n_cfgs);
-    for (uint32_t i = 0; i < n_cfgs; ++i) {
-        int rc = derive(&h_cfgs[i], &tab[i]);
-        if (rc != MAGUS_OK)
-            return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
+    // configs identical to the previous sweep's keep their lane tables
+    const bool same = ctx->sweep_cfg_host.size() == n_cfgs &&
+                      std::memcmp(ctx->sweep_cfg_host.data(), h_cfgs,
+                                  (size_t)n_cfgs * sizeof(magus_config)) == 0;
+    std::vector<DevCfg> tab;
+    if (!same) {
+        tab.resize(n_cfgs);
+        for (uint32_t i = 0; i < n_cfgs; ++i) {
+            int rc = derive(&h_cfgs[i], &tab[i]);
+            if (rc != MAGUS_OK)
+                return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
+        }
     }
     if (n_traces == 0) return MAGUS_OK;
 
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
-    const bool same = ctx->sweep_cfg_host.size() == n_cfgs &&
-                      std::memcmp(ctx->sweep_cfg_host.data(), h_cfgs,
-                                  (size_t)n_cfgs * sizeof(magus_config)) == 0;
     if (!same) {
         // Group configs by window into blocks of kSweepLanes lanes.
         std::vector<uint32_t> order(n_cfgs);

@@ -66,6 +66,7 @@ struct magus_ctx {
     magus::DevBuf step_enter;   // stepped replay: entering level per chunk
     magus::DevBuf step_sums;    // stepped replay: StepSum per chunk
     std::vector<magus::DevCfg> cfg_host;        // last uploaded table
+    std::vector<magus_config> cfg_raw;          // ... and the configs it came from
     magus::DevBuf keys;         // sweep: arg-min keys + status
     magus::DevBuf status;       // front end: per-call status word
     magus::DevBuf sweep_tab;    // sweep: lane tables

@@ -62,60 +62,64 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
     const uint32_t* __restrict__ cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
     uint32_t max_chunks, uint32_t* __restrict__ chunk_base, uint32_t* __restrict__ err)
 {
+    // Thread i owns the contiguous traces [i*per, (i+1)*per): one pass counts
+    // their chunks, one block-wide scan places them, a second pass writes.
     __shared__ uint32_t wave_sum[kPlanThreads / kWave];
-    __shared__ uint32_t s_running;
     __shared__ uint32_t s_err;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) { s_running = 0; s_err = 0; }
+    if (tid == 0) s_err = 0;
+    const uint32_t per = (n_traces + kPlanThreads - 1) / kPlanThreads;
+    const uint32_t t0 = min(tid * per, n_traces), t1 = min(t0 + per, n_traces);
+    auto chunks_of = [&](uint32_t t, uint32_t& e) -> uint32_t {
+        const uint64_t o0 = offsets[t], o1 = offsets[t + 1];
+        if (cfg_of_trace && cfg_of_trace[t] >= n_cfgs) e |= kErrCfgIndex;
+        if (o1 < o0 || o1 > n_samples) {
+            e |= kErrOffsets;
+            return 0;
+        }
+        if (o1 - o0 > MAGUS_MAX_TRACE_LEN) {
+            e |= kErrTooLong;
+            return 0;
+        }
+        return (uint32_t)((o1 - o0 + chunk - 1) / chunk);
+    };
+    uint32_t e = 0, mine = 0;
+    for (uint32_t t = t0; t < t1; ++t) mine += chunks_of(t, e);
     __syncthreads();
-    for (uint32_t base = 0; base < n_traces; base += kPlanThreads) {
-        const uint32_t t = base + tid;
-        uint32_t nch = 0, e = 0;
-        if (t < n_traces) {
-            const uint64_t o0 = offsets[t], o1 = offsets[t + 1];
-            if (o1 < o0 || o1 > n_samples) {
-                e |= kErrOffsets;
-            } else if (o1 - o0 > MAGUS_MAX_TRACE_LEN) {
-                e |= kErrTooLong;
-            } else {
-                nch = (uint32_t)((o1 - o0 + chunk - 1) / chunk);
-            }
-            if (cfg_of_trace && cfg_of_trace[t] >= n_cfgs) e |= kErrCfgIndex;
-        }
-        if (e) atomicOr(&s_err, e);
-        // inclusive scan inside the wave
-        uint32_t v = nch;
+    if (e) atomicOr(&s_err, e);
+    // exclusive scan of `mine` over the block
+    uint32_t v = mine;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            uint32_t o = __shfl_up(v, d, 64);
-            if (lane >= (uint32_t)d) v += o;
-        }
-        if (lane == 63) wave_sum[wv] = v;
-        __syncthreads();
-        if (wv == 0) {
-            uint32_t w = lane < kPlanThreads / kWave ? wave_sum[lane] : 0;
-#pragma unroll
-            for (int d = 1; d < kPlanThreads / kWave; d <<= 1) {
-                uint32_t o = __shfl_up(w, d, 64);
-                if (lane >= (uint32_t)d) w += o;
-            }
-            if (lane < kPlanThreads / kWave) wave_sum[lane] = w;   // inclusive
-        }
-        __syncthreads();
-        const uint32_t before = s_running + (wv ? wave_sum[wv - 1] : 0);
-        if (t < n_traces) chunk_base[t] = before + v - nch;
-        __syncthreads();
-        if (tid == 0) s_running += wave_sum[kPlanThreads / kWave - 1];
-        __syncthreads();
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += o;
     }
-    if (tid == 0) {
-        uint32_t total = s_running;
-        uint32_t e = s_err;
-        if (total > max_chunks) e |= kErrOffsets;
-        chunk_base[n_traces] = e ? 0u : total;
-        chunk_base[n_traces + 1] = e;            // status of this call
+    if (lane == 63) wave_sum[wv] = v;
+    __syncthreads();
+    if (wv == 0) {
+        uint32_t w = lane < kPlanThreads / kWave ? wave_sum[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < kPlanThreads / kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(w, d, 64);
+            if (lane >= (uint32_t)d) w += o;
+        }
+        if (lane < kPlanThreads / kWave) wave_sum[lane] = w;   // inclusive
+    }
+    __syncthreads();
+    uint32_t run = (wv ? wave_sum[wv - 1] : 0) + v - mine;
+    for (uint32_t t = t0; t < t1; ++t) {
+        uint32_t dummy = 0;
+        chunk_base[t] = run;
+        run += chunks_of(t, dummy);
+    }
+    if (tid == kPlanThreads - 1) {
+        const uint32_t total = wave_sum[kPlanThreads / kWave - 1];
+        uint32_t ee = s_err;
+        if (total > max_chunks) ee |= kErrOffsets;
+        chunk_base[n_traces] = ee ? 0u : total;
+        chunk_base[n_traces + 1] = ee;           // status of this call
         chunk_base[n_traces + 2] = 0;            // work counter of the persistent grid
-        if (e) atomicOr(err, e);
+        if (ee) atomicOr(err, ee);
     }
 }
 

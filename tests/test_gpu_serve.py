@@ -171,10 +171,12 @@ def test_fleet_flat_out_with_churn_matches_oracle(ctx, oracle_mod):
     assert st["joins_waited"] > 0 and st["max_in_flight"] >= 2
     assert check_fleet(oracle_mod, ev, n_streams, cfg_of_stream, grid, dec) > 300
     # batches larger than the fleet: every node queues several samples, and a
-    # batch takes only the oldest of each (the rest wait for later batches)
+    # batch takes only the oldest of each (the rest wait for later batches).
+    # Which samples are served depends on when leaves free slots, so the two
+    # runs may serve different samples; each must match the oracle on its own.
     dec2, _, st2 = srv.run(ev, n_streams, grid, realtime=False, max_batch=4096, depth=2)
     assert st2["deferred"] > 0
-    assert (dec2 == dec).all()
+    assert check_fleet(oracle_mod, ev, n_streams, cfg_of_stream, grid, dec2) > 300
     assert srv.open_count == 0                 # the runs closed what they opened
     srv.close()
 
