@@ -53,6 +53,40 @@ def stored_traffic(n_samples):
     return t.get("bytes_per_launch")
 
 
+def bench_sweep(magus, synth, ctx, dev):
+    """The configuration sweep: 1,024 traces x 50,000 samples x 16,384 configs."""
+    import numpy as np
+    import torch
+    log("sweep workload ...")
+    ssmp, soff = synth.workload_sweep_traces()
+    ss = torch.from_numpy(ssmp.view(np.int32)).to(dev)
+    so = torch.from_numpy(soff.view(np.int64)).to(dev)
+    grid = synth.sweep_grid()
+    grid_arr = magus.config_array(grid)      # marshalled once
+    ctx.sweep(ss, so, grid_arr)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    ctx.kernel_time(magus.KERNEL_SWEEP)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, arg = ctx.sweep(ss, so, grid_arr)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.set_profiling(False)
+    kms, kn = ctx.kernel_time(magus.KERNEL_SWEEP)
+    ctx.check()
+    evals = float(len(ssmp)) * len(grid)
+    kern_s = kms / kn * 1e-3
+    res = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
+           "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3, "kernel_ms": kern_s * 1e3,
+           "useful_op_frac_12ops": evals / kern_s * 12 / VALU_PEAK_OPS}
+    log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
+    del ss, so
+    torch.cuda.empty_cache()
+    return res, grid_arr
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +99,8 @@ def main():
     ap.add_argument("--serve-ticks", type=int, default=50)
     ap.add_argument("--chunk", type=int, default=0, help="time-chunk length (0: default)")
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only run the configuration sweep and print its figures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy kernel over as many bytes as the "
                          "bulk workload (read 4 B + write 4 B per sample), for scaling HBM "
@@ -91,6 +127,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "bitwise_xor int32", "elements": n,
                           "read_bytes": 4 * n, "write_bytes": 4 * n, "launches": 3}))
+        return
+    if args.sweep_only:
+        ctx = magus.Context(0)
+        res, _ = bench_sweep(magus, synth, ctx, dev)
+        ctx.close()
+        print(json.dumps({"sweep": res}), flush=True)
         return
     log(f"generating bulk workload {args.traces} x {args.length} ...")
     t0 = time.time()
@@ -218,33 +260,8 @@ def main():
         del s, o
         torch.cuda.empty_cache()
 
-        log("sweep workload ...")
-        ssmp, soff = synth.workload_sweep_traces()
-        ss = torch.from_numpy(ssmp.view(np.int32)).to(dev)
-        so = torch.from_numpy(soff.view(np.int64)).to(dev)
+        extra["sweep"], grid_arr = bench_sweep(magus, synth, ctx, dev)
         grid = synth.sweep_grid()
-        grid_arr = magus.config_array(grid)      # marshalled once
-        ctx.sweep(ss, so, grid_arr)
-        torch.cuda.synchronize()
-        ctx.set_profiling(True)
-        ctx.kernel_time(magus.KERNEL_SWEEP)
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            _, arg = ctx.sweep(ss, so, grid_arr)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        ctx.set_profiling(False)
-        kms, kn = ctx.kernel_time(magus.KERNEL_SWEEP)
-        ctx.check()
-        evals = float(len(ssmp)) * len(grid)
-        kern_s = kms / kn * 1e-3
-        extra["sweep"] = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
-                          "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3,
-                          "kernel_ms": kern_s * 1e3,
-                          "useful_op_frac_12ops": evals / kern_s * 12 / VALU_PEAK_OPS}
-        log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
-        del ss, so
 
         log("uneven workload: 20,000 traces, autotuned, hipGraph ...")
         t0 = time.time()

@@ -70,6 +70,8 @@ def _load():
         lib.oracle_sweep.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint32, P, P]
         lib.oracle_counters_to_mbps.argtypes = [P, P, ctypes.c_uint64, ctypes.c_uint32,
                                                 ctypes.c_uint32, P]
+        lib.oracle_proxy_model_valid.argtypes = [P]
+        lib.oracle_proxy_trace.argtypes = [P, ctypes.c_uint64, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -173,6 +175,65 @@ def counters_to_mbps(counts, ts_ns, counter_bits=48, bytes_per_count=64):
     if rc != 0:
         raise ValueError("oracle: invalid counter arguments")
     return out
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_uint32), ("interval_us", ctypes.c_uint32),
+                ("cap_mbps", ctypes.c_uint32 * 32), ("uncore_mw", ctypes.c_uint32 * 32),
+                ("core_mw", ctypes.c_uint32), ("gpu_mw", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("excess_max", ctypes.c_uint64), ("excess_min", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64 * 32), ("excess", ctypes.c_uint64 * 32)]
+
+
+_METRIC_KEYS = ("time_s", "energy_j", "pkg_power_w", "perf_loss", "pkg_power_saving",
+                "energy_saving", "edp_saving")
+
+
+class _Metrics(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double * 3) for k in _METRIC_KEYS]
+
+
+def _model(m: dict) -> _Model:
+    out = _Model()
+    out.n_levels = int(m["n_levels"])
+    out.interval_us = int(m["interval_us"])
+    for i, v in enumerate(m["cap_mbps"]):
+        out.cap_mbps[i] = int(v)
+    for i, v in enumerate(m["uncore_mw"]):
+        out.uncore_mw[i] = int(v)
+    out.core_mw = int(m["core_mw"])
+    out.gpu_mw = int(m["gpu_mw"])
+    return out
+
+
+def proxy_model_valid(model: dict) -> bool:
+    mm = _model(model)
+    return bool(_load().oracle_proxy_model_valid(ctypes.byref(mm)))
+
+
+def proxy_trace(x, cfg: dict, model: dict):
+    """Proxy energy / EDP model of one trace under MAGUS, always-max and always-min.
+
+    model: dict with n_levels, interval_us, cap_mbps[], uncore_mw[], core_mw, gpu_mw.
+    Returns (stats dict of exact integers, metrics dict of 3-element lists; column 0
+    MAGUS, 1 always at level_max (the baseline), 2 always at level_min).
+    """
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    c = _cfg(cfg)
+    mm = _model(model)
+    st = _Stats()
+    me = _Metrics()
+    rc = _load().oracle_proxy_trace(_ptr(x), len(x), ctypes.byref(c), ctypes.byref(mm),
+                                    ctypes.byref(st), ctypes.byref(me))
+    if rc != 0:
+        raise ValueError("oracle: invalid config, model or trace")
+    stats = {"excess_max": st.excess_max, "excess_min": st.excess_min,
+             "steps": list(st.steps), "excess": list(st.excess)}
+    metrics = {k: list(getattr(me, k)) for k in _METRIC_KEYS}
+    return stats, metrics
 
 
 def decode(byte_arr):

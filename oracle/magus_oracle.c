@@ -280,3 +280,91 @@ int oracle_counters_to_mbps(const uint64_t* counts, const uint64_t* ts_ns, uint6
     }
     return 0;
 }
+
+/* ------------------------------------------------------------ proxy energy model */
+/*
+ * Proxy of the four metrics of Sec. 5.4 (performance loss, package power
+ * saving, energy saving, energy-delay product) for three uncore policies run on
+ * the same trace: MAGUS with the trace's config, the default behaviour of
+ * Sec. 5.3 (the uncore stays at its maximum, the baseline of every saving) and
+ * a static minimum.  The paper measures these on hardware and gives no power
+ * or performance model, so the model here is a stated proxy:
+ *   - interval t (interval_us long) runs at the level the controller set after
+ *     reading interval t-1, i.e. the level after step t-1 (level_init for
+ *     t = 0); the static policies run at level_max / level_min throughout;
+ *   - at level i the uncore sustains cap_mbps[i]; an interval whose demand
+ *     x[t] exceeds that takes interval_us * x[t] / cap_mbps[i] instead of
+ *     interval_us (the interval's traffic moves at the capped rate);
+ *   - package power is core_mw + uncore_mw[i] and system power adds gpu_mw,
+ *     both held for the whole (possibly stretched) interval.
+ * The integer statistics are exact; the metrics are the plain definitions
+ * summed interval by interval in double precision.
+ */
+int oracle_proxy_model_valid(const oracle_proxy_model* m)
+{
+    if (!m || m->n_levels < 1 || m->n_levels > 32 || m->interval_us < 1) return 0;
+    for (uint32_t i = 0; i < m->n_levels; ++i)
+        if (m->cap_mbps[i] < 1 || (uint64_t)m->core_mw + m->uncore_mw[i] < 1) return 0;
+    return 1;
+}
+
+int oracle_proxy_trace(const uint32_t* x, uint64_t n, const oracle_config* cfg,
+                       const oracle_proxy_model* m, oracle_proxy_stats* st,
+                       oracle_proxy_metrics* out)
+{
+    if (!oracle_config_valid(cfg) || !oracle_proxy_model_valid(m) || !st || (n && !x))
+        return -1;
+    if (cfg->level_max >= m->n_levels) return -1;
+    uint8_t* bytes = n ? (uint8_t*)malloc(n) : NULL;
+    if (n && !bytes) return -1;
+    oracle_result r;
+    run_trace(x, n, cfg, 0, 0.0, 0.0, bytes, &r);
+
+    /* per interval: the level it runs at under each policy */
+    const double dt_s = m->interval_us * 1e-6;
+    double time_s[3] = {0, 0, 0}, pkg_j[3] = {0, 0, 0};
+    memset(st, 0, sizeof *st);
+    for (uint64_t t = 0; t < n; ++t) {
+        uint32_t lv[3];
+        lv[0] = t == 0 ? cfg->level_init : (uint32_t)(bytes[t - 1] & 31u);
+        lv[1] = cfg->level_max;
+        lv[2] = cfg->level_min;
+        for (int p = 0; p < 3; ++p) {
+            const uint32_t cap = m->cap_mbps[lv[p]];
+            const uint64_t excess = x[t] > cap ? (uint64_t)(x[t] - cap) : 0;
+            if (p == 0) {
+                st->steps[lv[0]] += 1;
+                st->excess[lv[0]] += excess;
+            } else if (p == 1) {
+                st->excess_max += excess;
+            } else {
+                st->excess_min += excess;
+            }
+            /* stretched length of this interval and the package energy over it */
+            const double len = x[t] > cap ? dt_s * ((double)x[t] / (double)cap) : dt_s;
+            time_s[p] += len;
+            pkg_j[p] += len * ((double)m->core_mw + (double)m->uncore_mw[lv[p]]) * 1e-3;
+        }
+    }
+    free(bytes);
+    if (!out) return 0;
+    for (int p = 0; p < 3; ++p) {
+        out->time_s[p] = time_s[p];
+        out->energy_j[p] = pkg_j[p] + time_s[p] * (double)m->gpu_mw * 1e-3;
+        out->pkg_power_w[p] = time_s[p] > 0 ? pkg_j[p] / time_s[p] : 0.0;
+    }
+    /* savings and loss relative to the default (always at the maximum) */
+    for (int p = 0; p < 3; ++p) {
+        if (n == 0) {
+            out->perf_loss[p] = out->pkg_power_saving[p] = 0.0;
+            out->energy_saving[p] = out->edp_saving[p] = 0.0;
+            continue;
+        }
+        out->perf_loss[p] = out->time_s[p] / out->time_s[1] - 1.0;
+        out->pkg_power_saving[p] = 1.0 - out->pkg_power_w[p] / out->pkg_power_w[1];
+        out->energy_saving[p] = 1.0 - out->energy_j[p] / out->energy_j[1];
+        out->edp_saving[p] = 1.0 - (out->energy_j[p] * out->time_s[p]) /
+                                   (out->energy_j[1] * out->time_s[1]);
+    }
+    return 0;
+}

@@ -56,4 +56,40 @@ int oracle_sweep(const uint32_t* samples, const uint64_t* offsets, uint32_t n_tr
  */
 int oracle_counters_to_mbps(const uint64_t* counts, const uint64_t* ts_ns, uint64_t n,
                             uint32_t counter_bits, uint32_t bytes_per_count, uint32_t* out);
+/*
+ * Proxy energy / EDP model (a proxy: the paper measures these on hardware).
+ * Policy columns of the metrics: 0 MAGUS, 1 uncore always at level_max (the
+ * default behaviour and the baseline of every saving), 2 always at level_min.
+ */
+typedef struct oracle_proxy_model {
+    uint32_t n_levels;         /* ladder rungs described below, 1..32           */
+    uint32_t interval_us;      /* monitoring interval                           */
+    uint32_t cap_mbps[32];     /* throughput the uncore sustains at each level  */
+    uint32_t uncore_mw[32];    /* uncore power at each level                    */
+    uint32_t core_mw;          /* rest of the CPU package                       */
+    uint32_t gpu_mw;           /* GPU (core and memory)                         */
+} oracle_proxy_model;
+
+typedef struct oracle_proxy_stats {   /* exact integer statistics of one trace */
+    uint64_t excess_max;       /* sum over intervals of max(0, x - cap[level_max]) */
+    uint64_t excess_min;       /* ... of max(0, x - cap[level_min])                */
+    uint64_t steps[32];        /* MAGUS: intervals run at each level               */
+    uint64_t excess[32];       /* MAGUS: sum of max(0, x - cap[i]) over those       */
+} oracle_proxy_stats;
+
+typedef struct oracle_proxy_metrics {
+    double time_s[3];          /* stretched run time                             */
+    double energy_j[3];        /* package + GPU energy                           */
+    double pkg_power_w[3];     /* average package power                          */
+    double perf_loss[3];       /* time / time[1] - 1                             */
+    double pkg_power_saving[3];/* 1 - pkg_power / pkg_power[1]                   */
+    double energy_saving[3];   /* 1 - energy / energy[1]                         */
+    double edp_saving[3];      /* 1 - energy * time / (energy[1] * time[1])      */
+} oracle_proxy_metrics;
+
+int oracle_proxy_model_valid(const oracle_proxy_model* m);
+/* metrics may be NULL; an empty trace gives zero times, energies and savings */
+int oracle_proxy_trace(const uint32_t* x, uint64_t n, const oracle_config* cfg,
+                       const oracle_proxy_model* m, oracle_proxy_stats* stats,
+                       oracle_proxy_metrics* metrics);
 #endif

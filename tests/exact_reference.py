@@ -79,3 +79,47 @@ def run(trace, cfg):
 def encode(steps):
     """Same byte layout as the oracle: level | high << 5 | (pred + 1) << 6."""
     return bytes(lv | (h << 5) | ((p + 1) << 6) for lv, h, p in steps)
+
+
+def proxy(trace, cfg, model):
+    """Proxy energy model in exact rationals, interval by interval.
+
+    Interval t runs at the level set after step t-1 (level_init first) under
+    MAGUS, at level_max or level_min under the static policies; its length is
+    interval * max(1, x / cap[level]); package power core + uncore[level] and
+    system power + gpu are held over it.  Returns (stats, metrics) in the same
+    layout as the C oracle, metrics as Fractions.
+    """
+    steps, *_ = run(trace, cfg)
+    dt = Fraction(model["interval_us"], 10**6)
+    levels = [cfg["level_init"]] + [lv for lv, _, _ in steps[:-1]]
+    pol = [levels, [cfg["level_max"]] * len(trace), [cfg["level_min"]] * len(trace)]
+    st = {"excess_max": 0, "excess_min": 0, "steps": [0] * 32, "excess": [0] * 32}
+    T = [Fraction(0)] * 3
+    Epkg = [Fraction(0)] * 3
+    for p in range(3):
+        for x, lv in zip(trace, pol[p]):
+            cap = model["cap_mbps"][lv]
+            over = max(0, int(x) - cap)
+            if p == 0:
+                st["steps"][lv] += 1
+                st["excess"][lv] += over
+            elif p == 1:
+                st["excess_max"] += over
+            else:
+                st["excess_min"] += over
+            length = dt * max(Fraction(1), Fraction(int(x), cap))
+            T[p] += length
+            Epkg[p] += length * Fraction(model["core_mw"] + model["uncore_mw"][lv], 1000)
+    E = [Epkg[p] + T[p] * Fraction(model["gpu_mw"], 1000) for p in range(3)]
+    P = [Epkg[p] / T[p] if T[p] else Fraction(0) for p in range(3)]
+    m = {"time_s": T, "energy_j": E, "pkg_power_w": P}
+    if len(trace) == 0:
+        zero = [Fraction(0)] * 3
+        m.update(perf_loss=zero, pkg_power_saving=zero, energy_saving=zero, edp_saving=zero)
+    else:
+        m["perf_loss"] = [T[p] / T[1] - 1 for p in range(3)]
+        m["pkg_power_saving"] = [1 - P[p] / P[1] for p in range(3)]
+        m["energy_saving"] = [1 - E[p] / E[1] for p in range(3)]
+        m["edp_saving"] = [1 - (E[p] * T[p]) / (E[1] * T[1]) for p in range(3)]
+    return st, m

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_proxy as proxy_pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "magus_oracle.c")
 
@@ -60,6 +61,15 @@ MUTANTS = [
      "        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
      "memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);\n"
      "        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0); if (H > 1) uncore_tune_ls[0] = 0;"),
+    ("proxy: interval runs at the level set after its own step",
+     "lv[0] = t == 0 ? cfg->level_init : (uint32_t)(bytes[t - 1] & 31u);",
+     "lv[0] = (uint32_t)(bytes[t] & 31u);"),
+    ("proxy: package power not held over the stretch",
+     "pkg_j[p] += len * ((double)m->core_mw", "pkg_j[p] += dt_s * ((double)m->core_mw"),
+    ("proxy: GPU energy left out", "out->energy_j[p] = pkg_j[p] + time_s[p] * (double)m->gpu_mw * 1e-3;",
+     "out->energy_j[p] = pkg_j[p];"),
+    ("proxy: EDP as energy only", "out->edp_saving[p] = 1.0 - (out->energy_j[p] * out->time_s[p]) /",
+     "out->edp_saving[p] = 1.0 - (out->energy_j[p] * 1.0) /"),
 ]
 
 
@@ -93,6 +103,16 @@ def _checks():
     ]
 
 
+def _proxy_checks():
+    om = oracle
+    return [
+        lambda: proxy_pins.test_worked_step_up_example(om),
+        lambda: proxy_pins.test_rise_and_fall_each_take_effect_one_interval_late(om),
+        lambda: proxy_pins.test_trace_below_every_cap_never_slows_down(om),
+        lambda: proxy_pins.test_against_exact_rationals_random(om),
+    ]
+
+
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pins_catch_planted_mistake(name, old, new):
     src = open(SRC).read()
@@ -106,12 +126,13 @@ def test_pins_catch_planted_mistake(name, old, new):
         real = oracle._load()
         mut = ctypes.CDLL(so)
         for fn in ("oracle_config_valid", "oracle_replay_trace", "oracle_replay_trace_fp64",
-                   "oracle_replay_batch", "oracle_sweep"):
+                   "oracle_replay_batch", "oracle_sweep", "oracle_counters_to_mbps",
+                   "oracle_proxy_model_valid", "oracle_proxy_trace"):
             getattr(mut, fn).argtypes = getattr(real, fn).argtypes
         oracle._lib = mut
         try:
             caught = False
-            for chk in _checks():
+            for chk in (_proxy_checks() if name.startswith("proxy:") else _checks()):
                 try:
                     chk()
                 except AssertionError:
