@@ -249,6 +249,72 @@ int magus_counters_to_mbps(magus_ctx* ctx, const uint64_t* d_counts, const uint6
                            uint32_t* d_samples, hipStream_t stream);
 
 /*
+ * Proxy energy / EDP model over replays.  Sec. 5.4 judges an uncore policy by
+ * performance loss, package power saving, energy saving (CPU package + GPU)
+ * and energy-delay product, each against the default of Sec. 5.3, where the
+ * uncore stays at its maximum.  The paper measures these on hardware and gives
+ * no model; this call evaluates a stated proxy of them for three policies on
+ * every trace: MAGUS with the trace's config (column 0), always at level_max
+ * (column 1, the baseline) and always at level_min (column 2).
+ *   - Interval t of a trace runs at the level set after step t-1
+ *     (level_init for t = 0): a decision takes effect on the next interval.
+ *   - At level i the uncore sustains cap_mbps[i]; an interval whose sample x
+ *     exceeds it lasts interval_us * x / cap_mbps[i] instead of interval_us.
+ *   - Package power core_mw + uncore_mw[i] and GPU power gpu_mw are held for
+ *     the whole (stretched) interval.
+ * magus_proxy_stats holds the exact integer statistics the metrics are made
+ * from; magus_proxy_metrics the seven figures per policy in double precision
+ * (all zero for an empty trace).
+ */
+#define MAGUS_PROXY_LEVELS 32
+typedef struct magus_proxy_model {
+    uint32_t n_levels;                       /* rungs described, 1..32; every   */
+                                             /* config needs level_max < this   */
+    uint32_t interval_us;                    /* >= 1                            */
+    uint32_t cap_mbps[MAGUS_PROXY_LEVELS];   /* >= 1 for the described rungs    */
+    uint32_t uncore_mw[MAGUS_PROXY_LEVELS];
+    uint32_t core_mw;                        /* core_mw + uncore_mw[i] >= 1     */
+    uint32_t gpu_mw;
+} magus_proxy_model;
+
+typedef struct magus_proxy_stats {
+    uint64_t excess_max;                     /* sum of max(0, x - cap[level_max]) */
+    uint64_t excess_min;                     /* sum of max(0, x - cap[level_min]) */
+    uint64_t steps[MAGUS_PROXY_LEVELS];      /* MAGUS: intervals run at level i  */
+    uint64_t excess[MAGUS_PROXY_LEVELS];     /* MAGUS: sum of max(0, x - cap[i]) */
+                                             /* over those intervals             */
+} magus_proxy_stats;
+
+typedef struct magus_proxy_metrics {         /* [policy]: 0 MAGUS, 1 max, 2 min  */
+    double time_s[3];                        /* stretched run time               */
+    double energy_j[3];                      /* package + GPU energy             */
+    double pkg_power_w[3];                   /* average package power            */
+    double perf_loss[3];                     /* time / time[1] - 1               */
+    double pkg_power_saving[3];              /* 1 - pkg_power / pkg_power[1]     */
+    double energy_saving[3];                 /* 1 - energy / energy[1]           */
+    double edp_saving[3];                    /* 1 - energy*time / (energy*time)[1] */
+} magus_proxy_metrics;
+
+/* MAGUS_OK if the model is valid (as required by magus_proxy), else MAGUS_EINVAL
+ * with the reason in magus_last_error().  Host only. */
+int magus_proxy_model_check(const magus_proxy_model* model);
+
+/*
+ * Runs the replay of magus_replay (same sample, offset and config rules; the
+ * per-step levels go to a context-owned buffer of n_samples bytes) and then
+ * the proxy for every trace.
+ *   h_model    the proxy model (host memory, read before return); an invalid
+ *              model, or a config with level_max >= n_levels, is MAGUS_EINVAL.
+ *   d_stats    n_traces magus_proxy_stats (written).
+ *   d_metrics  NULL or n_traces magus_proxy_metrics (written).
+ */
+int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                const uint64_t* d_offsets, uint32_t n_traces,
+                const magus_config* h_cfgs, uint32_t n_cfgs, const uint32_t* d_cfg_of_trace,
+                const magus_proxy_model* h_model, magus_proxy_stats* d_stats,
+                magus_proxy_metrics* d_metrics, hipStream_t stream);
+
+/*
  * Serving: a pool of slots, one per live telemetry stream, whose controller
  * state stays in device memory between steps.
  *   magus_server_create   capacity = as many slots as `mem_budget_bytes` of

@@ -59,11 +59,37 @@ class MagusTuneResult(ctypes.Structure):
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
+PROXY_LEVELS = 32
+
+
+class MagusProxyModel(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_uint32), ("interval_us", ctypes.c_uint32),
+                ("cap_mbps", ctypes.c_uint32 * PROXY_LEVELS),
+                ("uncore_mw", ctypes.c_uint32 * PROXY_LEVELS),
+                ("core_mw", ctypes.c_uint32), ("gpu_mw", ctypes.c_uint32)]
+
+
+class MagusProxyStats(ctypes.Structure):
+    _fields_ = [("excess_max", ctypes.c_uint64), ("excess_min", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64 * PROXY_LEVELS),
+                ("excess", ctypes.c_uint64 * PROXY_LEVELS)]
+
+
+PROXY_METRIC_KEYS = ("time_s", "energy_j", "pkg_power_w", "perf_loss", "pkg_power_saving",
+                     "energy_saving", "edp_saving")
+
+
+class MagusProxyMetrics(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double * 3) for k in PROXY_METRIC_KEYS]
+
+
 EV_SAMPLE, EV_JOIN, EV_LEAVE = 0, 1, 2
 EVENT_DTYPE = np.dtype([("t_ns", "<u8"), ("kind", "<u4"), ("stream", "<u4"),
                         ("value", "<u4"), ("reserved", "<u4")])
 
 assert ctypes.sizeof(MagusConfig) == 20 and ctypes.sizeof(MagusResult) == 32
+assert ctypes.sizeof(MagusProxyModel) == 272 and ctypes.sizeof(MagusProxyStats) == 528
+assert ctypes.sizeof(MagusProxyMetrics) == 168
 assert EVENT_DTYPE.itemsize == 24
 
 _lib = None
@@ -94,6 +120,10 @@ SIGNATURES = {
                                    ctypes.c_uint32, _P, _P, _P]),
     "magus_counters_to_mbps": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint32,
                                               ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
+    "magus_proxy_model_check": (ctypes.c_int, [ctypes.POINTER(MagusProxyModel)]),
+    "magus_proxy": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
+                                   ctypes.c_uint32, _P, ctypes.POINTER(MagusProxyModel), _P, _P,
+                                   _P]),
     "magus_server_slot_bytes": (ctypes.c_size_t, []),
     "magus_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(_P)]),
     "magus_server_destroy": (ctypes.c_int, [_P]),
@@ -175,6 +205,40 @@ def _stream_handle(stream, device):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream(device)
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_proxy_model(d: dict) -> MagusProxyModel:
+    """Proxy model from a dict: n_levels, interval_us, cap_mbps[], uncore_mw[],
+    core_mw, gpu_mw (see include/magus.h)."""
+    m = MagusProxyModel()
+    m.n_levels = int(d["n_levels"])
+    m.interval_us = int(d["interval_us"])
+    for i, v in enumerate(d["cap_mbps"]):
+        m.cap_mbps[i] = int(v)
+    for i, v in enumerate(d["uncore_mw"]):
+        m.uncore_mw[i] = int(v)
+    m.core_mw = int(d["core_mw"])
+    m.gpu_mw = int(d["gpu_mw"])
+    return m
+
+
+def proxy_model_check(d) -> None:
+    """Raise MagusError(EINVAL) unless the proxy model is valid (host only)."""
+    mm = d if isinstance(d, MagusProxyModel) else make_proxy_model(d)
+    _check(load().magus_proxy_model_check(ctypes.byref(mm)))
+
+
+def proxy_stats_dict(row) -> dict:
+    """One row of the int64[T, 66] stats tensor returned by Context.proxy."""
+    v = [int(x) & 0xFFFFFFFFFFFFFFFF for x in row]
+    return {"excess_max": v[0], "excess_min": v[1], "steps": v[2:2 + PROXY_LEVELS],
+            "excess": v[2 + PROXY_LEVELS:2 + 2 * PROXY_LEVELS]}
+
+
+def proxy_metrics_dict(row) -> dict:
+    """One row of the float64[T, 21] metrics tensor returned by Context.proxy."""
+    v = [float(x) for x in row]
+    return {k: v[3 * i:3 * i + 3] for i, k in enumerate(PROXY_METRIC_KEYS)}
 
 
 class Context:
@@ -274,6 +338,34 @@ class Context:
         _check(load().magus_replay(self._h, sp, samples.numel(), op, n_traces, arr, len(arr),
                                    cp, rp, lp, _stream_handle(stream, self.device)))
         return results, (levels_out if levels else None)
+
+    def proxy(self, samples, offsets, cfgs, model, cfg_of_trace=None, metrics: bool = True,
+              stream=None):
+        """Proxy energy / EDP model of MAGUS vs always-max vs always-min per trace.
+
+        Returns (stats int64[T, 66], metrics float64[T, 21] or None); decode rows
+        with proxy_stats_dict / proxy_metrics_dict.
+        """
+        torch = _torch()
+        arr = config_array(cfgs)
+        mm = model if isinstance(model, MagusProxyModel) else make_proxy_model(model)
+        sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
+        op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
+        n_traces = offsets.numel() - 1
+        st = torch.empty((n_traces, 2 + 2 * PROXY_LEVELS), dtype=torch.int64,
+                         device=samples.device)
+        me = None
+        mp = None
+        if metrics:
+            me = torch.empty((n_traces, 21), dtype=torch.float64, device=samples.device)
+            mp = _dev_ptr(me, "metrics", (torch.float64,))
+        cp = None
+        if cfg_of_trace is not None:
+            cp = _dev_ptr(cfg_of_trace, "cfg_of_trace", (torch.int32, torch.uint32))
+        _check(load().magus_proxy(self._h, sp, samples.numel(), op, n_traces, arr, len(arr),
+                                  cp, ctypes.byref(mm), _dev_ptr(st, "stats", (torch.int64,)),
+                                  mp, _stream_handle(stream, self.device)))
+        return st, me
 
     def counters_to_mbps(self, counts, ts_ns, offsets, counter_bits: int = 48,
                          bytes_per_count: int = 64, stream=None):

@@ -5,6 +5,7 @@
 // kernels of replay.hip, sweep.hip and serve.hip on the caller's stream.
 
 #include "host_internal.h"
+#include "proxy_internal.h"
 
 using namespace magus;
 
@@ -406,6 +407,63 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     if (tp.first) HIP_TRY(hipEventRecord(tp.first, stream));
     HIP_TRY(hipGraphLaunch(exec, stream));
     if (tp.second) HIP_TRY(hipEventRecord(tp.second, stream));
+    return MAGUS_OK;
+}
+
+int magus_proxy_model_check(const magus_proxy_model* model) {
+    if (!model) return fail(MAGUS_EINVAL, "model is NULL");
+    const magus_proxy_model& m = *model;
+    if (m.n_levels < 1 || m.n_levels > MAGUS_PROXY_LEVELS)
+        return fail(MAGUS_EINVAL, "model n_levels %u outside 1..%d", m.n_levels,
+                    MAGUS_PROXY_LEVELS);
+    if (m.interval_us < 1) return fail(MAGUS_EINVAL, "model interval_us must be >= 1");
+    for (uint32_t i = 0; i < m.n_levels; ++i) {
+        if (m.cap_mbps[i] < 1) return fail(MAGUS_EINVAL, "model cap_mbps[%u] must be >= 1", i);
+        if ((uint64_t)m.core_mw + m.uncore_mw[i] < 1)
+            return fail(MAGUS_EINVAL, "model package power at level %u is 0", i);
+    }
+    return MAGUS_OK;
+}
+
+int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                const uint64_t* d_offsets, uint32_t n_traces, const magus_config* h_cfgs,
+                uint32_t n_cfgs, const uint32_t* d_cfg_of_trace,
+                const magus_proxy_model* h_model, magus_proxy_stats* d_stats,
+                magus_proxy_metrics* d_metrics, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    int rc = magus_proxy_model_check(h_model);
+    if (rc != MAGUS_OK) return rc;
+    const magus_proxy_model& m = *h_model;
+    if (!h_cfgs || n_cfgs == 0) return fail(MAGUS_EINVAL, "need at least one config");
+    for (uint32_t i = 0; i < n_cfgs; ++i)
+        if (h_cfgs[i].level_max >= m.n_levels)
+            return fail(MAGUS_EINVAL, "config %u: level_max %u not described by the model "
+                        "(%u levels)", i, (unsigned)h_cfgs[i].level_max, m.n_levels);
+    if (n_traces && !d_stats) return fail(MAGUS_EINVAL, "stats is NULL");
+    if (n_traces == 0) return magus_replay(ctx, d_samples, n_samples, d_offsets, 0, h_cfgs,
+                                           n_cfgs, d_cfg_of_trace, nullptr, nullptr, stream);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    if ((rc = ctx->proxy_levels.ensure(std::max<uint64_t>(n_samples, 1))) ||
+        (rc = ctx->proxy_results.ensure((size_t)n_traces * sizeof(magus_result))) ||
+        (rc = ctx->proxy_model.ensure(sizeof(magus_proxy_model))))
+        return rc;
+    if ((rc = magus_replay(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
+                           d_cfg_of_trace, ctx->proxy_results.as<magus_result>(),
+                           ctx->proxy_levels.as<uint8_t>(), stream)))
+        return rc;
+    if (!ctx->proxy_model_set ||
+        std::memcmp(&ctx->proxy_model_host, &m, sizeof m) != 0) {
+        ctx->proxy_model_host = m;
+        HIP_TRY(hipMemcpyAsync(ctx->proxy_model.p, &ctx->proxy_model_host, sizeof m,
+                               hipMemcpyHostToDevice, stream));
+        ctx->proxy_model_set = true;
+    }
+    const uint32_t max_chunks = (uint32_t)(n_samples / ctx->chunk + n_traces + 1);
+    HIP_TRY(launch_proxy(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
+                         max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
+                         ctx->proxy_levels.as<uint8_t>(),
+                         ctx->proxy_model.as<magus_proxy_model>(), d_stats, d_metrics, stream));
     return MAGUS_OK;
 }
 

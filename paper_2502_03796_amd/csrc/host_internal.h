@@ -72,6 +72,11 @@ struct magus_ctx {
     magus::DevBuf sweep_tab;    // sweep: lane tables
     std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
     magus::SweepPlan plan{};
+    magus::DevBuf proxy_levels;   // proxy: decision bytes of the replay
+    magus::DevBuf proxy_results;  // proxy: replay results (not returned)
+    magus::DevBuf proxy_model;    // proxy: the model in device memory
+    magus_proxy_model proxy_model_host{};   // ... as last uploaded
+    bool proxy_model_set = false;
     // launch shape of the replay chunk kernel (0 = one wave per chunk)
     uint32_t persistent_blocks = 0;
     // hipGraph cache of replay calls

@@ -1,0 +1,228 @@
+// Proxy energy / EDP model over replays on gfx950.
+//
+// Sec. 5.4 judges an uncore policy by performance loss, package power saving,
+// energy saving and EDP against the default of Sec. 5.3 (uncore at its
+// maximum).  With no power or performance model in the paper, this file
+// evaluates a stated proxy from the per-step levels of a replay:
+//   - interval t runs at the level set after step t-1 (level_init for t = 0);
+//   - at level i the uncore sustains cap[i] MB/s and an interval whose sample x
+//     exceeds that is stretched to interval * x / cap[i];
+//   - package power core + uncore[i] and GPU power are held over the interval.
+// Everything the metrics need is a handful of exact integer sums per trace:
+// per level, the intervals run there and the sum of max(0, x - cap[level]);
+// for the two static policies the same excess sums at level_max / level_min.
+//
+// Kernels, in stream order (after the replay that wrote the decision bytes):
+//   zero     clears the statistics (no memset node, so the sequence can be
+//            captured into a graph)
+//   stats    one wave per replay chunk, HBM-bound: reads 4 B of sample and
+//            1 B of decision per step, integer sums in registers (levels
+//            strictly between the bounds: lane l keeps level l's sums), one
+//            atomic add per non-zero sum per chunk
+//   metrics  one thread per trace: the seven figures of each policy in FP64
+
+#include "proxy_internal.h"
+
+namespace magus {
+namespace {
+
+static_assert(sizeof(magus_proxy_model) == 8 + 4 * 64 + 8, "magus_proxy_model layout");
+static_assert(sizeof(magus_proxy_stats) == 16 + 8 * 64, "magus_proxy_stats layout");
+static_assert(sizeof(magus_proxy_metrics) == 7 * 3 * 8, "magus_proxy_metrics layout");
+
+constexpr int kStatsWaves = 4;
+constexpr uint32_t kUnroll = 4;        // steps per lane in flight
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t over(uint32_t x, uint32_t cap) { return x > cap ? x - cap : 0u; }
+
+__global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// One wave per chunk of the replay that produced `levels` (same chunk plan).
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, const uint8_t* __restrict__ levels,
+    const magus_proxy_model* __restrict__ model, magus_proxy_stats* __restrict__ stats)
+{
+    __shared__ uint32_t s_cap[MAGUS_PROXY_LEVELS];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x < MAGUS_PROXY_LEVELS) s_cap[threadIdx.x] = model->cap_mbps[threadIdx.x];
+    __syncthreads();
+    if (chunk_base[n_traces + 1] != 0) return;            // the replay rejected the batch
+    const uint32_t g = blockIdx.x * kStatsWaves + uniform(wv);
+    if (g >= chunk_base[n_traces]) return;
+
+    // trace of this chunk: the last t with chunk_base[t] <= g
+    uint32_t lo = 0, hi = n_traces;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (chunk_base[mid] <= g) lo = mid; else hi = mid;
+    }
+    const uint32_t t = lo;
+    const uint64_t tbase = offsets[t];
+    const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
+    const uint32_t s = (g - chunk_base[t]) * chunk;
+    const uint32_t e = min(s + chunk, n);
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    const uint32_t lmin = c.lmin, lmax = c.lmax;
+    const uint32_t cap_lo = s_cap[lmin], cap_hi = s_cap[lmax];
+    const uint32_t* x_t = samples + tbase;
+    const uint8_t* lv_t = levels + tbase;
+
+    uint64_t n_lo = 0, n_hi = 0, x_lo = 0, x_hi = 0, ex_max = 0, ex_min = 0;
+    uint64_t bin_n = 0, bin_x = 0;      // lane l: level l strictly inside the bounds
+    for (uint32_t base = s; base < e; base += 64 * kUnroll) {
+        uint32_t xs[kUnroll], ls[kUnroll];
+#pragma unroll
+        for (uint32_t k = 0; k < kUnroll; ++k) {
+            const uint32_t i = base + k * 64 + lane;
+            xs[k] = i < e ? x_t[i] : 0u;
+            ls[k] = i < e ? (i == 0 ? c.linit : (uint32_t)(lv_t[i - 1] & 31u)) : lmin;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kUnroll; ++k) {
+            const uint32_t i = base + k * 64 + lane;
+            const bool live = i < e;
+            const uint32_t x = xs[k], l = ls[k];
+            const uint32_t o_hi = over(x, cap_hi), o_lo = over(x, cap_lo);
+            const bool at_lo = live && l == lmin, at_hi = live && l == lmax;
+            n_lo += at_lo;
+            n_hi += at_hi;
+            x_lo += at_lo ? o_lo : 0u;
+            x_hi += at_hi ? o_hi : 0u;
+            ex_max += o_hi;                   // 0 for lanes past the end (x = 0)
+            ex_min += o_lo;
+            // levels strictly between the bounds (stepped actuation, or an
+            // initial level inside the range): one pass per distinct level
+            uint64_t other = __ballot(live && !at_lo && !at_hi);
+            while (other) {
+                const uint32_t l0 = uniform(__shfl(l, (int)__builtin_ctzll(other), 64));
+                const bool mine = live && l == l0;
+                const uint64_t m = __ballot(mine);
+                const uint64_t sx = wave_sum(mine ? over(x, s_cap[l0]) : 0u);
+                if (lane == l0) {
+                    bin_n += (uint64_t)__builtin_popcountll(m);
+                    bin_x += sx;
+                }
+                other &= ~m;
+            }
+        }
+    }
+    n_lo = wave_sum(n_lo);
+    n_hi = wave_sum(n_hi);
+    x_lo = wave_sum(x_lo);
+    x_hi = wave_sum(x_hi);
+    ex_max = wave_sum(ex_max);
+    ex_min = wave_sum(ex_min);
+    magus_proxy_stats* st = stats + t;
+    if (lane == 0) {
+        unsigned long long* p = reinterpret_cast<unsigned long long*>(st);
+        if (ex_max) atomicAdd(p + 0, (unsigned long long)ex_max);
+        if (ex_min) atomicAdd(p + 1, (unsigned long long)ex_min);
+        if (n_lo) atomicAdd(p + 2 + lmin, (unsigned long long)n_lo);
+        if (n_hi) atomicAdd(p + 2 + lmax, (unsigned long long)n_hi);
+        if (x_lo) atomicAdd(p + 2 + MAGUS_PROXY_LEVELS + lmin, (unsigned long long)x_lo);
+        if (x_hi) atomicAdd(p + 2 + MAGUS_PROXY_LEVELS + lmax, (unsigned long long)x_hi);
+    }
+    if (lane < MAGUS_PROXY_LEVELS) {
+        unsigned long long* p = reinterpret_cast<unsigned long long*>(st);
+        if (bin_n) atomicAdd(p + 2 + lane, (unsigned long long)bin_n);
+        if (bin_x) atomicAdd(p + 2 + MAGUS_PROXY_LEVELS + lane, (unsigned long long)bin_x);
+    }
+}
+
+// Stretched length of `steps` intervals of which the samples exceed `cap` by
+// `excess` in total, in units of one interval.
+__device__ __forceinline__ double stretched(uint64_t steps, uint64_t excess, uint32_t cap) {
+    return (double)steps + (double)excess / (double)cap;
+}
+
+__global__ __launch_bounds__(256) void proxy_metrics_kernel(
+    const uint64_t* __restrict__ offsets, uint32_t n_traces,
+    const uint32_t* __restrict__ chunk_base, const DevCfg* __restrict__ cfgs,
+    const uint32_t* __restrict__ cfg_of_trace, const magus_proxy_model* __restrict__ model,
+    const magus_proxy_stats* __restrict__ stats, magus_proxy_metrics* __restrict__ out)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    const magus_proxy_stats& st = stats[t];
+    const uint64_t n = offsets[t + 1] - offsets[t];
+    const double dt = (double)model->interval_us * 1e-6;
+    const double core = (double)model->core_mw, gpu = (double)model->gpu_mw * 1e-3;
+    double T[3], P[3];                       // intervals (stretched), package energy
+    T[0] = 0.0;
+    P[0] = 0.0;
+    for (uint32_t l = 0; l < model->n_levels; ++l) {
+        if (!st.steps[l]) continue;
+        const double len = stretched(st.steps[l], st.excess[l], model->cap_mbps[l]);
+        T[0] += len;
+        P[0] += len * (core + (double)model->uncore_mw[l]);
+    }
+    T[1] = stretched(n, st.excess_max, model->cap_mbps[c.lmax]);
+    P[1] = T[1] * (core + (double)model->uncore_mw[c.lmax]);
+    T[2] = stretched(n, st.excess_min, model->cap_mbps[c.lmin]);
+    P[2] = T[2] * (core + (double)model->uncore_mw[c.lmin]);
+    magus_proxy_metrics r;
+    for (int p = 0; p < 3; ++p) {
+        r.time_s[p] = T[p] * dt;
+        const double pkg_j = P[p] * dt * 1e-3;
+        r.energy_j[p] = pkg_j + r.time_s[p] * gpu;
+        r.pkg_power_w[p] = n ? pkg_j / r.time_s[p] : 0.0;
+    }
+    for (int p = 0; p < 3; ++p) {
+        if (n == 0) {
+            r.perf_loss[p] = r.pkg_power_saving[p] = r.energy_saving[p] = r.edp_saving[p] = 0.0;
+            continue;
+        }
+        r.perf_loss[p] = r.time_s[p] / r.time_s[1] - 1.0;
+        r.pkg_power_saving[p] = 1.0 - r.pkg_power_w[p] / r.pkg_power_w[1];
+        r.energy_saving[p] = 1.0 - r.energy_j[p] / r.energy_j[1];
+        r.edp_saving[p] = 1.0 - (r.energy_j[p] * r.time_s[p]) / (r.energy_j[1] * r.time_s[1]);
+    }
+    out[t] = r;
+}
+
+}  // namespace
+
+hipError_t launch_proxy(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                        const uint32_t* chunk_base, uint32_t max_chunks, const DevCfg* cfgs,
+                        const uint32_t* cfg_of_trace, uint32_t chunk, const uint8_t* levels,
+                        const magus_proxy_model* model, magus_proxy_stats* stats,
+                        magus_proxy_metrics* metrics, hipStream_t stream)
+{
+    if (n_traces == 0) return hipSuccess;
+    const uint64_t words = (uint64_t)n_traces * (sizeof(magus_proxy_stats) / 8);
+    proxy_zero_kernel<<<(uint32_t)std::min<uint64_t>((words + 255) / 256, 4096), 256, 0, stream>>>(
+        reinterpret_cast<uint64_t*>(stats), words);
+    const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
+    if (blocks)
+        proxy_stats_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
+            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, levels, model,
+            stats);
+    if (metrics)
+        proxy_metrics_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
+            offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);
+    return hipGetLastError();
+}
+
+}  // namespace magus

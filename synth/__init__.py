@@ -14,6 +14,7 @@ from .traces import (four_phase_trace, geometric_phase_trace, make_batch,
                      workload_small, workload_bulk, workload_sweep_traces,
                      workload_uneven, serve_stream_samples, serve_schedule,
                      serve_fleet_events, EVENT_DTYPE, EV_SAMPLE, EV_JOIN, EV_LEAVE)
+from .proxy import proxy_model, LADDER_MHZ
 from .grid import (default_config, THRESHOLD_TABLE_Q16, threshold_q16, sweep_grid,
                    sweep_config, config_index)
 
@@ -24,5 +25,5 @@ __all__ = [
     "serve_stream_samples", "serve_schedule", "serve_fleet_events", "EVENT_DTYPE",
     "EV_SAMPLE", "EV_JOIN", "EV_LEAVE",
     "default_config", "THRESHOLD_TABLE_Q16", "threshold_q16", "sweep_grid",
-    "sweep_config", "config_index",
+    "sweep_config", "config_index", "proxy_model", "LADDER_MHZ",
 ]

@@ -64,3 +64,31 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.magus_server_create(None, 1 << 20, None) == magus.EINVAL
     assert lib.magus_ctx_set_chunk(None, 64) == magus.EINVAL
     assert lib.magus_server_slot_bytes() == 192
+
+
+def test_proxy_struct_layouts_match_header():
+    text = open(HEADER).read()
+    for cname, pyt, size in (("magus_proxy_model", magus.MagusProxyModel, 272),
+                             ("magus_proxy_stats", magus.MagusProxyStats, 528),
+                             ("magus_proxy_metrics", magus.MagusProxyMetrics, 168)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), text, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = re.findall(r"(?:u?int\d+_t|double)\s+(\w+)", body)
+        assert names == [f[0] for f in pyt._fields_], cname
+        assert ctypes.sizeof(pyt) == size
+
+
+def test_proxy_model_validation_on_host():
+    from synth import proxy_model
+    good = proxy_model()
+    magus.proxy_model_check(good)
+    for bad in (dict(n_levels=0), dict(n_levels=33), dict(interval_us=0),
+                dict(cap_mbps=[0] + good["cap_mbps"][1:]),
+                dict(core_mw=0, uncore_mw=[0] * 17)):
+        with pytest.raises(magus.MagusError) as ei:
+            magus.proxy_model_check(dict(good, **bad))
+        assert ei.value.code == magus.EINVAL
+    lib = magus.load()
+    assert lib.magus_proxy_model_check(None) == magus.EINVAL
+    assert lib.magus_proxy(None, None, 0, None, 0, None, 0, None, None, None, None, None) == \
+        magus.EINVAL

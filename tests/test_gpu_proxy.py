@@ -1,0 +1,161 @@
+"""GPU parity of the proxy energy / EDP model (magus_proxy) against the oracle.
+
+The integer statistics (intervals per level, excess sums) must be identical;
+the FP64 metrics are compared within a tolerance derived from the rounding of
+the two evaluation orders: the oracle sums up to ~10^5 interval lengths one by
+one (relative error below n * 2^-53 ~ 1.1e-11 for n = 10^5), the kernel adds at
+most 32 per-level terms of exact integer sums; savings are differences of
+ratios near 1, so their absolute error is below ~4e-11.  Tolerance: relative
+1e-9 for times, energies and powers, absolute 1e-9 for the four fractions.
+"""
+import numpy as np
+import pytest
+
+import paper_2502_03796_amd as magus
+import synth
+from synth import default_config, proxy_model
+from tests.gpu_util import to_dev
+from tests.test_gpu_replay import mixed_traces, LENGTHS
+from tests.test_gpu_stepped import stepped_configs
+
+pytestmark = pytest.mark.gpu
+
+FRACTIONS = ("perf_loss", "pkg_power_saving", "energy_saving", "edp_saving")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = magus.Context(0)
+    yield c
+    c.close()
+
+
+def check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me, traces=None):
+    st = st.cpu().numpy()
+    me = me.cpu().numpy() if me is not None else None
+    n = len(offsets) - 1
+    for t in (range(n) if traces is None else traces):
+        x = samples[int(offsets[t]):int(offsets[t + 1])]
+        cfg = cfgs[int(cot[t])] if cot is not None else cfgs[0]
+        want_st, want_me = oracle_mod.proxy_trace(x, cfg, model)
+        got_st = magus.proxy_stats_dict(st[t])
+        assert got_st == want_st, f"trace {t} (length {len(x)}): stats differ"
+        if me is None:
+            continue
+        got_me = magus.proxy_metrics_dict(me[t])
+        for k in magus.PROXY_METRIC_KEYS:
+            for p in range(3):
+                if k in FRACTIONS:
+                    assert abs(got_me[k][p] - want_me[k][p]) <= 1e-9, (t, k, p)
+                else:
+                    assert got_me[k][p] == pytest.approx(want_me[k][p], rel=1e-9, abs=1e-300), \
+                        (t, k, p)
+
+
+def test_worked_examples_on_gpu(ctx, oracle_mod):
+    """The hand-worked traces of the oracle's pins, through the C ABI."""
+    model = dict(n_levels=17, interval_us=100000, cap_mbps=[15000] + [40000] * 16,
+                 uncore_mw=[10000] + [20000] * 15 + [30000], core_mw=50000, gpu_mw=200000)
+    traces = [np.array([10000] * 40 + [20000] * 60, np.uint32),
+              np.array([10000] * 10 + [30000] * 20 + [10000] * 20, np.uint32),
+              np.full(300, 14999, np.uint32), np.zeros(0, np.uint32)]
+    samples, offsets = synth.make_batch(traces)
+    s, o, _ = to_dev(samples, offsets)
+    st, me = ctx.proxy(s, o, [default_config()], model)
+    ctx.check()
+    got = [magus.proxy_stats_dict(r) for r in st.cpu().numpy()]
+    assert got[0]["steps"][0] == 41 and got[0]["steps"][16] == 59 and got[0]["excess"][0] == 5000
+    assert got[1]["steps"][0] == 30 and got[1]["steps"][16] == 20 and got[1]["excess"][0] == 15000
+    m0 = magus.proxy_metrics_dict(me.cpu().numpy()[0])
+    assert m0["time_s"][0] == pytest.approx(10 + 0.1 / 3, rel=1e-13)
+    assert m0["energy_j"][1] == pytest.approx(2800.0, rel=1e-13)
+    m3 = magus.proxy_metrics_dict(me.cpu().numpy()[3])
+    assert all(v == [0.0, 0.0, 0.0] for v in m3.values())
+    check_against_oracle(oracle_mod, samples, offsets, [default_config()], None, model, st, me)
+
+
+@pytest.mark.parametrize("chunk", [64, 192, 4096, 0])
+def test_mixed_traces_grid_configs(ctx, oracle_mod, chunk):
+    """Every length class across chunk boundaries, a grid config per trace."""
+    traces = mixed_traces(900 + chunk, LENGTHS)
+    grid = synth.sweep_grid()
+    rng = np.random.default_rng(chunk)
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), 30)] + [default_config()]
+    cot = rng.integers(0, len(cfgs), len(traces)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    model = proxy_model()
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, cfgs, model, c)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
+
+
+@pytest.mark.parametrize("chunk", [64, 4096])
+def test_stepped_configs_and_inner_levels(ctx, oracle_mod, chunk):
+    """Stepped actuation visits every rung; initial levels inside the range."""
+    traces = mixed_traces(1300 + chunk, LENGTHS)
+    cfgs = stepped_configs(chunk + 5, 20) + [default_config(level_init=7),
+                                             default_config(up_step=1, down_step=2)]
+    cot = (np.arange(len(traces)) % len(cfgs)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    rng = np.random.default_rng(chunk)
+    model = dict(n_levels=20, interval_us=int(rng.integers(1, 10**6)),
+                 cap_mbps=[int(v) for v in rng.integers(1000, 150000, 32)],
+                 uncore_mw=[int(v) for v in rng.integers(0, 50000, 32)],
+                 core_mw=30000, gpu_mw=300000)
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, cfgs, model, c)
+        ctx.check()
+        st2, _ = ctx.proxy(s, o, cfgs, model, c, metrics=False)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
+    assert (st.cpu().numpy() == st2.cpu().numpy()).all()
+
+
+def test_full_range_samples(ctx, oracle_mod):
+    rng = np.random.default_rng(99)
+    traces = [rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+              for n in (1, 5, 300, 5000)]
+    traces.append(np.array([0, 2**32 - 1] * 200, np.uint32))
+    cfg = default_config(window=2, hold=3, level_max=31)
+    model = dict(n_levels=32, interval_us=2**20, cap_mbps=[1] * 31 + [2**32 - 1],
+                 uncore_mw=[2**32 - 1] * 32, core_mw=2**32 - 1, gpu_mw=2**32 - 1)
+    samples, offsets = synth.make_batch(traces)
+    s, o, _ = to_dev(samples, offsets)
+    st, me = ctx.proxy(s, o, [cfg], model)
+    ctx.check()
+    check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
+
+
+def test_rejects_levels_the_model_does_not_describe(ctx):
+    samples, offsets = synth.make_batch([np.ones(10, np.uint32)])
+    s, o, _ = to_dev(samples, offsets)
+    with pytest.raises(magus.MagusError) as ei:
+        ctx.proxy(s, o, [default_config()], dict(proxy_model(), n_levels=16))
+    assert ei.value.code == magus.EINVAL
+
+
+def test_bulk_workload_full_size_sampled(ctx, oracle_mod):
+    """4,096 x 100,000 at full size; sampled traces against the oracle."""
+    samples, offsets = synth.workload_bulk(4096, 100000)
+    s, o, _ = to_dev(samples, offsets)
+    model = proxy_model()
+    st, me = ctx.proxy(s, o, [default_config()], model)
+    ctx.check()
+    rng = np.random.default_rng(3)
+    pick = sorted(set(rng.integers(0, 4096, 6).tolist()) | {0, 4095})
+    check_against_oracle(oracle_mod, samples, offsets, [default_config()], None, model, st, me,
+                         traces=pick)
+    # every interval is counted once
+    steps = st.cpu().numpy()[:, 2:2 + magus.PROXY_LEVELS].sum(axis=1)
+    assert (steps == np.diff(offsets.astype(np.int64))).all()
