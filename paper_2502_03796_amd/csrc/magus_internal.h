@@ -89,6 +89,21 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          uint32_t persistent_blocks, bool any_base, hipStream_t stream,
                          hipEvent_t ev0, hipEvent_t ev1);
 
+// Around the chunk kernel (replay_fold.hip): the plan (chunk prefix per trace,
+// data checks, status word chunk_base[n_traces + 1], work counter
+// chunk_base[n_traces + 2]), the fold of the chunk summaries of every trace
+// (fix: optional, receives the level entering each chunk) and the fix-up of the
+// decision bytes of the steps before each chunk's first decisive step.
+hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,
+                       const uint32_t* cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
+                       uint32_t max_chunks, uint32_t* chunk_base, uint32_t* err,
+                       hipStream_t stream);
+hipError_t launch_fold(const uint64_t* offsets, uint32_t n_traces, const uint32_t* chunk_base,
+                       const ChunkSum* sums, const DevCfg* cfgs, const uint32_t* cfg_of_trace,
+                       magus_result* results, ChunkFix* fix, hipStream_t stream);
+hipError_t launch_fixup(uint32_t n_traces, const uint32_t* chunk_base, const ChunkFix* fix,
+                        uint32_t max_chunks, uint8_t* levels, hipStream_t stream);
+
 // Replay for configs with stepped actuation (stepped.hip): two passes over
 // each chunk, the first composing the chunk's clamp-add map, the second
 // accumulating with the entering level that the per-trace fold derived.

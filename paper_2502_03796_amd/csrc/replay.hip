@@ -14,9 +14,10 @@
 // Kernels, in stream order:
 //   plan    prefix sum of chunks per trace + device-side data checks
 //   chunks  one wave per chunk -> ChunkSum (and decision bytes if asked)
-//   fold    one thread per trace -> magus_result
+//   fold    one wave per trace -> magus_result
 //   fixup   (decision bytes only) level of the steps before the first
 //           decisive step of each chunk
+// The plan, fold and fixup kernels are in replay_fold.hip.
 
 #include <type_traits>
 
@@ -29,7 +30,6 @@ __device__ int llvm_writelane(int v, int lane, int old) __asm("llvm.amdgcn.write
 namespace {
 
 constexpr int kChunkWavesPerBlock = 4;
-constexpr int kPlanThreads = 1024;
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -53,74 +53,6 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
 
 __device__ __forceinline__ uint64_t low_mask(uint32_t n) {   // n in [0, 64]
     return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
-}
-
-// ------------------------------------------------------------------ plan
-
-__global__ __launch_bounds__(kPlanThreads) void plan_kernel(
-    const uint64_t* __restrict__ offsets, uint32_t n_traces, uint64_t n_samples,
-    const uint32_t* __restrict__ cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
-    uint32_t max_chunks, uint32_t* __restrict__ chunk_base, uint32_t* __restrict__ err)
-{
-    // Thread i owns the contiguous traces [i*per, (i+1)*per): one pass counts
-    // their chunks, one block-wide scan places them, a second pass writes.
-    __shared__ uint32_t wave_sum[kPlanThreads / kWave];
-    __shared__ uint32_t s_err;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) s_err = 0;
-    const uint32_t per = (n_traces + kPlanThreads - 1) / kPlanThreads;
-    const uint32_t t0 = min(tid * per, n_traces), t1 = min(t0 + per, n_traces);
-    auto chunks_of = [&](uint32_t t, uint32_t& e) -> uint32_t {
-        const uint64_t o0 = offsets[t], o1 = offsets[t + 1];
-        if (cfg_of_trace && cfg_of_trace[t] >= n_cfgs) e |= kErrCfgIndex;
-        if (o1 < o0 || o1 > n_samples) {
-            e |= kErrOffsets;
-            return 0;
-        }
-        if (o1 - o0 > MAGUS_MAX_TRACE_LEN) {
-            e |= kErrTooLong;
-            return 0;
-        }
-        return (uint32_t)((o1 - o0 + chunk - 1) / chunk);
-    };
-    uint32_t e = 0, mine = 0;
-    for (uint32_t t = t0; t < t1; ++t) mine += chunks_of(t, e);
-    __syncthreads();
-    if (e) atomicOr(&s_err, e);
-    // exclusive scan of `mine` over the block
-    uint32_t v = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += o;
-    }
-    if (lane == 63) wave_sum[wv] = v;
-    __syncthreads();
-    if (wv == 0) {
-        uint32_t w = lane < kPlanThreads / kWave ? wave_sum[lane] : 0;
-#pragma unroll
-        for (int d = 1; d < kPlanThreads / kWave; d <<= 1) {
-            const uint32_t o = __shfl_up(w, d, 64);
-            if (lane >= (uint32_t)d) w += o;
-        }
-        if (lane < kPlanThreads / kWave) wave_sum[lane] = w;   // inclusive
-    }
-    __syncthreads();
-    uint32_t run = (wv ? wave_sum[wv - 1] : 0) + v - mine;
-    for (uint32_t t = t0; t < t1; ++t) {
-        uint32_t dummy = 0;
-        chunk_base[t] = run;
-        run += chunks_of(t, dummy);
-    }
-    if (tid == kPlanThreads - 1) {
-        const uint32_t total = wave_sum[kPlanThreads / kWave - 1];
-        uint32_t ee = s_err;
-        if (total > max_chunks) ee |= kErrOffsets;
-        chunk_base[n_traces] = ee ? 0u : total;
-        chunk_base[n_traces + 1] = ee;           // status of this call
-        chunk_base[n_traces + 2] = 0;            // work counter of the persistent grid
-        if (ee) atomicOr(err, ee);
-    }
 }
 
 // ------------------------------------------------------------------ chunks
@@ -440,68 +372,7 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel_pers
     }
 }
 
-// ------------------------------------------------------------------ fold
-
-__global__ __launch_bounds__(256) void fold_kernel(
-    const uint64_t* __restrict__ offsets, uint32_t n_traces,
-    const uint32_t* __restrict__ chunk_base, const ChunkSum* __restrict__ sums,
-    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
-    magus_result* __restrict__ results, ChunkFix* __restrict__ fix)
-{
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
-    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
-    uint64_t level = c.linit, level_sum = 0, trans = 0, th = 0;
-    for (uint32_t k = chunk_base[t]; k < chunk_base[t + 1]; ++k) {
-        const ChunkSum S = sums[k];
-        if (fix) fix[k].level = (uint32_t)level;
-        if (S.prefix >= S.len) {
-            level_sum += level * S.len;
-        } else {
-            const uint64_t first = S.first_up ? c.lmax : c.lmin;
-            level_sum += level * S.prefix + (uint64_t)c.lmax * S.cnt_max +
-                         (uint64_t)c.lmin * (S.len - S.prefix - S.cnt_max);
-            trans += S.trans0 - S.first_up + (first != level);
-            level = S.end_up ? c.lmax : c.lmin;
-        }
-        th += S.ticks_high;
-    }
-    magus_result r;
-    r.score = level_sum + 1000ull * trans;
-    r.level_sum = level_sum;
-    r.transitions = trans;
-    r.ticks_high = th;
-    results[t] = r;
-}
-
-// ------------------------------------------------------------------ fixup
-
-__global__ __launch_bounds__(256) void fixup_kernel(
-    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
-    const ChunkFix* __restrict__ fix, uint8_t* __restrict__ levels)
-{
-    if (chunk_base[n_traces + 1] != 0) return;
-    const uint32_t total = chunk_base[n_traces];
-    for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
-        const ChunkFix f = fix[k];
-        for (uint32_t i = threadIdx.x; i < f.prefix; i += blockDim.x) {
-            uint8_t* p = levels + f.start + i;
-            *p = (uint8_t)((*p & 0xE0u) | f.level);
-        }
-    }
-}
-
 }  // namespace
-
-hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,
-                       const uint32_t* cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
-                       uint32_t max_chunks, uint32_t* chunk_base, uint32_t* err,
-                       hipStream_t stream)
-{
-    plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
-                                                n_cfgs, chunk, max_chunks, chunk_base, err);
-    return hipGetLastError();
-}
 
 hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
                          uint32_t n_traces, const DevCfg* cfgs, uint32_t n_cfgs,
@@ -512,8 +383,8 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          hipEvent_t ev0, hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
-    plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
-                                                n_cfgs, chunk, max_chunks, chunk_base, err);
+    (void)launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk, max_chunks,
+                      chunk_base, err, stream);
     uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
     if (ev0) (void)hipEventRecord(ev0, stream);
     auto go = [&](auto levels_tag, auto base_tag) {
@@ -538,12 +409,10 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
         }
     }
     if (ev1) (void)hipEventRecord(ev1, stream);
-    fold_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
-        offsets, n_traces, chunk_base, sums, cfgs, cfg_of_trace, results,
-        levels ? fix : nullptr);
+    (void)launch_fold(offsets, n_traces, chunk_base, sums, cfgs, cfg_of_trace, results,
+                      levels ? fix : nullptr, stream);
     if (levels && blocks)
-        fixup_kernel<<<min(max_chunks, 65535u), 256, 0, stream>>>(n_traces, chunk_base, fix,
-                                                                   levels);
+        (void)launch_fixup(n_traces, chunk_base, fix, max_chunks, levels, stream);
     return hipGetLastError();
 }
 

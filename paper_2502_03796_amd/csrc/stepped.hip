@@ -258,11 +258,6 @@ __global__ __launch_bounds__(256) void stepped_fold_kernel(
 
 }  // namespace
 
-hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,
-                       const uint32_t* cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
-                       uint32_t max_chunks, uint32_t* chunk_base, uint32_t* err,
-                       hipStream_t stream);
-
 hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
                                  uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
