@@ -208,26 +208,21 @@ def bulk():
     return synth.workload_bulk()
 
 
-def test_bulk_workload_full_size_sampled(ctx, oracle_mod, bulk):
+def test_bulk_workload_full_size(ctx, oracle_mod, bulk):
     """4,096 x 100,000 samples, single default config, the benchmark's launch:
-    results of a sample of traces against the oracle, one by one."""
+    every trace's results and every step's decision byte against the oracle."""
     samples, offsets = bulk
     s, o, _ = to_dev(samples, offsets)
     res, _ = ctx.replay(s, o, [default_config()])
     ctx.check()
     got = results_np(res)
-    rng = np.random.default_rng(2)
-    pick = sorted(set(rng.integers(0, 4096, 48).tolist()) | {0, 4095})
-    for t in pick:
-        x = samples[int(offsets[t]):int(offsets[t + 1])]
-        r, _ = oracle_mod.replay_trace(x, default_config(), want_bytes=False)
-        assert list(got[t]) == [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]], t
-    # per-step bytes of the same launch for the first traces
+    want_res, want = oracle_mod.replay_batch(samples, offsets, [default_config()],
+                                             want_bytes=True)
+    assert (got == want_res).all(), describe_mismatch(got[:, 0], want_res[:, 0])
     _, lv = ctx.replay(s, o, [default_config()], levels=True)
-    head = int(offsets[8])
-    _, want = oracle_mod.replay_batch(samples[:head], offsets[:9], [default_config()],
-                                      want_bytes=True)
-    assert (lv[:head].cpu().numpy() == want).all()
+    ctx.check()
+    b = lv.cpu().numpy()
+    assert (b == want).all(), describe_mismatch(b, want, offsets)
 
 
 def test_persistent_grid_and_graph_replays_match(ctx, oracle_mod):
@@ -273,10 +268,10 @@ def uneven():
     return synth.workload_uneven()
 
 
-def test_uneven_workload_full_size_sampled_with_autotune(ctx, oracle_mod, uneven):
+def test_uneven_workload_full_size_with_autotune(ctx, oracle_mod, uneven):
     """20,000 bursty traces of log-normal length with a grid config each (the
-    benchmark's uneven launch): autotuned shape, graph relaunch, sampled traces
-    against the oracle."""
+    benchmark's uneven launch): autotuned shape, graph relaunch; every trace's
+    results and every step's decision byte against the oracle."""
     samples, offsets, cot = uneven
     grid = synth.sweep_grid()
     s, o, c = to_dev(samples, offsets, cot)
@@ -288,14 +283,12 @@ def test_uneven_workload_full_size_sampled_with_autotune(ctx, oracle_mod, uneven
             res, _ = ctx.replay(s, o, grid, c)
             ctx.check()
         got = results_np(res)
-        lens = np.diff(offsets.astype(np.int64))
-        pick = sorted(set(np.random.default_rng(8).integers(0, len(lens), 24).tolist())
-                      | {int(np.argmax(lens)), int(np.argmin(lens))})
-        for t in pick:
-            x = samples[int(offsets[t]):int(offsets[t + 1])]
-            r, _ = oracle_mod.replay_trace(x, grid[int(cot[t])], want_bytes=False)
-            assert list(got[t]) == [r["score"], r["level_sum"], r["transitions"],
-                                    r["ticks_high"]], t
+        want_res, want = oracle_mod.replay_batch(samples, offsets, grid, cot, want_bytes=True)
+        assert (got == want_res).all(), describe_mismatch(got[:, 0], want_res[:, 0])
+        _, lv = ctx.replay(s, o, grid, c, levels=True)
+        ctx.check()
+        b = lv.cpu().numpy()
+        assert (b == want).all(), describe_mismatch(b, want, offsets)
     finally:
         ctx.set_graphs(False)
         ctx.set_chunk(0)
