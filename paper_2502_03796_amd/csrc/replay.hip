@@ -110,27 +110,48 @@ __device__ __forceinline__ void replay_chunk(
     // per-lane constants
     const int bperm_addr = (int)(((lane - (W - 1)) & 63u) << 2);  // lane of x[t-W+1]
     const bool from_cur = lane >= W - 1;
-    const uint32_t thr_lane = c.thr + lane;
+    // Alg. 2 compare, rearranged so that the block's carried-in count can stay
+    // in an SGPR: count = acc0 + X >= thr + lane  <=>  X + bias >= 2^31 - acc0
+    // with the per-lane bias = 2^31 - thr - lane (X, acc0 and thr + lane are
+    // all below 2^8, so nothing wraps).
+    const uint32_t bias_lane = 0x80000000u - (c.thr + lane);
+    // (with a zero count threshold every step is high: no block is quiet)
+    const uint64_t loud = c.thr == 0 ? 1ull : 0ull;
     // thresholds as per-lane registers: a select between a VGPR and an SGPR
     // operand needs no copy inside the loop
     uint32_t mu;
     asm volatile("v_mov_b32 %0, %1" : "=v"(mu) : "s"(c.mu));
     const uint32_t md = c.md;
+    // E1 with the default base: a rise is an event iff b 2^16 > a (2^16 + W q_inc),
+    // a fall iff a 2^16 > b (2^16 + W |q_dec|) (both sides below 2^59)
+    const uint32_t ku = 65536u + c.mu, kd = 65536u + c.md;
+    // 2^16 as an opaque SGPR operand, so that x 2^16 stays one 32x32->64
+    // multiply instead of a zero-extension plus a 64-bit shift
+    uint32_t k16;
+    asm volatile("s_mov_b32 %0, 0x10000" : "=s"(k16));
 
     auto load_block = [&](uint32_t desc_blk) -> uint32_t {
         return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((desc_blk * 64 + lane) * 4), 0, 0);
     };
-    // Alg. 1 for the 64 steps of a block: event and rising masks.
-    auto events = [&](uint32_t a, uint32_t b, uint64_t& E, uint64_t& R) {
-        const bool rising = b > a;
-        uint32_t lov = min(a, b);
-        const uint32_t d = max(a, b) - lov;
-        if constexpr (kAnyBase) lov = derivative_base(a, b, c.base);
-        const uint32_t m = rising ? mu : md;
-        // r = d / (W lo) beyond q / 2^16  <=>  d 2^16 > lo (W q)
-        const bool ev = ((uint64_t)d << 16) > (uint64_t)lov * m;
-        E = ballot(ev);
-        R = ballot(rising);
+    // Alg. 1 for the 64 steps of a block: masks of the +1 and -1 predictions.
+    auto events = [&](uint32_t a, uint32_t b, uint64_t& EU, uint64_t& ED) {
+        if constexpr (kAnyBase) {
+            const bool rising = b > a;
+            const uint32_t lov = derivative_base(a, b, c.base);
+            const uint32_t d = max(a, b) - min(a, b);
+            const uint32_t m = rising ? mu : md;
+            // r = d / (W base) beyond q / 2^16  <=>  d 2^16 > base (W q)
+            const uint64_t E = ballot(((uint64_t)d << 16) > (uint64_t)lov * m);
+            const uint64_t R = ballot(rising);
+            EU = E & R;
+            ED = E & ~R;
+        } else {
+            // the smaller sample is the base: with b > a, (b - a) 2^16 > a W q
+            // <=> b 2^16 > a (2^16 + W q), which cannot hold for b <= a
+            // (x 2^16 as a 64-bit product: no register pair to zero-extend into)
+            EU = ballot((uint64_t)b * k16 > (uint64_t)a * ku);
+            ED = ballot((uint64_t)a * k16 > (uint64_t)b * kd);
+        }
     };
 
     uint32_t xp = 0;             // samples of the block before the current one
@@ -138,8 +159,9 @@ __device__ __forceinline__ void replay_chunk(
     if (first_real) {
         const uint32_t x0 = load_block(0);
         const uint32_t ac = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)x0);
-        uint64_t E, R;
-        events(from_cur ? ac : 0u, x0, E, R);
+        uint64_t EU, ED;
+        events(from_cur ? ac : 0u, x0, EU, ED);
+        uint64_t E = EU | ED;
         const uint32_t tb = s - 64;
         if (tb < W - 1) E &= ~low_mask(W - 1 - tb);       // FIFO not yet full
         fps = E >> 1;
@@ -216,6 +238,9 @@ __device__ __forceinline__ void replay_chunk(
         gcarry = k1 | k2;
         g0 += gi * 64;
         gi = 0;
+        // lanes of quiet blocks are not written: start the next group at zero
+        upL = upH = dnL = dnH = 0;
+        if constexpr (kLevels) puL = puH = pdL = pdH = hmL = hmH = 0;
     };
 
     // One iteration: blocks it*kIter .. it*kIter+kIter-1 (real-block index).
@@ -236,27 +261,31 @@ __device__ __forceinline__ void replay_chunk(
         }
 #pragma unroll
         for (uint32_t j = 0; j < kIter; ++j) {
-            uint64_t E, R;
-            events(from_cur ? ac[j] : ap[j], cur[j], E, R);
-            uint64_t vm = ~0ull;
+            uint64_t PU, PD;
+            events(from_cur ? ac[j] : ap[j], cur[j], PU, PD);
             if constexpr (generic) {
                 const uint32_t tb = s + (it * kIter + j) * 64;     // trace step of lane 0
-                vm = low_mask(tb < e ? min(64u, e - tb) : 0u);
+                uint64_t vm = low_mask(tb < e ? min(64u, e - tb) : 0u);
                 if (tb < W - 1) vm &= ~low_mask(W - 1 - tb);
-                E &= vm;
+                PU &= vm;
+                PD &= vm;
             }
+            const uint64_t E = PU | PD;
+            // A quiet block (no event in it nor in the H-1 steps before it,
+            // and a non-zero count threshold) is never high and has no
+            // decisive step: its group lanes stay zero and nothing else changes.
+            if (!generic && (E | fps | loud) == 0) continue;
             // Alg. 2: events among the last H steps, for all 64 steps at once
             const uint64_t B = fps >> (64 - H);           // last H-1 flags of the block before
             const uint64_t nG = ~((E << (H - 1)) | B);    // ~(flag H-1 steps back)
             const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(E & 1ull);
-            const uint32_t cnt = mbcnt(nG, mbcnt(E >> 1, acc0));
-            uint64_t HM = ballot(cnt >= thr_lane);
+            const uint32_t cnt = mbcnt(nG, mbcnt(E >> 1, bias_lane));
+            uint64_t HM = ballot(cnt >= 0x80000000u - acc0);
             if constexpr (generic) {
                 const uint32_t tb = s + (it * kIter + j) * 64;
                 HM &= low_mask(tb < e ? min(64u, e - tb) : 0u);
             }
             fps = E >> 1;
-            const uint64_t PU = E & R, PD = E & ~R;
             const uint64_t UP = HM | PU;                  // high or +1 -> max
             const uint64_t DN = PD & ~HM;                 // -1 executed -> min
             th += (uint32_t)__popcll(HM);
