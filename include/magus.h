@@ -126,8 +126,8 @@ int magus_ctx_destroy(magus_ctx* ctx);
 
 /*
  * Time-chunk length (steps, a multiple of 64, 64..2^24) used to split long
- * traces across wavefronts; 0 restores the default.  Results never depend on
- * it.
+ * traces across wavefronts; 0 restores the default (4,096).  Results never
+ * depend on it.
  */
 int magus_ctx_set_chunk(magus_ctx* ctx, uint32_t chunk_steps);
 uint32_t magus_ctx_get_chunk(const magus_ctx* ctx);

@@ -13,7 +13,7 @@ namespace magus {
 
 namespace {
 thread_local std::string g_last_error;
-constexpr uint32_t kDefaultChunk = 8192;
+constexpr uint32_t kDefaultChunk = 4096;
 }  // namespace
 
 int fail(int code, const char* fmt, ...) {

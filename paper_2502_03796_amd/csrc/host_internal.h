@@ -56,7 +56,7 @@ struct DeviceGuard {
 
 struct magus_ctx {
     int device = 0;
-    uint32_t chunk = 8192;
+    uint32_t chunk = 4096;
     magus::DevBuf err;          // uint32 sticky error word
     magus::DevBuf chunk_base;   // replay: chunk prefix sum + status
     magus::DevBuf sums;         // replay: ChunkSum per chunk

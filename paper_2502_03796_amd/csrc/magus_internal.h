@@ -35,6 +35,29 @@ __device__ __forceinline__ uint32_t derivative_base(uint32_t a, uint32_t b, uint
     return min(a | mo, b | mn);
 }
 
+// Trace of chunk g: the last t with chunk_base[t] <= g, for a non-decreasing
+// chunk_base[0..n_traces] with chunk_base[n_traces] > g.  A 64-way search:
+// every lane probes one position per round, so a round shrinks the range 64x
+// (two rounds for 4,096 traces instead of twelve dependent loads).  Called by
+// a whole wave; the result is wave-uniform.
+__device__ __forceinline__ uint32_t trace_of_chunk(const uint32_t* chunk_base,
+                                                   uint32_t n_traces, uint32_t g,
+                                                   uint32_t lane) {
+    uint32_t lo = 0, hi = n_traces;
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) >> 6;
+        const uint32_t idx = lo + lane * step;
+        const bool le = idx < hi && chunk_base[idx] <= g;   // a prefix of the lanes
+        const uint64_t m = __ballot(le);                    // lane 0 (idx = lo) is set
+        const uint32_t k = 63u - (uint32_t)__builtin_clzll(m);
+        lo += k * step;
+        hi = min(lo + step, hi);
+        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+        hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi);
+    }
+    return lo;
+}
+
 // Summary of one time chunk of one trace, computed without knowing the level
 // entering the chunk (taken as level_min for the bit vector).  32 bytes.
 struct ChunkSum {

@@ -71,13 +71,7 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
     const uint32_t g = blockIdx.x * kStatsWaves + uniform(wv);
     if (g >= chunk_base[n_traces]) return;
 
-    // trace of this chunk: the last t with chunk_base[t] <= g
-    uint32_t lo = 0, hi = n_traces;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (chunk_base[mid] <= g) lo = mid; else hi = mid;
-    }
-    const uint32_t t = lo;
+    const uint32_t t = trace_of_chunk(chunk_base, n_traces, g, lane);
     const uint64_t tbase = offsets[t];
     const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
     const uint32_t s = (g - chunk_base[t]) * chunk;

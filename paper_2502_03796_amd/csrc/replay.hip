@@ -27,6 +27,11 @@ namespace magus {
 
 __device__ int llvm_writelane(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
+// lane `lane` of `dst` := v
+__device__ __forceinline__ void writelane_into(uint32_t& dst, uint32_t v, uint32_t lane) {
+    dst = (uint32_t)llvm_writelane((int)v, (int)lane, (int)dst);
+}
+
 namespace {
 
 constexpr int kChunkWavesPerBlock = 4;
@@ -76,13 +81,7 @@ __device__ __forceinline__ void replay_chunk(
     uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
     uint8_t* __restrict__ levels, const uint32_t g, const uint32_t lane)
 {
-    // trace of this chunk: the last t with chunk_base[t] <= g
-    uint32_t lo = 0, hi = n_traces;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (chunk_base[mid] <= g) lo = mid; else hi = mid;
-    }
-    const uint32_t t = lo;
+    const uint32_t t = trace_of_chunk(chunk_base, n_traces, g, lane);
     const uint64_t tbase = offsets[t];
     const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
     const uint32_t s = (g - chunk_base[t]) * chunk;
@@ -271,12 +270,16 @@ __device__ __forceinline__ void replay_chunk(
                 PD &= vm;
             }
             const uint64_t E = PU | PD;
-            // A quiet block (no event in it nor in the H-1 steps before it,
-            // and a non-zero count threshold) is never high and has no
-            // decisive step: its group lanes stay zero and nothing else changes.
-            if (!generic && (E | fps | loud) == 0) continue;
             // Alg. 2: events among the last H steps, for all 64 steps at once
             const uint64_t B = fps >> (64 - H);           // last H-1 flags of the block before
+            // A quiet block (no event in it nor in the H-1 steps before it,
+            // and a non-zero count threshold) is never high and has no
+            // decisive step: its group lanes stay zero and only the flag
+            // history moves on.
+            if (!generic && (E | B | loud) == 0) {
+                fps = 0;
+                continue;
+            }
             const uint64_t nG = ~((E << (H - 1)) | B);    // ~(flag H-1 steps back)
             const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(E & 1ull);
             const uint32_t cnt = mbcnt(nG, mbcnt(E >> 1, bias_lane));
@@ -289,18 +292,18 @@ __device__ __forceinline__ void replay_chunk(
             const uint64_t UP = HM | PU;                  // high or +1 -> max
             const uint64_t DN = PD & ~HM;                 // -1 executed -> min
             th += (uint32_t)__popcll(HM);
-            const int li = (int)(gi + j);
-            upL = (uint32_t)llvm_writelane((int)lo32(UP), li, (int)upL);
-            upH = (uint32_t)llvm_writelane((int)hi32(UP), li, (int)upH);
-            dnL = (uint32_t)llvm_writelane((int)lo32(DN), li, (int)dnL);
-            dnH = (uint32_t)llvm_writelane((int)hi32(DN), li, (int)dnH);
+            const uint32_t li = gi + j;
+            writelane_into(upL, lo32(UP), li);
+            writelane_into(upH, hi32(UP), li);
+            writelane_into(dnL, lo32(DN), li);
+            writelane_into(dnH, hi32(DN), li);
             if constexpr (kLevels) {
-                puL = (uint32_t)llvm_writelane((int)lo32(PU), li, (int)puL);
-                puH = (uint32_t)llvm_writelane((int)hi32(PU), li, (int)puH);
-                pdL = (uint32_t)llvm_writelane((int)lo32(PD), li, (int)pdL);
-                pdH = (uint32_t)llvm_writelane((int)hi32(PD), li, (int)pdH);
-                hmL = (uint32_t)llvm_writelane((int)lo32(HM), li, (int)hmL);
-                hmH = (uint32_t)llvm_writelane((int)hi32(HM), li, (int)hmH);
+                writelane_into(puL, lo32(PU), li);
+                writelane_into(puH, hi32(PU), li);
+                writelane_into(pdL, lo32(PD), li);
+                writelane_into(pdH, hi32(PD), li);
+                writelane_into(hmL, lo32(HM), li);
+                writelane_into(hmH, hi32(HM), li);
             }
         }
         xp = cur[kIter - 1];

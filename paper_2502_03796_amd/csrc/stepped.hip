@@ -75,12 +75,7 @@ __device__ __forceinline__ ChunkView chunk_view(
     uint32_t chunk, uint32_t g)
 {
     ChunkView v;
-    uint32_t lo = 0, hi = n_traces;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (chunk_base[mid] <= g) lo = mid; else hi = mid;
-    }
-    v.t = lo;
+    v.t = trace_of_chunk(chunk_base, n_traces, g, threadIdx.x & 63);
     v.tbase = offsets[v.t];
     const uint32_t n = (uint32_t)(offsets[v.t + 1] - v.tbase);
     v.s = (g - chunk_base[v.t]) * chunk;
