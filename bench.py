@@ -26,15 +26,16 @@ HBM_PEAK_GBS = 8000.0
 # int32 VALU issue peak: 256 CUs x 64 lanes per clock x 2.4 GHz
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chunk_kernel_bulk_traffic.json")
+SWEEP_COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_sweep_counters.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash():
+def source_hash(files=("replay.hip", "magus_internal.h")):
     h = hashlib.sha256()
-    for f in ("replay.hip", "magus_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2502_03796_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -51,6 +52,19 @@ def stored_traffic(n_samples):
     if t.get("source_sha256") != source_hash() or t.get("n_samples") != n_samples:
         return None
     return t.get("bytes_per_launch")
+
+
+def stored_sweep_counters():
+    """VALU instruction count per sweep launch from the committed rocprofv3
+    counter summary, if it was taken on the current sweep kernel source."""
+    try:
+        with open(SWEEP_COUNTERS_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash(("sweep.hip", "magus_internal.h")):
+        return None
+    return t
 
 
 def bench_sweep(magus, synth, ctx, dev):
@@ -80,7 +94,14 @@ def bench_sweep(magus, synth, ctx, dev):
     kern_s = kms / kn * 1e-3
     res = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
            "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3, "kernel_ms": kern_s * 1e3,
-           "useful_op_frac_12ops": evals / kern_s * 12 / VALU_PEAK_OPS}
+           # lane-ops per evaluation the VALU could issue at peak in this time
+           "valu_lane_ops_per_eval_at_peak": VALU_PEAK_OPS * kern_s / evals}
+    cnt = stored_sweep_counters()
+    if cnt:
+        # wave instructions issued / (kernel time x 1 wave-instruction per
+        # clock per compute unit x 256 compute units x 2.4 GHz)
+        res["valu_issue_frac"] = cnt["valu_insts_per_launch"] / (kern_s * 256 * 2.4e9)
+        res["valu_lane_ops_per_eval"] = cnt["valu_insts_per_launch"] * 64 / evals
     log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
     del ss, so
     torch.cuda.empty_cache()

@@ -1,5 +1,6 @@
 """GPU parity of magus_sweep: scores and arg-min against the oracle, and the
 sweep against the plain replay of each config on the same GPU."""
+import os
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -89,39 +90,39 @@ def test_sweep_equals_replay_on_the_gpu(ctx, oracle_mod):
 
 def test_sweep_workload_full_size(ctx, oracle_mod):
     """1,024 traces x 50,000 samples x a window block of 4,096 configs (the
-    benchmark's sweep launch): scores of 1/16 of the configs on three traces and
-    of 1/64 of the configs on every trace against the oracle, and every trace's
-    arg-min."""
+    benchmark's sweep launch), for the first and the last window block: every
+    config on 16 traces, a stratified 1/16 (first block) or 1/64 (last block)
+    of the configs on every trace, and every trace's arg-min, against the
+    oracle.  The oracle runs in host threads (its ctypes calls release the
+    interpreter lock)."""
     samples, offsets = synth.workload_sweep_traces()
     grid = synth.sweep_grid()
-    for wblock in (0, 3):
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    s, o, _ = to_dev(samples, offsets)
+
+    def oracle_scores(traces, cfgs):
+        part = synth.make_batch([samples[int(offsets[t]):int(offsets[t + 1])] for t in traces])
+        return oracle_mod.sweep(part[0], part[1], cfgs)[0]
+
+    for wblock, stride in ((0, 16), (3, 64)):
         cfgs = grid[wblock * 4096:(wblock + 1) * 4096]
-        s, o, _ = to_dev(samples, offsets)
         sc, arg = ctx.sweep(s, o, cfgs, scores=True)
         ctx.check()
         sc = sc.cpu().numpy().view(np.uint64)
         arg = arg.cpu().numpy()
         rng = np.random.default_rng(wblock)
-        cpick = np.arange(int(rng.integers(0, 16)), 4096, 16)    # 1/16 of the configs
-        for t in (0, 511, 1023):
-            x = samples[int(offsets[t]):int(offsets[t + 1])]
-            sub = synth.make_batch([x])
-            want, _ = oracle_mod.sweep(sub[0], sub[1], [cfgs[i] for i in cpick])
-            assert (sc[t, cpick] == want[0]).all(), t
-        # every trace against a stratified 1/64 of the configs (the oracle runs
-        # in host threads: its ctypes calls release the interpreter lock)
-        cpick64 = np.arange(int(rng.integers(0, 64)), 4096, 64)
-        sub_cfgs = [cfgs[i] for i in cpick64]
-
-        def oracle_rows(t0):
-            t1 = min(t0 + 64, 1024)
-            part = synth.make_batch([samples[int(offsets[t]):int(offsets[t + 1])]
-                                     for t in range(t0, t1)])
-            return t0, oracle_mod.sweep(part[0], part[1], sub_cfgs)[0]
-
-        with ThreadPoolExecutor(max_workers=8) as pool:
-            for t0, rows in pool.map(oracle_rows, range(0, 1024, 64)):
-                assert (sc[t0:t0 + len(rows)][:, cpick64] == rows).all(), t0
+        every16 = sorted(rng.choice(1024, 16, replace=False).tolist())
+        cpick = np.arange(int(rng.integers(0, stride)), 4096, stride)
+        sub_cfgs = [cfgs[i] for i in cpick]
+        with ThreadPoolExecutor(max_workers=threads) as pool:
+            # every config on 16 traces (one trace per task)
+            for t, row in zip(every16, pool.map(lambda t: oracle_scores([t], cfgs)[0], every16)):
+                assert (sc[t] == row).all(), (wblock, t)
+            # the stratified config sample on every trace
+            starts = list(range(0, 1024, 16))
+            rows = pool.map(lambda t0: oracle_scores(range(t0, t0 + 16), sub_cfgs), starts)
+            for t0, r in zip(starts, rows):
+                assert (sc[t0:t0 + 16][:, cpick] == r).all(), (wblock, t0)
         # the arg-min of every trace: the lowest index among the minimal scores
         mins = sc.min(axis=1)
         assert (sc[np.arange(1024), arg] == mins).all()
