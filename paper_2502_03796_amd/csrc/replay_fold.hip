@@ -33,14 +33,16 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
 {
     // Thread i owns the contiguous traces [i*per, (i+1)*per): one pass counts
     // their chunks, one block-wide scan places them, a second pass writes.
+    // Up to kCache traces per thread (8,192 traces) the offsets are loaded
+    // once, all at the same time, and the counts stay in registers.
+    constexpr uint32_t kCache = 8;
     __shared__ uint32_t wave_sum[kPlanThreads / kWave];
     __shared__ uint32_t s_err;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_err = 0;
     const uint32_t per = (n_traces + kPlanThreads - 1) / kPlanThreads;
     const uint32_t t0 = min(tid * per, n_traces), t1 = min(t0 + per, n_traces);
-    auto chunks_of = [&](uint32_t t, uint32_t& e) -> uint32_t {
-        const uint64_t o0 = offsets[t], o1 = offsets[t + 1];
+    auto count = [&](uint32_t t, uint64_t o0, uint64_t o1, uint32_t& e) -> uint32_t {
         if (cfg_of_trace && cfg_of_trace[t] >= n_cfgs) e |= kErrCfgIndex;
         if (o1 < o0 || o1 > n_samples) {
             e |= kErrOffsets;
@@ -50,10 +52,23 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
             e |= kErrTooLong;
             return 0;
         }
-        return (uint32_t)((o1 - o0 + chunk - 1) / chunk);
+        return ((uint32_t)(o1 - o0) + chunk - 1) / chunk;   // both below 2^31
     };
+    const bool cached = per <= kCache;
+    uint32_t cnt[kCache];
     uint32_t e = 0, mine = 0;
-    for (uint32_t t = t0; t < t1; ++t) mine += chunks_of(t, e);
+    if (cached) {
+        uint64_t o[kCache + 1];
+#pragma unroll
+        for (uint32_t k = 0; k <= kCache; ++k) o[k] = t0 + k <= t1 ? offsets[t0 + k] : 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kCache; ++k) {
+            cnt[k] = t0 + k < t1 ? count(t0 + k, o[k], o[k + 1], e) : 0u;
+            mine += cnt[k];
+        }
+    } else {
+        for (uint32_t t = t0; t < t1; ++t) mine += count(t, offsets[t], offsets[t + 1], e);
+    }
     __syncthreads();
     if (e) atomicOr(&s_err, e);
     // exclusive scan of `mine` over the block
@@ -76,10 +91,19 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
     }
     __syncthreads();
     uint32_t run = (wv ? wave_sum[wv - 1] : 0) + v - mine;
-    for (uint32_t t = t0; t < t1; ++t) {
-        uint32_t dummy = 0;
-        chunk_base[t] = run;
-        run += chunks_of(t, dummy);
+    if (cached) {
+#pragma unroll
+        for (uint32_t k = 0; k < kCache; ++k)
+            if (t0 + k < t1) {
+                chunk_base[t0 + k] = run;
+                run += cnt[k];
+            }
+    } else {
+        for (uint32_t t = t0; t < t1; ++t) {
+            uint32_t dummy = 0;
+            chunk_base[t] = run;
+            run += count(t, offsets[t], offsets[t + 1], dummy);
+        }
     }
     if (tid == kPlanThreads - 1) {
         const uint32_t total = wave_sum[kPlanThreads / kWave - 1];
