@@ -134,9 +134,9 @@ uint32_t magus_ctx_get_chunk(const magus_ctx* ctx);
 
 /*
  * Launch shape of the replay chunk kernel: 0 launches one wavefront per time
- * chunk; N > 0 launches N workgroups of 4 wavefronts that take chunks from a
- * device-side counter until none is left (a persistent grid).  Results never
- * depend on it.
+ * chunk; N > 0 launches N workgroups of 4 wavefronts that replay the chunks
+ * round-robin (wavefront w takes chunks w, w + 4N, w + 8N, ...; a persistent
+ * grid).  Results never depend on it.
  */
 int magus_ctx_set_persistent(magus_ctx* ctx, uint32_t workgroups);
 uint32_t magus_ctx_get_persistent(const magus_ctx* ctx);

@@ -113,8 +113,7 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          hipEvent_t ev0, hipEvent_t ev1);
 
 // Around the chunk kernel (replay_fold.hip): the plan (chunk prefix per trace,
-// data checks, status word chunk_base[n_traces + 1], work counter
-// chunk_base[n_traces + 2]), the fold of the chunk summaries of every trace
+// data checks, status word chunk_base[n_traces + 1]), the fold of the chunk summaries of every trace
 // (fix: optional, receives the level entering each chunk) and the fix-up of the
 // decision bytes of the steps before each chunk's first decisive step.
 hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,

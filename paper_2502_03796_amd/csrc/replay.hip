@@ -364,44 +364,25 @@ __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel(
                                     chunk, sums, fix, levels, g, threadIdx.x & 63);
 }
 
-// One chunk as a real call: the call boundary makes every lane of the wave
-// reconverge before the persistent loop fetches the next chunk (inlined, the
-// divergent summary store at the end of a chunk could otherwise be merged
-// into the loop exit, letting lanes re-enter the loop without a new fetch).
-template <bool kLevels, bool kAnyBase>
-__device__ __noinline__ void replay_chunk_call(
-    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
-    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
-    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
-    uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
-    uint8_t* __restrict__ levels, const uint32_t g, const uint32_t lane)
-{
-    replay_chunk<kLevels, kAnyBase>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
-                                    chunk, sums, fix, levels, g, lane);
-}
-
-// Persistent grid: every wave takes chunks from a device counter until none
-// is left (the counter is cleared by the plan kernel of the same call).  Every
-// lane takes part in the fetch (only lane 0 adds 1), so the loop has no
-// divergent branch of its own.
+// Persistent grid: wave w of a grid of W waves replays chunks w, w + W,
+// w + 2W, ... in order.  The chunk index is a wave-uniform scalar computed
+// from the grid shape alone, so the loop and its exit are scalar branches
+// (every lane runs the same iterations) and no counter is shared.
 template <bool kLevels, bool kAnyBase>
 __global__ __launch_bounds__(kChunkWavesPerBlock * kWave) void chunk_kernel_persistent(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
-    uint32_t n_traces, uint32_t* __restrict__ chunk_base,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
     uint32_t chunk, ChunkSum* __restrict__ sums, ChunkFix* __restrict__ fix,
     uint8_t* __restrict__ levels)
 {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t total = chunk_base[n_traces];
-    uint32_t* counter = chunk_base + n_traces + 2;
-    for (;;) {
-        const uint32_t mine = atomicAdd(counter, lane == 0 ? 1u : 0u);
-        const uint32_t g = uniform(__shfl(mine, 0, 64));   // lane 0's fetch
-        if (g >= total) break;
-        replay_chunk_call<kLevels, kAnyBase>(samples, offsets, n_traces, chunk_base, cfgs,
-                                             cfg_of_trace, chunk, sums, fix, levels, g, lane);
-    }
+    const uint32_t total = uniform(chunk_base[n_traces]);
+    const uint32_t stride = gridDim.x * kChunkWavesPerBlock;
+    for (uint32_t g = blockIdx.x * kChunkWavesPerBlock + uniform(threadIdx.x >> 6); g < total;
+         g += stride)
+        replay_chunk<kLevels, kAnyBase>(samples, offsets, n_traces, chunk_base, cfgs,
+                                        cfg_of_trace, chunk, sums, fix, levels, g, lane);
 }
 
 }  // namespace

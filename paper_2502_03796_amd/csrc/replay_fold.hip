@@ -1,8 +1,7 @@
 // Plan, fold and fix-up kernels around the replay chunk kernel (replay.hip).
 //
 //   plan    one workgroup: prefix sum of the chunks of every trace, data checks
-//           (offsets, trace length, config index), the per-call status word and
-//           the persistent grid's work counter
+//           (offsets, trace length, config index) and the per-call status word
 //   fold    one wave per trace: composes the trace's chunk summaries in order
 //   fixup   (decision bytes only) writes the entering level into the steps
 //           before the first decisive step of each chunk
@@ -111,7 +110,6 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
         if (total > max_chunks) ee |= kErrOffsets;
         chunk_base[n_traces] = ee ? 0u : total;
         chunk_base[n_traces + 1] = ee;           // status of this call
-        chunk_base[n_traces + 2] = 0;            // work counter of the persistent grid
         if (ee) atomicOr(err, ee);
     }
 }
