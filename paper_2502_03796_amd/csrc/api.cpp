@@ -283,18 +283,13 @@ int magus_ctx_check(magus_ctx* ctx, hipStream_t stream) {
     return MAGUS_OK;
 }
 
-int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
-                 const uint64_t* d_offsets, uint32_t n_traces, const magus_config* h_cfgs,
-                 uint32_t n_cfgs, const uint32_t* d_cfg_of_trace, magus_result* d_results,
-                 uint8_t* d_levels, hipStream_t stream) {
-    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
-    if (!h_cfgs || n_cfgs == 0) return fail(MAGUS_EINVAL, "need at least one config");
-    if (n_traces && (!d_offsets || !d_results))
-        return fail(MAGUS_EINVAL, "offsets and results are required");
-    if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
-    if (n_traces > (1u << 30)) return fail(MAGUS_EINVAL, "too many traces");
-    // configs identical to the previous call's are neither re-validated nor
-    // re-uploaded
+namespace {
+
+// Validates h_cfgs (skipped when they equal the previous call's), makes sure the
+// device table holds their kernel form (uploaded on `stream` when changed) and
+// reports whether any config is stepped or uses another derivative base.
+int stage_configs(magus_ctx* ctx, const magus_config* h_cfgs, uint32_t n_cfgs,
+                  hipStream_t stream, bool* stepped, bool* any_base) {
     const bool same = ctx->cfg_raw.size() == n_cfgs &&
                       std::memcmp(ctx->cfg_raw.data(), h_cfgs,
                                   (size_t)n_cfgs * sizeof(magus_config)) == 0;
@@ -308,24 +303,64 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         }
     }
     const std::vector<DevCfg>& tab = same ? ctx->cfg_host : fresh;
-    if (n_traces == 0) return MAGUS_OK;
+    *stepped = false;
+    *any_base = false;
+    for (const DevCfg& d : tab) {
+        *stepped |= d.up || d.down;
+        *any_base |= d.base != 0;
+    }
+    const void* before = ctx->cfgs.p;
+    int rc;
+    if ((rc = ctx->cfgs.ensure((size_t)n_cfgs * sizeof(DevCfg)))) return rc;
+    if (ctx->cfgs.p != before) ctx->drop_graphs();
+    if (!same || ctx->cfgs.p != before) {
+        // pageable source: the runtime stages it before returning
+        HIP_TRY(hipMemcpyAsync(ctx->cfgs.p, tab.data(), tab.size() * sizeof(DevCfg),
+                               hipMemcpyHostToDevice, stream));
+        if (!same) {
+            ctx->cfg_host = fresh;
+            ctx->cfg_raw.assign(h_cfgs, h_cfgs + n_cfgs);
+        }
+    }
+    return MAGUS_OK;
+}
+
+}  // namespace
+
+int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                 const uint64_t* d_offsets, uint32_t n_traces, const magus_config* h_cfgs,
+                 uint32_t n_cfgs, const uint32_t* d_cfg_of_trace, magus_result* d_results,
+                 uint8_t* d_levels, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (!h_cfgs || n_cfgs == 0) return fail(MAGUS_EINVAL, "need at least one config");
+    if (n_traces && (!d_offsets || !d_results))
+        return fail(MAGUS_EINVAL, "offsets and results are required");
+    if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
+    if (n_traces > (1u << 30)) return fail(MAGUS_EINVAL, "too many traces");
+    if (n_traces == 0) {
+        // nothing to run; the configs are still validated
+        for (uint32_t i = 0; i < n_cfgs; ++i) {
+            DevCfg d;
+            int rc = derive(&h_cfgs[i], &d);
+            if (rc != MAGUS_OK)
+                return fail(rc, "config %u: %s", i, std::string(last_error()).c_str());
+        }
+        return MAGUS_OK;
+    }
     const uint64_t max_chunks64 = n_samples / ctx->chunk + n_traces + 1;
     if (max_chunks64 > 0xFFFFFFF0ull) return fail(MAGUS_EINVAL, "batch too large for one call");
     const uint32_t max_chunks = (uint32_t)max_chunks64;
 
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    // configs identical to the previous call's are neither re-validated nor
+    // re-uploaded
     bool stepped = false, any_base = false;
-    for (const DevCfg& d : tab) {
-        stepped |= d.up || d.down;
-        any_base |= d.base != 0;
-    }
-    const void* before[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p,
+    int rc = stage_configs(ctx, h_cfgs, n_cfgs, stream, &stepped, &any_base);
+    if (rc != MAGUS_OK) return rc;
+    const void* before[6] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p,
                              ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
-    int rc;
-    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4)) ||
-        (rc = ctx->cfgs.ensure((size_t)n_cfgs * sizeof(DevCfg))))
-        return rc;
+    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4))) return rc;
     if (stepped) {
         if ((rc = ctx->step_funcs.ensure((size_t)max_chunks * sizeof(ClampAdd))) ||
             (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
@@ -335,18 +370,9 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         if ((rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum)))) return rc;
         if (d_levels && (rc = ctx->fix.ensure((size_t)max_chunks * sizeof(ChunkFix)))) return rc;
     }
-    const void* after[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->cfgs.p, ctx->fix.p,
+    const void* after[6] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p,
                             ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
     if (std::memcmp(before, after, sizeof before) != 0) ctx->drop_graphs();
-    if (!same || before[2] != after[2]) {
-        // pageable source: the runtime stages it before returning
-        HIP_TRY(hipMemcpyAsync(ctx->cfgs.p, tab.data(), tab.size() * sizeof(DevCfg),
-                               hipMemcpyHostToDevice, stream));
-        if (!same) {
-            ctx->cfg_host = fresh;
-            ctx->cfg_raw.assign(h_cfgs, h_cfgs + n_cfgs);
-        }
-    }
     auto launch = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
         if (stepped)
             return launch_replay_stepped(
@@ -444,14 +470,15 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                            n_cfgs, d_cfg_of_trace, nullptr, nullptr, stream);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
-    if ((rc = ctx->proxy_levels.ensure(std::max<uint64_t>(n_samples, 1))) ||
-        (rc = ctx->proxy_results.ensure((size_t)n_traces * sizeof(magus_result))) ||
-        (rc = ctx->proxy_model.ensure(sizeof(magus_proxy_model))))
-        return rc;
-    if ((rc = magus_replay(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
-                           d_cfg_of_trace, ctx->proxy_results.as<magus_result>(),
-                           ctx->proxy_levels.as<uint8_t>(), stream)))
-        return rc;
+    if ((rc = ctx->proxy_model.ensure(sizeof(magus_proxy_model)))) return rc;
+    const uint64_t max_chunks64 = n_samples / ctx->chunk + n_traces + 1;
+    if (max_chunks64 > 0xFFFFFFF0ull) return fail(MAGUS_EINVAL, "batch too large for one call");
+    const uint32_t max_chunks = (uint32_t)max_chunks64;
+    if (n_samples && !d_samples) return fail(MAGUS_EINVAL, "samples is NULL");
+    if (!d_offsets) return fail(MAGUS_EINVAL, "offsets is NULL");
+    if (n_traces > (1u << 30)) return fail(MAGUS_EINVAL, "too many traces");
+    bool stepped = false, any_base = false;
+    if ((rc = stage_configs(ctx, h_cfgs, n_cfgs, stream, &stepped, &any_base))) return rc;
     if (!ctx->proxy_model_set ||
         std::memcmp(&ctx->proxy_model_host, &m, sizeof m) != 0) {
         ctx->proxy_model_host = m;
@@ -459,7 +486,31 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                hipMemcpyHostToDevice, stream));
         ctx->proxy_model_set = true;
     }
-    const uint32_t max_chunks = (uint32_t)(n_samples / ctx->chunk + n_traces + 1);
+    if (!stepped) {
+        // one pass over the samples: plan, fused chunk pass, fold, metrics
+        const void* before = ctx->chunk_base.p;
+        if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4)) ||
+            (rc = ctx->proxy_sums.ensure((size_t)max_chunks * sizeof(ProxySum))))
+            return rc;
+        if (ctx->chunk_base.p != before) ctx->drop_graphs();
+        HIP_TRY(launch_plan(d_offsets, n_traces, n_samples, d_cfg_of_trace, n_cfgs, ctx->chunk,
+                            max_chunks, ctx->chunk_base.as<uint32_t>(), ctx->err.as<uint32_t>(),
+                            stream));
+        HIP_TRY(launch_proxy_fused(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
+                                   max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
+                                   ctx->proxy_model.as<magus_proxy_model>(),
+                                   ctx->proxy_sums.as<ProxySum>(), d_stats, d_metrics, stream));
+        return MAGUS_OK;
+    }
+    // stepped actuation: the replay writes every step's level, then a pass
+    // over samples and levels
+    if ((rc = ctx->proxy_levels.ensure(std::max<uint64_t>(n_samples, 1))) ||
+        (rc = ctx->proxy_results.ensure((size_t)n_traces * sizeof(magus_result))))
+        return rc;
+    if ((rc = magus_replay(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
+                           d_cfg_of_trace, ctx->proxy_results.as<magus_result>(),
+                           ctx->proxy_levels.as<uint8_t>(), stream)))
+        return rc;
     HIP_TRY(launch_proxy(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
                          max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
                          ctx->proxy_levels.as<uint8_t>(),

@@ -1,6 +1,6 @@
 // Alg. 1 and Alg. 2 for 64 consecutive steps of one trace at once (one step
-// per lane of a wavefront), as 64-bit lane masks.  Shared by the stepped-
-// actuation kernels.
+// per lane of a wavefront), as 64-bit lane masks, and a walker over the
+// blocks of a time chunk.  Shared by the stepped-actuation and proxy kernels.
 #pragma once
 
 #include "magus_internal.h"
@@ -57,6 +57,64 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, ui
     r.HM = lane_ballot(cnt >= c.thr + lane) & valid;
     fps = r.E >> 1;
     return r;
+}
+
+// A time chunk of a trace as one wave sees it: the trace, the chunk's steps
+// [s, e), the first loaded step wbeg (one warm-up block before s when s > 0),
+// the config and a bounds-checked buffer descriptor over samples [wbeg, e).
+struct ChunkView {
+    uint32_t t, s, e, wbeg;
+    uint64_t tbase;
+    DevCfg c;
+    __amdgpu_buffer_rsrc_t rsrc;
+};
+
+__device__ __forceinline__ uint32_t bm_uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ ChunkView chunk_view(
+    const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+    const uint32_t* chunk_base, const DevCfg* cfgs, const uint32_t* cfg_of_trace,
+    uint32_t chunk, uint32_t g)
+{
+    ChunkView v;
+    v.t = trace_of_chunk(chunk_base, n_traces, g, threadIdx.x & 63);
+    v.tbase = offsets[v.t];
+    const uint32_t n = (uint32_t)(offsets[v.t + 1] - v.tbase);
+    v.s = (g - chunk_base[v.t]) * chunk;
+    v.e = min(v.s + chunk, n);
+    v.c = cfgs[cfg_of_trace ? cfg_of_trace[v.t] : 0];
+    v.wbeg = v.s >= 64 ? v.s - 64 : 0;
+    const uint64_t base = (uint64_t)(samples + v.tbase + v.wbeg);
+    const uint64_t base_u = ((uint64_t)bm_uniform((uint32_t)(base >> 32)) << 32) |
+                            bm_uniform((uint32_t)base);
+    v.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base_u, (short)0,
+                                               (int)bm_uniform((v.e - v.wbeg) * 4u),
+                                               0x00020000);
+    return v;
+}
+
+// Walks the blocks of a chunk, calling body(block masks, first step of the
+// block, valid-lane mask, this lane's sample) for every real block (the
+// warm-up block only feeds the FIFOs).  Lanes past the chunk's end read 0.
+template <class Body>
+__device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane, Body&& body) {
+    const uint32_t first_real = v.s >= 64 ? 1u : 0u;
+    const uint32_t nblk = (v.e - v.wbeg + 63) >> 6;
+    uint64_t fps = 0;
+    uint32_t xprev = 0;
+    uint32_t xnext = __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)(lane * 4), 0, 0);
+    for (uint32_t blk = 0; blk < nblk; ++blk) {
+        const uint32_t x = xnext;
+        xnext = __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)(((blk + 1) * 64 + lane) * 4),
+                                                     0, 0);
+        const uint32_t tb = v.wbeg + blk * 64;
+        const uint64_t valid = mask_below(min(64u, v.e - tb));
+        const BlockMasks m = block_masks(x, xprev, tb, valid, v.c, fps, lane);
+        xprev = x;
+        if (blk >= first_real) body(m, tb, valid, x);
+    }
 }
 
 }  // namespace magus

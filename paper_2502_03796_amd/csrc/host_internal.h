@@ -75,6 +75,7 @@ struct magus_ctx {
     magus::DevBuf proxy_levels;   // proxy: decision bytes of the replay
     magus::DevBuf proxy_results;  // proxy: replay results (not returned)
     magus::DevBuf proxy_model;    // proxy: the model in device memory
+    magus::DevBuf proxy_sums;     // proxy: per-chunk summaries of the fused pass
     magus_proxy_model proxy_model_host{};   // ... as last uploaded
     bool proxy_model_set = false;
     // launch shape of the replay chunk kernel (0 = one wave per chunk)

@@ -12,6 +12,18 @@
 // per level, the intervals run there and the sum of max(0, x - cap[level]);
 // for the two static policies the same excess sums at level_max / level_min.
 //
+// Configs that jump to the bound (the paper's rule) take a fused pass that
+// reads each sample once: per chunk, the level before every step follows from
+// the chunk's own decisive steps except for the steps up to the first of them,
+// whose interval runs at the level entering the chunk; those are summed at each
+// of the three possible entering levels and a per-trace fold picks one.
+//   plan        (replay_fold.hip) chunk prefix and data checks
+//   fused chunk one wave per chunk: Alg. 1 / Alg. 2 per 64-step block, the
+//               block's level bits from the carries of ~DN + UP + level, the
+//               excess sums per level -> ProxySum
+//   fused fold  one wave per trace -> magus_proxy_stats
+//   metrics     as below
+// Stepped configs take the general path:
 // Kernels, in stream order (after the replay that wrote the decision bytes):
 //   zero     clears the statistics (no memset node, so the sequence can be
 //            captured into a graph)
@@ -21,6 +33,7 @@
 //            atomic add per non-zero sum per chunk
 //   metrics  one thread per trace: the seven figures of each policy in FP64
 
+#include "block_masks.h"
 #include "proxy_internal.h"
 
 namespace magus {
@@ -196,6 +209,171 @@ __global__ __launch_bounds__(256) void proxy_metrics_kernel(
     out[t] = r;
 }
 
+__device__ __forceinline__ uint32_t sat_sub(uint32_t x, uint32_t cap) {
+    return __builtin_elementwise_sub_sat(x, cap);
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) { return wave_sum(v); }
+
+// Fused pass, one wave per chunk.
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, const magus_proxy_model* __restrict__ model, ProxySum* __restrict__ psums)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
+    if (chunk_base[n_traces + 1] != 0 || g >= chunk_base[n_traces]) return;
+    const ChunkView v = chunk_view(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
+                                   chunk, g);
+    const uint32_t c_lo = model->cap_mbps[v.c.lmin], c_hi = model->cap_mbps[v.c.lmax];
+    const uint32_t c_in = model->cap_mbps[v.c.linit];
+    uint64_t a_pre0 = 0, a_pre1 = 0, a_pre2 = 0, a_lo = 0, a_hi = 0, a_max = 0, a_min = 0;
+    uint32_t ppre = 0, n_lo = 0, n_hi = 0;
+    bool seen = false;        // a decisive step earlier in this chunk
+    uint64_t lvl = 0;         // level bit after the last step (once seen)
+    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t valid, uint32_t x) {
+        const uint64_t UP = m.HM | (m.E & m.R);          // high or +1 -> max
+        const uint64_t DN = (m.E & ~m.R) & ~m.HM;        // -1 executed -> min
+        const uint64_t D = UP | DN;
+        const uint32_t e_hi = sat_sub(x, c_hi), e_lo = sat_sub(x, c_lo);
+        a_max += e_hi;                                   // lanes past the end read 0
+        a_min += e_lo;
+        // level bit before each step: the carries into the bits of ~DN + UP + lvl
+        const uint64_t nd = ~DN;
+        const uint64_t t1 = nd + UP;
+        const uint64_t c1 = t1 < nd;
+        const uint64_t t2 = t1 + lvl;
+        const uint64_t c2 = t2 < t1;
+        const uint64_t C = ~(t2 ^ D);
+        uint64_t det = valid;
+        if (!seen) {
+            // steps up to and including the first decisive step run their
+            // interval at the level entering the chunk
+            const uint32_t p = D ? (uint32_t)__builtin_ctzll(D) : 64u;
+            const uint64_t pre = mask_below(min(p + 1u, 64u)) & valid;
+            if ((pre >> lane) & 1ull) {
+                a_pre0 += e_lo;
+                a_pre1 += e_hi;
+                a_pre2 += sat_sub(x, c_in);
+            }
+            ppre += (uint32_t)__builtin_popcountll(pre);
+            det &= ~pre;
+            seen = D != 0;
+        }
+        const uint64_t hi_m = C & det, lo_m = ~C & det;
+        n_hi += (uint32_t)__builtin_popcountll(hi_m);
+        n_lo += (uint32_t)__builtin_popcountll(lo_m);
+        if ((hi_m >> lane) & 1ull) a_hi += e_hi;
+        if ((lo_m >> lane) & 1ull) a_lo += e_lo;
+        lvl = c1 | c2;                                   // level after the block's last step
+    });
+    a_pre0 = wave_sum64(a_pre0);
+    a_pre1 = wave_sum64(a_pre1);
+    a_pre2 = wave_sum64(a_pre2);
+    a_lo = wave_sum64(a_lo);
+    a_hi = wave_sum64(a_hi);
+    a_max = wave_sum64(a_max);
+    a_min = wave_sum64(a_min);
+    if (lane == 0) {
+        ProxySum r;
+        r.len = v.e - v.s;
+        r.ppre = ppre;
+        r.has_dec = seen ? 1u : 0u;
+        r.end_up = (uint32_t)lvl;
+        r.n_lo = n_lo;
+        r.n_hi = n_hi;
+        r.pre_x[0] = a_pre0;
+        r.pre_x[1] = a_pre1;
+        r.pre_x[2] = a_pre2;
+        r.x_lo = a_lo;
+        r.x_hi = a_hi;
+        r.ex_max = a_max;
+        r.ex_min = a_min;
+        psums[g] = r;
+    }
+}
+
+// Fused fold, one wave per trace; lane j takes chunk j of each group of 64.
+// The level entering chunk j is the end level of the last earlier chunk with
+// a decisive step (else the group's entering level, level_init at the start).
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const ProxySum* __restrict__ psums, const DevCfg* __restrict__ cfgs,
+    const uint32_t* __restrict__ cfg_of_trace, magus_proxy_stats* __restrict__ stats)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
+    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    const uint32_t lmin = c.lmin, lmax = c.lmax, linit = c.linit;
+    const uint32_t k0 = chunk_base[t], k1 = chunk_base[t + 1];
+    uint32_t level = linit;                  // level entering the current group
+    // per lane: intervals and excess at level_min (0), level_max (1), and at
+    // level_init when it is neither (2); excess of the two static policies
+    uint64_t n0 = 0, n1 = 0, n2 = 0, x0 = 0, x1 = 0, x2 = 0, emax = 0, emin = 0;
+    for (uint32_t kb = k0; kb < k1; kb += 64) {
+        const uint32_t k = kb + lane;
+        const bool valid = k < k1;
+        ProxySum P{};
+        if (valid) P = psums[k];
+        const uint64_t E = __ballot(valid && P.has_dec);
+        const uint32_t end_level = P.end_up ? lmax : lmin;
+        const uint64_t before = E & (lane ? (~0ull >> (64 - lane)) : 0ull);
+        const int src = before ? 63 - __builtin_clzll(before) : (int)lane;
+        const uint32_t from_src = (uint32_t)__shfl((int)end_level, src, 64);
+        const uint32_t lin = before ? from_src : level;
+        if (valid) {
+            if (lin == lmin) {
+                n0 += P.ppre;
+                x0 += P.pre_x[0];
+            } else if (lin == lmax) {
+                n1 += P.ppre;
+                x1 += P.pre_x[1];
+            } else {
+                n2 += P.ppre;
+                x2 += P.pre_x[2];
+            }
+            n0 += P.n_lo;
+            x0 += P.x_lo;
+            n1 += P.n_hi;
+            x1 += P.x_hi;
+            emax += P.ex_max;
+            emin += P.ex_min;
+        }
+        if (E) level = (uint32_t)__shfl((int)end_level, 63 - __builtin_clzll(E), 64);
+    }
+    n0 = wave_sum64(n0);
+    n1 = wave_sum64(n1);
+    n2 = wave_sum64(n2);
+    x0 = wave_sum64(x0);
+    x1 = wave_sum64(x1);
+    x2 = wave_sum64(x2);
+    emax = wave_sum64(emax);
+    emin = wave_sum64(emin);
+    // every word of the trace's stats: 0 excess_max, 1 excess_min,
+    // 2 + l steps[l], 2 + 32 + l excess[l]
+    uint64_t* out = reinterpret_cast<uint64_t*>(stats + t);
+    constexpr uint32_t kWords = sizeof(magus_proxy_stats) / 8;
+    for (uint32_t w = lane; w < kWords; w += 64) {
+        uint64_t val;
+        if (w == 0) {
+            val = emax;
+        } else if (w == 1) {
+            val = emin;
+        } else {
+            const bool is_n = w < 2 + MAGUS_PROXY_LEVELS;
+            const uint32_t l = is_n ? w - 2 : w - 2 - MAGUS_PROXY_LEVELS;
+            val = 0;
+            if (l == lmin) val += is_n ? n0 : x0;
+            if (l == lmax) val += is_n ? n1 : x1;
+            if (l == linit && linit != lmin && linit != lmax) val += is_n ? n2 : x2;
+        }
+        out[w] = val;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_proxy(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
@@ -213,6 +391,26 @@ hipError_t launch_proxy(const uint32_t* samples, const uint64_t* offsets, uint32
         proxy_stats_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
             samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, levels, model,
             stats);
+    if (metrics)
+        proxy_metrics_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
+            offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);
+    return hipGetLastError();
+}
+
+hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                              const uint32_t* chunk_base, uint32_t max_chunks,
+                              const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
+                              const magus_proxy_model* model, ProxySum* psums,
+                              magus_proxy_stats* stats, magus_proxy_metrics* metrics,
+                              hipStream_t stream)
+{
+    if (n_traces == 0) return hipSuccess;
+    const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
+    if (blocks)
+        proxy_chunk_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
+            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, model, psums);
+    proxy_fold_kernel<<<(n_traces + kStatsWaves - 1) / kStatsWaves, kStatsWaves * kWave, 0,
+                        stream>>>(n_traces, chunk_base, psums, cfgs, cfg_of_trace, stats);
     if (metrics)
         proxy_metrics_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);

@@ -5,6 +5,36 @@
 
 namespace magus {
 
+// Per-chunk summary of the fused proxy pass (jump-to-bound configs), free of
+// the level entering the chunk: the steps whose interval runs at the entering
+// level (up to and including the chunk's first decisive step) are kept with
+// their excess at each of the three levels a chunk can be entered at
+// (level_min, level_max, level_init); every later step's level is fixed by
+// the chunk's own decisive steps.  80 bytes.
+struct ProxySum {
+    uint32_t len;        // steps in the chunk
+    uint32_t ppre;       // steps whose interval runs at the entering level
+    uint32_t has_dec;    // the chunk has a decisive step
+    uint32_t end_up;     // level after the chunk's last step is level_max (if has_dec)
+    uint32_t n_lo, n_hi; // other steps whose interval runs at level_min / level_max
+    uint64_t pre_x[3];   // excess of the entering-level steps at cap[min], cap[max], cap[init]
+    uint64_t x_lo, x_hi; // excess of the other steps at their level
+    uint64_t ex_max;     // excess of every step at cap[level_max] (always-max policy)
+    uint64_t ex_min;     // ... at cap[level_min] (always-min policy)
+};
+static_assert(sizeof(ProxySum) == 80, "ProxySum layout");
+
+// Fused proxy pass for batches whose configs all jump to the bound: one read
+// of the samples per step after the plan (chunk_base from launch_plan),
+// per-chunk summaries into psums (max_chunks), one wave per trace folds them
+// into stats, and metrics (optional) follow.
+hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
+                              const uint32_t* chunk_base, uint32_t max_chunks,
+                              const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
+                              const magus_proxy_model* model, ProxySum* psums,
+                              magus_proxy_stats* stats, magus_proxy_metrics* metrics,
+                              hipStream_t stream);
+
 // Runs after a replay of the same batch that wrote the decision bytes
 // `levels` with the chunk plan in `chunk_base` (chunk steps per chunk).
 // `model` is in device memory.  stats (n_traces) is cleared and filled;

@@ -62,57 +62,6 @@ __device__ __forceinline__ ClampAdd step_map(const BlockMasks& m, const DevCfg& 
     return f;
 }
 
-struct ChunkView {
-    uint32_t t, s, e, wbeg;
-    uint64_t tbase;
-    DevCfg c;
-    __amdgpu_buffer_rsrc_t rsrc;
-};
-
-__device__ __forceinline__ ChunkView chunk_view(
-    const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
-    const uint32_t* chunk_base, const DevCfg* cfgs, const uint32_t* cfg_of_trace,
-    uint32_t chunk, uint32_t g)
-{
-    ChunkView v;
-    v.t = trace_of_chunk(chunk_base, n_traces, g, threadIdx.x & 63);
-    v.tbase = offsets[v.t];
-    const uint32_t n = (uint32_t)(offsets[v.t + 1] - v.tbase);
-    v.s = (g - chunk_base[v.t]) * chunk;
-    v.e = min(v.s + chunk, n);
-    v.c = cfgs[cfg_of_trace ? cfg_of_trace[v.t] : 0];
-    v.wbeg = v.s >= 64 ? v.s - 64 : 0;
-    const uint64_t base = (uint64_t)(samples + v.tbase + v.wbeg);
-    const uint64_t base_u = ((uint64_t)wave_uniform((uint32_t)(base >> 32)) << 32) |
-                            wave_uniform((uint32_t)base);
-    v.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base_u, (short)0,
-                                               (int)wave_uniform((v.e - v.wbeg) * 4u),
-                                               0x00020000);
-    return v;
-}
-
-// Walks the blocks of a chunk, calling body(block masks, first step of the
-// block, valid-lane mask) for every real block (the warm-up block only feeds
-// the FIFOs).
-template <class Body>
-__device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane, Body&& body) {
-    const uint32_t first_real = v.s >= 64 ? 1u : 0u;
-    const uint32_t nblk = (v.e - v.wbeg + 63) >> 6;
-    uint64_t fps = 0;
-    uint32_t xprev = 0;
-    uint32_t xnext = __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)(lane * 4), 0, 0);
-    for (uint32_t blk = 0; blk < nblk; ++blk) {
-        const uint32_t x = xnext;
-        xnext = __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)(((blk + 1) * 64 + lane) * 4),
-                                                     0, 0);
-        const uint32_t tb = v.wbeg + blk * 64;
-        const uint64_t valid = mask_below(min(64u, v.e - tb));
-        const BlockMasks m = block_masks(x, xprev, tb, valid, v.c, fps, lane);
-        xprev = x;
-        if (blk >= first_real) body(m, tb, valid);
-    }
-}
-
 // Pass 1: the clamp-add map of every chunk.
 __global__ __launch_bounds__(kWaves * kWave) void stepped_map_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
@@ -126,7 +75,7 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_map_kernel(
     const ChunkView v = chunk_view(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
                                    chunk, g);
     ClampAdd F{0, (int32_t)v.c.lmin, (int32_t)v.c.lmax};      // identity
-    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t) {
+    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t, uint32_t) {
         if (((m.E | m.HM)) == 0) return;                        // 64 identity steps
         ClampAdd f = step_map(m, v.c, lane);
         // ordered tree: lane i composes the map of lanes [i, i + 2k) (k doubling)
@@ -179,7 +128,7 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_sum_kernel(
     int32_t x = (int32_t)entering[g];                 // level before the block
     uint64_t lsum = 0;                                 // per lane
     uint32_t trans = 0, th = 0;
-    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid) {
+    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid, uint32_t) {
         int32_t lv;
         if (((m.E | m.HM)) == 0) {
             lv = x;                                    // 64 identity steps

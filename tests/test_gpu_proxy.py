@@ -125,6 +125,33 @@ def test_stepped_configs_and_inner_levels(ctx, oracle_mod, chunk):
     assert (st.cpu().numpy() == st2.cpu().numpy()).all()
 
 
+@pytest.mark.parametrize("chunk", [64, 128, 4096])
+def test_jump_to_bound_with_inner_initial_levels(ctx, oracle_mod, chunk):
+    """The single-pass path (every config jumps to the bound) with initial
+    levels strictly inside the range, so a chunk can be entered at level_init,
+    level_min or level_max, across chunk boundaries of every kind."""
+    traces = mixed_traces(1700 + chunk, LENGTHS)
+    grid = synth.sweep_grid()
+    rng = np.random.default_rng(chunk + 11)
+    cfgs = []
+    for i in rng.integers(0, len(grid), 24):
+        c = dict(grid[int(i)])
+        c["level_init"] = int(rng.integers(0, 17))
+        cfgs.append(c)
+    cfgs.append(default_config(level_min=3, level_max=9, level_init=5))
+    cot = rng.integers(0, len(cfgs), len(traces)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    model = proxy_model()
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, cfgs, model, c)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
+
+
 def test_full_range_samples(ctx, oracle_mod):
     rng = np.random.default_rng(99)
     traces = [rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
