@@ -37,24 +37,40 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, ui
     const uint32_t ap = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)xprev);
     const uint32_t a = lane >= W - 1 ? ac : ap;      // x[t-W+1]
     const uint32_t b = x;
-    const bool rising = b > a;
-    const uint32_t d = max(a, b) - min(a, b);
-    const uint32_t lov = derivative_base(a, b, c.base);
-    const uint32_t m = rising ? c.mu : c.md;
-    // r = d / (W lo) beyond q / 2^16  <=>  d 2^16 > lo (W q)
-    const bool ev = ((uint64_t)d << 16) > (uint64_t)lov * m;
     uint64_t vm = valid;
     if (tb < W - 1) vm &= ~mask_below(W - 1 - tb);
     BlockMasks r;
-    r.E = lane_ballot(ev) & vm;
-    r.R = lane_ballot(rising);
+    if (c.base == 0) {
+        // the smaller sample is the base: a rise is an event iff
+        // b 2^16 > a (2^16 + W q_inc), a fall iff a 2^16 > b (2^16 + W |q_dec|)
+        // (2^16 as an opaque scalar keeps x 2^16 one 32x32->64 multiply)
+        uint32_t k16;
+        asm volatile("s_mov_b32 %0, 0x10000" : "=s"(k16));
+        const uint64_t up = lane_ballot((uint64_t)b * k16 > (uint64_t)a * (65536u + c.mu)) & vm;
+        const uint64_t dn = lane_ballot((uint64_t)a * k16 > (uint64_t)b * (65536u + c.md)) & vm;
+        r.E = up | dn;
+        r.R = up;
+    } else {
+        const bool rising = b > a;
+        const uint32_t d = max(a, b) - min(a, b);
+        const uint32_t lov = derivative_base(a, b, c.base);
+        const uint32_t m = rising ? c.mu : c.md;
+        // r = d / (W base) beyond q / 2^16  <=>  d 2^16 > base (W q)
+        r.E = lane_ballot(((uint64_t)d << 16) > (uint64_t)lov * m) & vm;
+        r.R = lane_ballot(rising);
+    }
     // events among the last H steps (this block's flags and the last H-1 of
-    // the block before), for all 64 steps
+    // the block before), for all 64 steps; with none of them and a non-zero
+    // count threshold no step is high
     const uint64_t B = fps >> (64 - H);
-    const uint64_t nG = ~((r.E << (H - 1)) | B);
-    const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(r.E & 1ull);
-    const uint32_t cnt = bits_below_lane(nG, bits_below_lane(r.E >> 1, acc0));
-    r.HM = lane_ballot(cnt >= c.thr + lane) & valid;
+    if ((r.E | B) == 0 && c.thr != 0) {
+        r.HM = 0;
+    } else {
+        const uint64_t nG = ~((r.E << (H - 1)) | B);
+        const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(r.E & 1ull);
+        const uint32_t cnt = bits_below_lane(nG, bits_below_lane(r.E >> 1, acc0));
+        r.HM = lane_ballot(cnt >= c.thr + lane) & valid;
+    }
     fps = r.E >> 1;
     return r;
 }
