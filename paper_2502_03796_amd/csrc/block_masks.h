@@ -114,22 +114,34 @@ __device__ __forceinline__ ChunkView chunk_view(
 // Walks the blocks of a chunk, calling body(block masks, first step of the
 // block, valid-lane mask, this lane's sample) for every real block (the
 // warm-up block only feeds the FIFOs).  Lanes past the chunk's end read 0.
+// kAhead blocks are loaded ahead of the one being evaluated, so a wave keeps
+// that many loads in flight.
 template <class Body>
 __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane, Body&& body) {
+    constexpr uint32_t kAhead = 8;
     const uint32_t first_real = v.s >= 64 ? 1u : 0u;
     const uint32_t nblk = (v.e - v.wbeg + 63) >> 6;
+    auto load = [&](uint32_t blk) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)((blk * 64 + lane) * 4), 0, 0);
+    };
     uint64_t fps = 0;
     uint32_t xprev = 0;
-    uint32_t xnext = __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)(lane * 4), 0, 0);
-    for (uint32_t blk = 0; blk < nblk; ++blk) {
-        const uint32_t x = xnext;
-        xnext = __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)(((blk + 1) * 64 + lane) * 4),
-                                                     0, 0);
-        const uint32_t tb = v.wbeg + blk * 64;
-        const uint64_t valid = mask_below(min(64u, v.e - tb));
-        const BlockMasks m = block_masks(x, xprev, tb, valid, v.c, fps, lane);
-        xprev = x;
-        if (blk >= first_real) body(m, tb, valid, x);
+    uint32_t buf[kAhead];
+#pragma unroll
+    for (uint32_t k = 0; k < kAhead; ++k) buf[k] = load(k);
+    for (uint32_t b0 = 0; b0 < nblk; b0 += kAhead) {
+#pragma unroll
+        for (uint32_t k = 0; k < kAhead; ++k) {
+            const uint32_t blk = b0 + k;
+            if (blk >= nblk) break;
+            const uint32_t x = buf[k];
+            buf[k] = load(blk + kAhead);        // past the end: reads 0
+            const uint32_t tb = v.wbeg + blk * 64;
+            const uint64_t valid = mask_below(min(64u, v.e - tb));
+            const BlockMasks m = block_masks(x, xprev, tb, valid, v.c, fps, lane);
+            xprev = x;
+            if (blk >= first_real) body(m, tb, valid, x);
+        }
     }
 }
 
