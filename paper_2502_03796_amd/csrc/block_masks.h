@@ -3,6 +3,8 @@
 // blocks of a time chunk.  Shared by the stepped-actuation and proxy kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "magus_internal.h"
 
 namespace magus {
@@ -27,6 +29,10 @@ struct BlockMasks {
 // One block: x = this block's samples, xprev = the block before (lane i holds
 // step tb+i).  fps carries (flags of the block before) >> 1 and is updated.
 // valid = lanes whose step exists; steps before W-1 of the trace never predict.
+// kFull: every lane's step exists and the trace's FIFO is already full (the
+// block does not end the chunk and does not start the trace), so no lane mask
+// is needed.
+template <bool kFull = false>
 __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, uint32_t tb,
                                                   uint64_t valid, const DevCfg& c,
                                                   uint64_t& fps, uint32_t lane)
@@ -37,8 +43,8 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, ui
     const uint32_t ap = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)xprev);
     const uint32_t a = lane >= W - 1 ? ac : ap;      // x[t-W+1]
     const uint32_t b = x;
-    uint64_t vm = valid;
-    if (tb < W - 1) vm &= ~mask_below(W - 1 - tb);
+    uint64_t vm = kFull ? ~0ull : valid;
+    if (!kFull && tb < W - 1) vm &= ~mask_below(W - 1 - tb);
     BlockMasks r;
     if (c.base == 0) {
         // the smaller sample is the base: a rise is an event iff
@@ -69,7 +75,7 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, ui
         const uint64_t nG = ~((r.E << (H - 1)) | B);
         const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(r.E & 1ull);
         const uint32_t cnt = bits_below_lane(nG, bits_below_lane(r.E >> 1, acc0));
-        r.HM = lane_ballot(cnt >= c.thr + lane) & valid;
+        r.HM = lane_ballot(cnt >= c.thr + lane) & (kFull ? ~0ull : valid);
     }
     fps = r.E >> 1;
     return r;
@@ -114,11 +120,10 @@ __device__ __forceinline__ ChunkView chunk_view(
 // Walks the blocks of a chunk, calling body(block masks, first step of the
 // block, valid-lane mask, this lane's sample) for every real block (the
 // warm-up block only feeds the FIFOs).  Lanes past the chunk's end read 0.
-// kAhead blocks are loaded ahead of the one being evaluated, so a wave keeps
-// that many loads in flight.
-template <class Body>
+// A group of kAhead blocks is loaded while the group before it is
+// evaluated, so a wave keeps that many loads in flight.
+template <uint32_t kAhead = 8, class Body>
 __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane, Body&& body) {
-    constexpr uint32_t kAhead = 8;
     const uint32_t first_real = v.s >= 64 ? 1u : 0u;
     const uint32_t nblk = (v.e - v.wbeg + 63) >> 6;
     auto load = [&](uint32_t blk) -> uint32_t {
@@ -126,22 +131,40 @@ __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane
     };
     uint64_t fps = 0;
     uint32_t xprev = 0;
-    uint32_t buf[kAhead];
+    auto step = [&](uint32_t blk, uint32_t x, auto full_tag) {
+        constexpr bool kFull = decltype(full_tag)::value;
+        const uint32_t tb = v.wbeg + blk * 64;
+        const uint64_t valid = kFull ? ~0ull : mask_below(min(64u, v.e - tb));
+        const BlockMasks m = block_masks<kFull>(x, xprev, tb, valid, v.c, fps, lane);
+        xprev = x;
+        if (kFull || blk >= first_real) body(m, tb, valid, x);
+    };
+    // blocks [1, nfull) hold 64 steps each and never start the trace
+    const uint32_t nfull = (v.e - v.wbeg) >> 6;
+    auto group = [&](uint32_t g, const uint32_t (&cur)[kAhead]) {
+        if (g >= 1 && (g + 1) * kAhead <= nfull) {
 #pragma unroll
-    for (uint32_t k = 0; k < kAhead; ++k) buf[k] = load(k);
-    for (uint32_t b0 = 0; b0 < nblk; b0 += kAhead) {
+            for (uint32_t k = 0; k < kAhead; ++k) step(g * kAhead + k, cur[k], std::true_type{});
+        } else {
 #pragma unroll
-        for (uint32_t k = 0; k < kAhead; ++k) {
-            const uint32_t blk = b0 + k;
-            if (blk >= nblk) break;
-            const uint32_t x = buf[k];
-            buf[k] = load(blk + kAhead);        // past the end: reads 0
-            const uint32_t tb = v.wbeg + blk * 64;
-            const uint64_t valid = mask_below(min(64u, v.e - tb));
-            const BlockMasks m = block_masks(x, xprev, tb, valid, v.c, fps, lane);
-            xprev = x;
-            if (blk >= first_real) body(m, tb, valid, x);
+            for (uint32_t k = 0; k < kAhead; ++k)
+                if (g * kAhead + k < nblk) step(g * kAhead + k, cur[k], std::false_type{});
         }
+    };
+    // two alternating groups of kAhead blocks: one is evaluated while the
+    // other is loaded (loads past the end read 0)
+    uint32_t bufA[kAhead], bufB[kAhead];
+#pragma unroll
+    for (uint32_t k = 0; k < kAhead; ++k) bufA[k] = load(k);
+    const uint32_t groups = (nblk + kAhead - 1) / kAhead;
+    for (uint32_t g = 0; g < groups; g += 2) {
+#pragma unroll
+        for (uint32_t k = 0; k < kAhead; ++k) bufB[k] = load((g + 1) * kAhead + k);
+        group(g, bufA);
+        if (g + 1 >= groups) break;
+#pragma unroll
+        for (uint32_t k = 0; k < kAhead; ++k) bufA[k] = load((g + 2) * kAhead + k);
+        group(g + 1, bufB);
     }
 }
 

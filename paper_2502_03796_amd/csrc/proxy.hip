@@ -215,7 +215,16 @@ __device__ __forceinline__ uint32_t sat_sub(uint32_t x, uint32_t cap) {
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) { return wave_sum(v); }
 
-// Fused pass, one wave per chunk.
+// v in the lanes whose bit of the wave-uniform mask is set, else 0
+__device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
+    const uint64_t m = ((uint64_t)uniform((uint32_t)(mask >> 32)) << 32) | uniform((uint32_t)mask);
+    uint32_t r;
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(m));
+    return r;
+}
+
+// Fused pass, one wave per chunk (blocks loaded four at a time: the per-lane
+// sums leave fewer registers for loads in flight than the plain replay has).
 __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -230,45 +239,64 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     const uint32_t c_lo = model->cap_mbps[v.c.lmin], c_hi = model->cap_mbps[v.c.lmax];
     const uint32_t c_in = model->cap_mbps[v.c.linit];
     uint64_t a_pre0 = 0, a_pre1 = 0, a_pre2 = 0, a_lo = 0, a_hi = 0, a_max = 0, a_min = 0;
-    uint32_t ppre = 0, n_lo = 0, n_hi = 0;
+    uint32_t n_lo = 0, n_hi = 0;
     bool seen = false;        // a decisive step earlier in this chunk
-    uint64_t lvl = 0;         // level bit after the last step (once seen)
-    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t valid, uint32_t x) {
+    uint32_t ppre = v.e - v.s;  // steps up to and including the first decisive step
+    uint32_t lvl = 0;         // level bit after the last step (once seen)
+    for_each_block<4>(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid, uint32_t x) {
         const uint64_t UP = m.HM | (m.E & m.R);          // high or +1 -> max
         const uint64_t DN = (m.E & ~m.R) & ~m.HM;        // -1 executed -> min
         const uint64_t D = UP | DN;
         const uint32_t e_hi = sat_sub(x, c_hi), e_lo = sat_sub(x, c_lo);
         a_max += e_hi;                                   // lanes past the end read 0
         a_min += e_lo;
-        // level bit before each step: the carries into the bits of ~DN + UP + lvl
-        const uint64_t nd = ~DN;
-        const uint64_t t1 = nd + UP;
-        const uint64_t c1 = t1 < nd;
-        const uint64_t t2 = t1 + lvl;
-        const uint64_t c2 = t2 < t1;
-        const uint64_t C = ~(t2 ^ D);
+        // level bit before each step: the carries into the bits of
+        // ~DN + UP + lvl, formed from 32-bit halves so that everything
+        // stays in scalar registers
+        const uint32_t n0 = ~(uint32_t)DN, n1 = ~(uint32_t)(DN >> 32);
+        const uint32_t u0 = (uint32_t)UP, u1 = (uint32_t)(UP >> 32);
+        const uint32_t s0 = n0 + u0;
+        const uint32_t k0 = s0 < n0;
+        const uint32_t t0 = s0 + lvl;
+        const uint32_t cin1 = k0 | (t0 < s0);
+        const uint32_t s1 = n1 + u1;
+        const uint32_t k1 = s1 < n1;
+        const uint32_t t1 = s1 + cin1;
+        const uint32_t cout = k1 | (t1 < s1);
+        const uint64_t C = ~((((uint64_t)t1 << 32) | t0) ^ D);
+        // steps whose interval level is known: after the chunk's first
+        // decisive step (the ones up to it are summed after the walk)
         uint64_t det = valid;
         if (!seen) {
-            // steps up to and including the first decisive step run their
-            // interval at the level entering the chunk
-            const uint32_t p = D ? (uint32_t)__builtin_ctzll(D) : 64u;
-            const uint64_t pre = mask_below(min(p + 1u, 64u)) & valid;
-            if ((pre >> lane) & 1ull) {
-                a_pre0 += e_lo;
-                a_pre1 += e_hi;
-                a_pre2 += sat_sub(x, c_in);
+            if (D) {
+                const uint32_t p = (uint32_t)__builtin_ctzll(D);
+                ppre = tb + p + 1 - v.s;
+                det &= ~mask_below(p + 1);
+                seen = true;
+            } else {
+                det = 0;
             }
-            ppre += (uint32_t)__builtin_popcountll(pre);
-            det &= ~pre;
-            seen = D != 0;
         }
         const uint64_t hi_m = C & det, lo_m = ~C & det;
         n_hi += (uint32_t)__builtin_popcountll(hi_m);
         n_lo += (uint32_t)__builtin_popcountll(lo_m);
-        if ((hi_m >> lane) & 1ull) a_hi += e_hi;
-        if ((lo_m >> lane) & 1ull) a_lo += e_lo;
-        lvl = c1 | c2;                                   // level after the block's last step
+        a_hi += lane_sel(hi_m, e_hi);
+        a_lo += lane_sel(lo_m, e_lo);
+        lvl = seen ? cout : 0u;                          // level after the block's last step
     });
+    // the steps up to and including the first decisive step, at each of the
+    // three levels the chunk can be entered at (usually a block or two)
+    {
+        const uint32_t first_real = v.s >= 64 ? 1u : 0u;
+        for (uint32_t b = 0; b * 64 < ppre; ++b) {
+            const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(
+                v.rsrc, (int)(((first_real + b) * 64 + lane) * 4), 0, 0);
+            const uint64_t in = mask_below(min(ppre - b * 64, 64u));
+            a_pre0 += lane_sel(in, sat_sub(x, c_lo));
+            a_pre1 += lane_sel(in, sat_sub(x, c_hi));
+            a_pre2 += lane_sel(in, sat_sub(x, c_in));
+        }
+    }
     a_pre0 = wave_sum64(a_pre0);
     a_pre1 = wave_sum64(a_pre1);
     a_pre2 = wave_sum64(a_pre2);
