@@ -194,25 +194,18 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_profiling(False)
+    # the chunk kernel of every timed step, between the event-record nodes
+    # that bracket it inside the graph (on the launch stream)
     kms, launches = ctx.kernel_time(magus.KERNEL_REPLAY)
     ctx.check()
     ctx.set_graphs(False)
-    # the chunk kernel alone, timed with events around it on its stream
-    ctx.set_profiling(True)
-    ctx.kernel_time(magus.KERNEL_REPLAY)
-    for _ in range(args.steps):
-        ctx.replay(s, o, cfg_arr, results=results)
-    torch.cuda.synchronize()
-    ctx.set_profiling(False)
-    kchunk, nchunk = ctx.kernel_time(magus.KERNEL_REPLAY)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n_samples / (ms_per_step * 1e-3)
-    graph_ms = kms / max(launches, 1)
-    avg_kernel_ms = kchunk / max(nchunk, 1)
+    avg_kernel_ms = kms / max(launches, 1)
     bytes_per_launch = 4.0 * n_samples            # one read of every uint32 sample
     achieved = bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9
-    log(f"replay: {ms_per_step:.4f} ms/step (graph {graph_ms:.4f} ms on the stream, eager "
-        f"{eager_ms:.4f} ms/step), chunk kernel {avg_kernel_ms:.4f} ms ({achieved:.0f} GB/s), "
+    log(f"replay: {ms_per_step:.4f} ms/step (eager {eager_ms:.4f} ms/step), chunk kernel "
+        f"{avg_kernel_ms:.4f} ms ({achieved:.0f} GB/s, {launches} timed launches), "
         f"{value:.3e} samples/s")
 
     # parity spot check of the timed launch against the oracle
@@ -294,6 +287,32 @@ def main():
             tot += len(x)
         extra["fp64_side_form"] = {"pred_disagreement_rate": dp / tot,
                                    "level_disagreement_rate": dl / tot, "steps": tot}
+
+        # context for the roofline: plain torch kernels over the same bytes (a
+        # max reduction reads them; a device copy reads and writes them)
+        def torch_ms(fn):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 10
+        dst = torch.empty_like(s)
+        amax_ms = torch_ms(lambda: torch.amax(s))
+        copy_ms = torch_ms(lambda: dst.copy_(s))
+        del dst
+        extra["read_reference"] = {
+            "amax": {"kernel": "torch.amax over the bulk samples", "ms": amax_ms,
+                     "read_gb_per_s": bytes_per_launch / amax_ms / 1e6},
+            "copy": {"kernel": "device copy of the bulk samples", "ms": copy_ms,
+                     "read_plus_write_gb_per_s": 2 * bytes_per_launch / copy_ms / 1e6}}
+        log(f"  torch.amax over the same bytes: {amax_ms:.4f} ms "
+            f"({bytes_per_launch / amax_ms / 1e6:.0f} GB/s); device copy {copy_ms:.4f} ms "
+            f"({2 * bytes_per_launch / copy_ms / 1e6:.0f} GB/s read + write)")
 
         log("stepped actuation (up 2 rungs, down 1 rung) on the bulk workload ...")
         scfg = synth.default_config(up_step=2, down_step=1)

@@ -146,7 +146,9 @@ uint32_t magus_ctx_get_persistent(const magus_ctx* ctx);
  * graph the first time it sees a given set of arguments (pointers, sizes,
  * config count, chunk and launch shape) and relaunches that graph on later
  * calls with the same set; the config table is uploaded outside the graph.
- * Up to 8 graphs are kept per context.
+ * Up to 8 graphs are kept per context.  Kernel timing (below) works inside
+ * the graph: two event-record nodes bracket the chunk kernel and each launch
+ * points them at that launch's events.
  */
 int magus_ctx_set_graphs(magus_ctx* ctx, int enable);
 

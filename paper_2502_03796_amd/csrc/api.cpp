@@ -89,6 +89,28 @@ void DevBuf::release() {
     cap = 0;
 }
 
+thread_local std::vector<hipGraphNode_t>* capture_marks = nullptr;
+
+hipError_t record_timing_event(hipEvent_t ev, hipStream_t stream) {
+    if (!ev) return hipSuccess;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &st);
+    if (e != hipSuccess) return e;
+    if (st == hipStreamCaptureStatusNone) return hipEventRecord(ev, stream);
+    if (st != hipStreamCaptureStatusActive) return hipErrorStreamCaptureInvalidated;
+    unsigned long long id = 0;
+    hipGraph_t graph = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t n_deps = 0;
+    e = hipStreamGetCaptureInfo_v2(stream, &st, &id, &graph, &deps, &n_deps);
+    hipGraphNode_t node = nullptr;
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&node, graph, deps, n_deps, ev);
+    if (e == hipSuccess)
+        e = hipStreamUpdateCaptureDependencies(stream, &node, 1, hipStreamSetCaptureDependencies);
+    if (e == hipSuccess && capture_marks) capture_marks->push_back(node);
+    return e;
+}
+
 }  // namespace magus
 
 std::pair<hipEvent_t, hipEvent_t> magus_ctx::timing_pair(int kernel) {
@@ -112,8 +134,10 @@ std::pair<hipEvent_t, hipEvent_t> magus_ctx::timing_pair(int kernel) {
 }
 
 void magus_ctx::drop_graphs() {
-    for (auto& e : graphs)
+    for (auto& e : graphs) {
         if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
     graphs.clear();
 }
 
@@ -209,7 +233,8 @@ int magus_ctx_destroy(magus_ctx* ctx) {
         (void)hipDeviceSynchronize();
         for (DevBuf* b : {&ctx->err, &ctx->chunk_base, &ctx->sums, &ctx->fix, &ctx->cfgs,
                           &ctx->keys, &ctx->sweep_tab, &ctx->step_funcs, &ctx->step_enter,
-                          &ctx->step_sums, &ctx->status})
+                          &ctx->step_sums, &ctx->step_masks, &ctx->status, &ctx->proxy_levels,
+                          &ctx->proxy_results, &ctx->proxy_model, &ctx->proxy_sums})
             b->release();
         for (auto& r : ctx->recorded)
             for (auto& pr : r) {
@@ -218,6 +243,8 @@ int magus_ctx_destroy(magus_ctx* ctx) {
             }
         for (auto ev : ctx->ev_pool) (void)hipEventDestroy(ev);
         ctx->drop_graphs();
+        for (auto ev : ctx->graph_ev)
+            if (ev) (void)hipEventDestroy(ev);
         if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     }
     delete ctx;
@@ -358,20 +385,22 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     bool stepped = false, any_base = false;
     int rc = stage_configs(ctx, h_cfgs, n_cfgs, stream, &stepped, &any_base);
     if (rc != MAGUS_OK) return rc;
-    const void* before[6] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p,
-                             ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
+    const void* before[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p, ctx->step_funcs.p,
+                             ctx->step_enter.p, ctx->step_sums.p, ctx->step_masks.p};
     if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4))) return rc;
     if (stepped) {
         if ((rc = ctx->step_funcs.ensure((size_t)max_chunks * sizeof(ClampAdd))) ||
             (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
-            (rc = ctx->step_sums.ensure((size_t)max_chunks * sizeof(StepSum))))
+            (rc = ctx->step_sums.ensure((size_t)max_chunks * sizeof(StepSum))) ||
+            (rc = ctx->step_masks.ensure(
+                 (size_t)stepped_mask_blocks(n_samples, n_traces) * 3 * sizeof(uint64_t))))
             return rc;
     } else {
         if ((rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum)))) return rc;
         if (d_levels && (rc = ctx->fix.ensure((size_t)max_chunks * sizeof(ChunkFix)))) return rc;
     }
-    const void* after[6] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p,
-                            ctx->step_funcs.p, ctx->step_enter.p, ctx->step_sums.p};
+    const void* after[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p, ctx->step_funcs.p,
+                            ctx->step_enter.p, ctx->step_sums.p, ctx->step_masks.p};
     if (std::memcmp(before, after, sizeof before) != 0) ctx->drop_graphs();
     auto launch = [&](hipStream_t q, hipEvent_t e0, hipEvent_t e1) {
         if (stepped)
@@ -379,8 +408,8 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(), n_cfgs,
                 d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(), max_chunks,
                 ctx->step_funcs.as<ClampAdd>(), ctx->step_enter.as<uint32_t>(),
-                ctx->step_sums.as<StepSum>(), d_results, d_levels, ctx->err.as<uint32_t>(), q,
-                e0, e1);
+                ctx->step_sums.as<StepSum>(), ctx->step_masks.as<uint64_t>(), d_results,
+                d_levels, ctx->err.as<uint32_t>(), q, e0, e1);
         return launch_replay(d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(),
                              n_cfgs, d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(),
                              ctx->sums.as<ChunkSum>(), max_chunks,
@@ -394,13 +423,14 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         return MAGUS_OK;
     }
     // hipGraph path: the kernels of a call with these exact arguments are
-    // captured once and relaunched (timing events then bracket the graph)
+    // captured once and relaunched
     const std::vector<uint64_t> key = {
         (uint64_t)d_samples, n_samples, (uint64_t)d_offsets, n_traces, n_cfgs,
         (uint64_t)d_cfg_of_trace, (uint64_t)d_results, (uint64_t)d_levels, ctx->chunk,
         ctx->persistent_blocks, (uint64_t)ctx->cfgs.p, (uint64_t)ctx->chunk_base.p,
         (uint64_t)ctx->sums.p, (uint64_t)ctx->fix.p, (uint64_t)stepped, (uint64_t)any_base,
-        (uint64_t)ctx->step_funcs.p, (uint64_t)ctx->step_enter.p, (uint64_t)ctx->step_sums.p};
+        (uint64_t)ctx->step_funcs.p, (uint64_t)ctx->step_enter.p, (uint64_t)ctx->step_sums.p,
+        (uint64_t)ctx->step_masks.p};
     hipGraphExec_t exec = nullptr;
     for (size_t i = 0; i < ctx->graphs.size(); ++i)
         if (ctx->graphs[i].key == key) {
@@ -408,31 +438,61 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
             std::rotate(ctx->graphs.begin() + i, ctx->graphs.begin() + i + 1, ctx->graphs.end());
             break;
         }
+    magus_ctx::GraphEntry* entry = nullptr;
     if (!exec) {
         if (!ctx->cap_stream)
             HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        for (auto& ev : ctx->graph_ev)
+            if (!ev) HIP_TRY(hipEventCreate(&ev));
+        // the chunk kernel is bracketed by two event-record nodes; each
+        // launch points them at the events of that launch
+        std::vector<hipGraphNode_t> marks;
         HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = launch(ctx->cap_stream, nullptr, nullptr);
+        magus::capture_marks = &marks;
+        const hipError_t le = launch(ctx->cap_stream, ctx->graph_ev[0], ctx->graph_ev[1]);
+        magus::capture_marks = nullptr;
         hipGraph_t graph = nullptr;
         const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (le != hipSuccess || ce != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
-            return fail(MAGUS_EDEVICE, "graph capture: %s",
+            return fail(MAGUS_EDEVICE, "graph capture (%s): %s",
+                        le != hipSuccess ? "launch" : "end",
                         hipGetErrorString(le != hipSuccess ? le : ce));
         }
-        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) return fail(MAGUS_EDEVICE, "hipGraphInstantiate: %s",
-                                          hipGetErrorString(ie));
+        if (marks.size() != 2) {
+            (void)hipGraphDestroy(graph);
+            return fail(MAGUS_EDEVICE, "graph capture: %zu timing nodes instead of 2",
+                        marks.size());
+        }
+        magus_ctx::GraphEntry fresh;
+        fresh.key = key;
+        fresh.graph = graph;
+        fresh.rec[0] = marks[0];
+        fresh.rec[1] = marks[1];
+        const hipError_t ge = hipGraphInstantiate(&fresh.exec, graph, nullptr, nullptr, 0);
+        if (ge != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(MAGUS_EDEVICE, "graph instantiate: %s", hipGetErrorString(ge));
+        }
         if (ctx->graphs.size() >= 8) {
             (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+            (void)hipGraphDestroy(ctx->graphs.front().graph);
             ctx->graphs.erase(ctx->graphs.begin());
         }
-        ctx->graphs.push_back({key, exec});
+        ctx->graphs.push_back(fresh);
+        entry = &ctx->graphs.back();
+        exec = entry->exec;
+    } else {
+        entry = &ctx->graphs.back();       // the hit was rotated to the back
     }
-    if (tp.first) HIP_TRY(hipEventRecord(tp.first, stream));
+    for (int k = 0; k < 2; ++k) {
+        hipEvent_t ev = k == 0 ? tp.first : tp.second;
+        const hipError_t se = hipGraphExecEventRecordNodeSetEvent(exec, entry->rec[k],
+                                                                  ev ? ev : ctx->graph_ev[k]);
+        if (se != hipSuccess)
+            return fail(MAGUS_EDEVICE, "graph timing node %d: %s", k, hipGetErrorString(se));
+    }
     HIP_TRY(hipGraphLaunch(exec, stream));
-    if (tp.second) HIP_TRY(hipEventRecord(tp.second, stream));
     return MAGUS_OK;
 }
 

@@ -65,6 +65,7 @@ struct magus_ctx {
     magus::DevBuf step_funcs;   // stepped replay: ClampAdd per chunk
     magus::DevBuf step_enter;   // stepped replay: entering level per chunk
     magus::DevBuf step_sums;    // stepped replay: StepSum per chunk
+    magus::DevBuf step_masks;   // stepped replay: 3 x 8 B of step masks per block
     std::vector<magus::DevCfg> cfg_host;        // last uploaded table
     std::vector<magus_config> cfg_raw;          // ... and the configs it came from
     magus::DevBuf keys;         // sweep: arg-min keys + status
@@ -85,8 +86,11 @@ struct magus_ctx {
     hipStream_t cap_stream = nullptr;
     struct GraphEntry {
         std::vector<uint64_t> key;
+        hipGraph_t graph = nullptr;             // kept: its record nodes are retargeted
         hipGraphExec_t exec = nullptr;
+        hipGraphNode_t rec[2] = {nullptr, nullptr};   // event records around the chunk kernel
     };
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};      // record targets while not timing
     std::vector<GraphEntry> graphs;          // most recent last
     void drop_graphs();
     // kernel timing: event pairs recorded around the dominant kernel of a call

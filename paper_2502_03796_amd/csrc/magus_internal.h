@@ -1,6 +1,8 @@
 // Internal types shared by the host side and the gfx950 kernels of libmagus.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -58,6 +60,13 @@ __device__ __forceinline__ uint32_t trace_of_chunk(const uint32_t* chunk_base,
     return lo;
 }
 
+__device__ int llvm_writelane(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// lane `lane` of `dst` := v (lane wave-uniform)
+__device__ __forceinline__ void writelane_into(uint32_t& dst, uint32_t v, uint32_t lane) {
+    dst = (uint32_t)llvm_writelane((int)v, (int)lane, (int)dst);
+}
+
 // Summary of one time chunk of one trace, computed without knowing the level
 // entering the chunk (taken as level_min for the bit vector).  32 bytes.
 struct ChunkSum {
@@ -101,9 +110,18 @@ struct StepSum {
     uint32_t ticks_high;
 };
 
+// Records a timing event on `stream` (nothing when ev is null).  Under stream
+// capture it adds an event-record node after the work captured so far and
+// makes the work captured next depend on it; each launch of the graph can
+// then point the node at an event of its own.  The nodes added are appended
+// to *capture_marks while that is set (by the thread that captures).
+hipError_t record_timing_event(hipEvent_t ev, hipStream_t stream);
+extern thread_local std::vector<hipGraphNode_t>* capture_marks;
+
 // Kernel launchers (replay.hip / sweep.hip / serve.hip).  When ev0/ev1 are
 // not null they are recorded on `stream` right before and after the dominant
-// kernel of the call (the chunk, sweep or serve-step kernel).
+// kernel of the call (the chunk, sweep or serve-step kernel); the replay
+// launchers record them with record_timing_event.
 hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
                          uint32_t n_traces, const DevCfg* cfgs, uint32_t n_cfgs,
                          const uint32_t* cfg_of_trace, uint32_t chunk, uint32_t* chunk_base,
@@ -126,16 +144,24 @@ hipError_t launch_fold(const uint64_t* offsets, uint32_t n_traces, const uint32_
 hipError_t launch_fixup(uint32_t n_traces, const uint32_t* chunk_base, const ChunkFix* fix,
                         uint32_t max_chunks, uint8_t* levels, hipStream_t stream);
 
-// Replay for configs with stepped actuation (stepped.hip): two passes over
-// each chunk, the first composing the chunk's clamp-add map, the second
-// accumulating with the entering level that the per-trace fold derived.
+// Replay for configs with stepped actuation (stepped.hip): pass 1 reads the
+// samples once and writes the chunk's clamp-add map and the masks of the
+// steps that can move the level (`masks`: three arrays of
+// stepped_mask_blocks() words); pass 2 accumulates with the entering level
+// that the per-trace fold derived, from the masks, or from the samples when
+// `levels` is not null.
 hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
                                  uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                                  uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
-                                 uint32_t* entering, StepSum* sums, magus_result* results,
-                                 uint8_t* levels, uint32_t* err, hipStream_t stream,
-                                 hipEvent_t ev0, hipEvent_t ev1);
+                                 uint32_t* entering, StepSum* sums, uint64_t* masks,
+                                 magus_result* results, uint8_t* levels, uint32_t* err,
+                                 hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+// Length of each of the three block-mask arrays of the stepped replay
+// (3 x this many uint64 words of scratch): one slot per 64-step block.
+inline uint64_t stepped_mask_blocks(uint64_t n_samples, uint32_t n_traces) {
+    return n_samples / 64 + n_traces + 1;
+}
 
 // Counter readings to MB/s samples (frontend.hip).
 hipError_t launch_counters(const uint64_t* counts, const uint64_t* ts, const uint64_t* offsets,

@@ -25,13 +25,6 @@
 
 namespace magus {
 
-__device__ int llvm_writelane(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-
-// lane `lane` of `dst` := v
-__device__ __forceinline__ void writelane_into(uint32_t& dst, uint32_t v, uint32_t lane) {
-    dst = (uint32_t)llvm_writelane((int)v, (int)lane, (int)dst);
-}
-
 namespace {
 
 constexpr int kChunkWavesPerBlock = 4;
@@ -399,7 +392,7 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
     (void)launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk, max_chunks,
                       chunk_base, err, stream);
     uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
-    if (ev0) (void)hipEventRecord(ev0, stream);
+    if (hipError_t e = record_timing_event(ev0, stream); e != hipSuccess) return e;
     auto go = [&](auto levels_tag, auto base_tag) {
         constexpr bool kL = decltype(levels_tag)::value, kB = decltype(base_tag)::value;
         ChunkFix* f = kL ? fix : nullptr;
@@ -421,7 +414,7 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
             else go(std::false_type{}, std::false_type{});
         }
     }
-    if (ev1) (void)hipEventRecord(ev1, stream);
+    if (hipError_t e = record_timing_event(ev1, stream); e != hipSuccess) return e;
     (void)launch_fold(offsets, n_traces, chunk_base, sums, cfgs, cfg_of_trace, results,
                       levels ? fix : nullptr, stream);
     if (levels && blocks)

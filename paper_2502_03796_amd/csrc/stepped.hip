@@ -10,11 +10,21 @@
 //   +1 / -1, step 0 -> constant max / min
 //   otherwise       -> identity                   (a = 0,  lo = min, hi = max)
 // Clamp-add maps are closed under composition (see compose()), so a time
-// chunk has one map.  Pass 1 composes each chunk's map with a wave-wide tree
-// over the 64 steps of every block; a per-trace fold applies the maps in order
-// to find the level entering every chunk; pass 2 replays each chunk again with
-// its entering level, turning the per-step maps into levels with a wave-wide
-// inclusive scan, and accumulates the level sum and transitions.
+// chunk has one map.
+//
+// Pass 1 streams the samples once.  Per 64-step block it keeps only the
+// steps that can move the level, as three lane masks (raise by up_step, lower
+// by down_step, set level_max at the start of a run of high steps), parks
+// them in lane j of six registers for block j of a group of 64 blocks, and
+// per group writes them out (24 B per block) and composes the group's map:
+// lane j walks the set bits of its block, then a wave-wide tree composes the
+// 64 block maps.  A per-trace fold applies the chunk maps in order to find
+// the level entering every chunk.  Pass 2 reads only the masks: lane j
+// composes its block's map again, an inclusive wave scan of the block maps
+// gives the level entering every block, and lane j walks its block once more
+// to add up levels and count transitions.  When the per-step decision bytes
+// are asked for, pass 2 instead replays the samples of the chunk from its
+// entering level (a wave-wide scan of the per-step maps of every block).
 
 #include "block_masks.h"
 
@@ -62,38 +72,223 @@ __device__ __forceinline__ ClampAdd step_map(const BlockMasks& m, const DevCfg& 
     return f;
 }
 
-// Pass 1: the clamp-add map of every chunk.
-__global__ __launch_bounds__(kWaves * kWave) void stepped_map_kernel(
+// The steps of a block that can move the level, as disjoint lane masks: raise
+// by up_step, lower by down_step, or set level_max (hs: a high step that does
+// not follow another high step; a high step after one leaves level_max where
+// it is).  hm_before: bit 0 = the step before the block was high.
+struct StepMasks {
+    uint64_t hs, up, dn;
+};
+
+__device__ __forceinline__ StepMasks step_masks(const BlockMasks& m, uint64_t hm_before) {
+    StepMasks s;
+    s.hs = m.HM & ~((m.HM << 1) | hm_before);
+    const uint64_t ev = m.E & ~m.HM;
+    s.up = ev & m.R;
+    s.dn = ev & ~m.R;
+    return s;
+}
+
+// Rung moves of a config: a jump to the bound is a move of 64 rungs (beyond
+// any range), so every kind of step is one clamped add.
+struct Moves {
+    int32_t up, down, lmin, lmax;
+};
+
+__device__ __forceinline__ Moves moves_of(const DevCfg& c) {
+    return Moves{c.up ? (int32_t)c.up : 64, c.down ? (int32_t)c.down : 64, (int32_t)c.lmin,
+                 (int32_t)c.lmax};
+}
+
+// The rung move of bit p of a block's masks (p is one of its set bits).
+__device__ __forceinline__ int32_t move_at(const StepMasks& s, uint32_t p, const Moves& mv) {
+    const bool hs = (s.hs >> p) & 1ull;
+    const bool up = (s.up >> p) & 1ull;
+    return hs ? 64 : (up ? mv.up : -mv.down);
+}
+
+// The map of one block: its moves composed in step order.
+__device__ __forceinline__ ClampAdd block_map(const StepMasks& s, const Moves& mv) {
+    ClampAdd f{0, mv.lmin, mv.lmax};
+    uint64_t c = s.hs | s.up | s.dn;
+    while (c) {
+        const uint32_t p = (uint32_t)__builtin_ctzll(c);
+        c &= c - 1;
+        const int32_t d = move_at(s, p, mv);
+        f.a += d;
+        f.lo = min(max(f.lo + d, mv.lmin), mv.lmax);
+        f.hi = min(max(f.hi + d, mv.lmin), mv.lmax);
+    }
+    return f;
+}
+
+// Level sum and transitions of steps [0, n) of a block entered at level x.
+__device__ __forceinline__ void block_walk(const StepMasks& s, const Moves& mv, int32_t x,
+                                           uint32_t n, uint32_t& lsum, uint32_t& trans) {
+    uint64_t c = s.hs | s.up | s.dn;
+    int32_t lv = x;
+    uint32_t last = 0;
+    while (c) {
+        const uint32_t p = (uint32_t)__builtin_ctzll(c);
+        c &= c - 1;
+        lsum += (uint32_t)lv * (p - last);
+        const int32_t nl = min(max(lv + move_at(s, p, mv), mv.lmin), mv.lmax);
+        trans += nl != lv;
+        lv = nl;
+        last = p;
+    }
+    lsum += (uint32_t)lv * (n - last);
+}
+
+// The masks of 64 blocks, block j in lane j, as three pairs of halves.
+struct ParkedMasks {
+    uint32_t hs0, hs1, up0, up1, dn0, dn1;
+    __device__ __forceinline__ StepMasks get() const {
+        return StepMasks{((uint64_t)hs1 << 32) | hs0, ((uint64_t)up1 << 32) | up0,
+                         ((uint64_t)dn1 << 32) | dn0};
+    }
+};
+
+// Ordered wave reduction: the composition of the maps of lanes 0..63 (lane 0
+// first), wave-uniform.
+__device__ __forceinline__ ClampAdd wave_compose(ClampAdd f, uint32_t lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        ClampAdd o;
+        o.a = __shfl_down(f.a, d, 64);
+        o.lo = __shfl_down(f.lo, d, 64);
+        o.hi = __shfl_down(f.hi, d, 64);
+        if (lane + d < 64) f = compose(f, o);
+    }
+    ClampAdd r;
+    r.a = __builtin_amdgcn_readfirstlane(f.a);
+    r.lo = __builtin_amdgcn_readfirstlane(f.lo);
+    r.hi = __builtin_amdgcn_readfirstlane(f.hi);
+    return r;
+}
+
+// Inclusive wave scan: lane i gets the composition of the maps of lanes 0..i.
+__device__ __forceinline__ ClampAdd wave_scan(ClampAdd f, uint32_t lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        ClampAdd o;
+        o.a = __shfl_up(f.a, d, 64);
+        o.lo = __shfl_up(f.lo, d, 64);
+        o.hi = __shfl_up(f.hi, d, 64);
+        if (lane >= (uint32_t)d) f = compose(o, f);
+    }
+    return f;
+}
+
+// Index of the first block of a chunk in the mask arrays: blocks of one trace
+// start 64 steps apart, so (absolute first step) / 64 + trace is one-to-one
+// over all blocks of a batch and stays below n_samples / 64 + n_traces.
+__device__ __forceinline__ uint64_t first_block(uint64_t tbase, uint32_t s, uint32_t t) {
+    return (tbase + s) / 64 + t;
+}
+
+// Pass 1: masks of every block, the map and the high steps of every chunk.
+__global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
-    uint32_t chunk, ClampAdd* __restrict__ funcs)
+    uint32_t chunk, uint64_t n_blocks, ClampAdd* __restrict__ funcs,
+    StepSum* __restrict__ sums, uint64_t* __restrict__ masks)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x * kWaves + wave_uniform(threadIdx.x >> 6);
     if (g >= chunk_base[n_traces]) return;
     const ChunkView v = chunk_view(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
                                    chunk, g);
-    ClampAdd F{0, (int32_t)v.c.lmin, (int32_t)v.c.lmax};      // identity
-    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t, uint32_t) {
-        if (((m.E | m.HM)) == 0) return;                        // 64 identity steps
-        ClampAdd f = step_map(m, v.c, lane);
-        // ordered tree: lane i composes the map of lanes [i, i + 2k) (k doubling)
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            ClampAdd o;
-            o.a = __shfl_down(f.a, d, 64);
-            o.lo = __shfl_down(f.lo, d, 64);
-            o.hi = __shfl_down(f.hi, d, 64);
-            if (lane + d < 64) f = compose(f, o);
+    const Moves mv = moves_of(v.c);
+    uint64_t* out = masks + first_block(v.tbase, v.s, v.t);
+    ClampAdd F{0, mv.lmin, mv.lmax};                   // identity
+    uint32_t th = 0, j = 0;
+    uint64_t hm_before = 0;
+    ParkedMasks pk{0, 0, 0, 0, 0, 0};
+    auto flush = [&](uint32_t cnt) {
+        const StepMasks s = pk.get();
+        if (lane < cnt) {
+            out[lane] = s.hs;
+            out[n_blocks + lane] = s.up;
+            out[2 * n_blocks + lane] = s.dn;
         }
-        ClampAdd blk;
-        blk.a = __builtin_amdgcn_readfirstlane(f.a);
-        blk.lo = __builtin_amdgcn_readfirstlane(f.lo);
-        blk.hi = __builtin_amdgcn_readfirstlane(f.hi);
-        F = compose(F, blk);
+        out += cnt;
+        F = compose(F, wave_compose(block_map(s, mv), lane));
+        pk = ParkedMasks{0, 0, 0, 0, 0, 0};
+    };
+    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t, uint32_t) {
+        th += (uint32_t)__popcll(m.HM);
+        if ((m.E | m.HM) != 0) {
+            const StepMasks s = step_masks(m, hm_before);
+            writelane_into(pk.hs0, (uint32_t)s.hs, j);
+            writelane_into(pk.hs1, (uint32_t)(s.hs >> 32), j);
+            writelane_into(pk.up0, (uint32_t)s.up, j);
+            writelane_into(pk.up1, (uint32_t)(s.up >> 32), j);
+            writelane_into(pk.dn0, (uint32_t)s.dn, j);
+            writelane_into(pk.dn1, (uint32_t)(s.dn >> 32), j);
+        }
+        hm_before = m.HM >> 63;
+        if (++j == 64) {
+            flush(64);
+            j = 0;
+        }
     });
-    if (lane == 0) funcs[g] = F;
+    if (j) flush(j);
+    if (lane == 0) {
+        funcs[g] = F;
+        sums[g].ticks_high = th;
+    }
+}
+
+// Pass 2 from the masks: level sum and transitions of every chunk.
+__global__ __launch_bounds__(kWaves * kWave) void stepped_walk_kernel(
+    const uint64_t* __restrict__ offsets, uint32_t n_traces,
+    const uint32_t* __restrict__ chunk_base, const DevCfg* __restrict__ cfgs,
+    const uint32_t* __restrict__ cfg_of_trace, uint32_t chunk, uint64_t n_blocks,
+    const uint32_t* __restrict__ entering, const uint64_t* __restrict__ masks,
+    StepSum* __restrict__ sums)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = blockIdx.x * kWaves + wave_uniform(threadIdx.x >> 6);
+    if (g >= chunk_base[n_traces]) return;
+    const uint32_t t = trace_of_chunk(chunk_base, n_traces, g, lane);
+    const uint64_t tbase = offsets[t];
+    const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
+    const uint32_t s = (g - chunk_base[t]) * chunk;
+    const uint32_t len = min(s + chunk, n) - s;
+    const Moves mv = moves_of(cfgs[cfg_of_trace ? cfg_of_trace[t] : 0]);
+    const uint64_t* in = masks + first_block(tbase, s, t);
+    const uint32_t nblk = (len + 63) >> 6;
+    int32_t x = (int32_t)entering[g];                  // level before the group
+    uint32_t lsum = 0, trans = 0;
+    for (uint32_t b0 = 0; b0 < nblk; b0 += 64) {
+        const uint32_t j = b0 + lane;
+        StepMasks sm{0, 0, 0};
+        uint32_t steps = 0;
+        if (j < nblk) {
+            sm.hs = in[j];
+            sm.up = in[n_blocks + j];
+            sm.dn = in[2 * n_blocks + j];
+            steps = min(64u, len - 64 * j);
+        }
+        const ClampAdd incl = wave_scan(block_map(sm, mv), lane);
+        int32_t after = apply(incl, x);                // level after this lane's block
+        int32_t before = __shfl_up(after, 1, 64);
+        if (lane == 0) before = x;
+        block_walk(sm, mv, before, steps, lsum, trans);
+        x = __builtin_amdgcn_readlane(after, 63);
+    }
+    uint64_t ls = lsum;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        ls += __shfl_xor(ls, d, 64);
+        trans += __shfl_xor(trans, d, 64);
+    }
+    if (lane == 0) {
+        sums[g].level_sum = ls;
+        sums[g].transitions = trans;
+    }
 }
 
 // Fold 1: the level entering every chunk.
@@ -111,9 +306,8 @@ __global__ __launch_bounds__(256) void stepped_enter_kernel(
     }
 }
 
-// Pass 2: levels, sums and (optionally) decision bytes of every chunk.
-template <bool kLevels>
-__global__ __launch_bounds__(kWaves * kWave) void stepped_sum_kernel(
+// Pass 2 from the samples: levels, sums and decision bytes of every chunk.
+__global__ __launch_bounds__(kWaves * kWave) void stepped_levels_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
@@ -153,15 +347,13 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_sum_kernel(
             trans += lv != before;
         }
         th += (uint32_t)__popcll(m.HM);
-        if constexpr (kLevels) {
-            if (ok) {
-                const bool hb = (m.HM >> lane) & 1ull;
-                const bool ev = (m.E >> lane) & 1ull;
-                const bool up = (m.R >> lane) & 1ull;
-                const uint32_t pr = ev ? (up ? 2u : 0u) : 1u;
-                levels[v.tbase + tb + lane] = (uint8_t)((uint32_t)lv | ((uint32_t)hb << 5) |
-                                                        (pr << 6));
-            }
+        if (ok) {
+            const bool hb = (m.HM >> lane) & 1ull;
+            const bool ev = (m.E >> lane) & 1ull;
+            const bool up = (m.R >> lane) & 1ull;
+            const uint32_t pr = ev ? (up ? 2u : 0u) : 1u;
+            levels[v.tbase + tb + lane] = (uint8_t)((uint32_t)lv | ((uint32_t)hb << 5) |
+                                                    (pr << 6));
         }
         const uint32_t last = min(64u, v.e - tb) - 1;
         x = __builtin_amdgcn_readlane(lv, (int)last);
@@ -206,29 +398,31 @@ hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
                                  uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                                  uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
-                                 uint32_t* entering, StepSum* sums, magus_result* results,
-                                 uint8_t* levels, uint32_t* err, hipStream_t stream,
-                                 hipEvent_t ev0, hipEvent_t ev1)
+                                 uint32_t* entering, StepSum* sums, uint64_t* masks,
+                                 magus_result* results, uint8_t* levels, uint32_t* err,
+                                 hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
     hipError_t e = launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk,
                                max_chunks, chunk_base, err, stream);
     if (e != hipSuccess) return e;
     const uint32_t blocks = (max_chunks + kWaves - 1) / kWaves;
-    if (ev0) (void)hipEventRecord(ev0, stream);
-    stepped_map_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
-        samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, funcs);
+    const uint64_t n_blocks = stepped_mask_blocks(n_samples, n_traces);
+    if ((e = record_timing_event(ev0, stream)) != hipSuccess) return e;
+    stepped_mask_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
+        samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, n_blocks, funcs, sums,
+        masks);
     stepped_enter_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
         n_traces, chunk_base, cfgs, cfg_of_trace, funcs, entering);
     if (levels)
-        stepped_sum_kernel<true><<<blocks, kWaves * kWave, 0, stream>>>(
+        stepped_levels_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
             samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, sums,
             levels);
     else
-        stepped_sum_kernel<false><<<blocks, kWaves * kWave, 0, stream>>>(
-            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, sums,
-            nullptr);
-    if (ev1) (void)hipEventRecord(ev1, stream);
+        stepped_walk_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
+            offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, n_blocks, entering, masks,
+            sums);
+    if ((e = record_timing_event(ev1, stream)) != hipSuccess) return e;
     stepped_fold_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(n_traces, chunk_base, sums,
                                                                     results);
     return hipGetLastError();

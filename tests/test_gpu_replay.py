@@ -263,6 +263,46 @@ def test_persistent_grid_and_graph_replays_match(ctx, oracle_mod):
         ctx.set_persistent(0)
 
 
+def test_kernel_timing_inside_graphs(ctx, oracle_mod):
+    """With timing on, each graph launch times its own chunk kernel: one
+    launch per call, eager and graph calls alike, and the results stay right."""
+    import torch
+    traces = mixed_traces(505, LENGTHS * 2)
+    cfgs = [default_config(), default_config(window=5, hold=2)]
+    cot = (np.arange(len(traces)) % 2).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    want_res, _ = oracle_mod.replay_batch(samples, offsets, cfgs, cot)
+    s, o, c = to_dev(samples, offsets, cot)
+    res = torch.zeros((len(traces), 4), dtype=torch.int64, device="cuda")
+    ctx.set_profiling(True)
+    try:
+        ctx.kernel_time(magus.KERNEL_REPLAY)
+        for graphs in (False, True, True, False, True):
+            ctx.set_graphs(graphs)
+            res.zero_()
+            ctx.replay(s, o, cfgs, c, results=res)
+            ctx.check()
+            assert (results_np(res) == want_res).all(), graphs
+        ms, n = ctx.kernel_time(magus.KERNEL_REPLAY)
+        assert n == 5 and ms > 0
+        # timing off: the graph is reused, nothing is counted
+        ctx.set_profiling(False)
+        ctx.replay(s, o, cfgs, c, results=res)
+        ctx.check()
+        assert (results_np(res) == want_res).all()
+        ctx.set_profiling(True)
+        ms, n = ctx.kernel_time(magus.KERNEL_REPLAY)
+        assert n == 0 and ms == 0
+        for rep in range(3):
+            ctx.replay(s, o, cfgs, c, results=res)
+        ctx.check()
+        ms, n = ctx.kernel_time(magus.KERNEL_REPLAY)
+        assert n == 3 and ms > 0
+    finally:
+        ctx.set_profiling(False)
+        ctx.set_graphs(False)
+
+
 @pytest.fixture(scope="module")
 def uneven():
     return synth.workload_uneven()

@@ -59,6 +59,57 @@ def test_stepped_replay_matches_oracle(ctx, oracle_mod, chunk):
     assert (b == want_b).all(), describe_mismatch(b, want_b, offsets)
 
 
+def dense_traces(seed):
+    """Traces whose every step is an event (alternating samples), long high
+    runs broken by single events, and plain mixed traces."""
+    rng = np.random.default_rng(seed)
+    out = [np.array([1000, 3000] * 5000, np.uint32),
+           np.array([1000, 1000, 5000] * 3001, np.uint32)]
+    x = rng.integers(1000, 1100, 20000).astype(np.uint32)
+    x[rng.integers(0, 20000, 400)] = 50000
+    out.append(x)
+    return out + mixed_traces(seed, [70001, 16385, 8193, 4097, 65, 1])
+
+
+@pytest.mark.parametrize("chunk", [64, 4096, 8192, 16384, 65536])
+def test_stepped_dense_events_and_long_chunks(ctx, oracle_mod, chunk):
+    """Blocks with a move at every step, chunks of one block and chunks of
+    several groups of 64 blocks, with and without decision bytes."""
+    traces = dense_traces(chunk)
+    cfgs = stepped_configs(chunk + 1, 12) + [
+        default_config(window=2, hold=2, up_step=1, down_step=1),
+        default_config(window=2, hold=4, up_step=3, down_step=0, level_init=9),
+        default_config(up_step=0, down_step=2, level_min=2, level_max=29, level_init=20)]
+    cot = (np.arange(len(traces)) % len(cfgs)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    want_res, want_b = oracle_mod.replay_batch(samples, offsets, cfgs, cot, want_bytes=True)
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        res, _ = ctx.replay(s, o, cfgs, c)
+        ctx.check()
+        res2, lv = ctx.replay(s, o, cfgs, c, levels=True)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    got = results_np(res)
+    assert (got == want_res).all(), describe_mismatch(got[:, 0], want_res[:, 0])
+    assert (results_np(res2) == want_res).all()
+    assert (lv.cpu().numpy() == want_b).all()
+
+
+def test_stepped_bulk_workload_full_size(ctx, oracle_mod):
+    """4,096 x 100,000 with up 2 / down 1 rungs: every trace's results."""
+    samples, offsets = synth.workload_bulk(4096, 100000)
+    cfg = default_config(up_step=2, down_step=1)
+    s, o, _ = to_dev(samples, offsets)
+    res, _ = ctx.replay(s, o, [cfg])
+    ctx.check()
+    want, _ = oracle_mod.replay_batch(samples, offsets, [cfg])
+    got = results_np(res)
+    assert (got == want).all(), describe_mismatch(got[:, 0], want[:, 0])
+
+
 def test_stepped_staircase_on_gpu(ctx, oracle_mod):
     cfg = default_config(window=2, hold=32, hf_num=1, hf_den=1, up_step=3)
     x = np.array([1000 * 2 ** k for k in range(20)], np.uint32)
