@@ -108,6 +108,94 @@ def bench_sweep(magus, synth, ctx, dev):
     return res, grid_arr
 
 
+# The stepped-actuation replay on the bulk traces (up 2 rungs, down 1).
+def bench_stepped(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, pick, args,
+                  dev, extra, checks):
+    n_samples = int(offsets[-1])
+    log("stepped actuation (up 2 rungs, down 1 rung) on the bulk workload ...")
+    scfg = synth.default_config(up_step=2, down_step=1)
+    sarr = magus.config_array([scfg])
+    sctx = magus.Context(0)
+    sres = torch.empty((args.traces, 4), dtype=torch.int64, device=dev)
+    for _ in range(2):
+        sctx.replay(s, o, sarr, results=sres)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sctx.replay(s, o, sarr, results=sres)
+    torch.cuda.synchronize()
+    sdt = (time.perf_counter() - t0) / reps
+    sctx.check()
+    sgot = sres.cpu().numpy().view(np.uint64)
+    extra["stepped"] = {
+        "workload": "bulk traces, default config with up_step 2, down_step 1",
+        "ms_per_call": sdt * 1e3, "samples_per_s": n_samples / sdt,
+        # algorithmic bytes: one read of every sample (the 24 B of step
+        # masks per 64-step block written and read back are scratch)
+        "hbm_frac": 4.0 * n_samples / sdt / (HBM_PEAK_GBS * 1e9),
+        "scratch_bytes_per_sample": 2 * 24 / 64,
+        "parity": "not checked (--no-cpu)"}
+
+    def check_stepped(oracle):
+        for t in pick[:3]:
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            r, _ = oracle.replay_trace(x, scfg, want_bytes=False)
+            if list(sgot[t]) != [r["score"], r["level_sum"], r["transitions"],
+                                 r["ticks_high"]]:
+                raise SystemExit(f"stepped parity failure on trace {t}")
+        extra["stepped"]["parity"] = "ok: 3 sampled traces equal the oracle"
+    checks.append(check_stepped)
+    log(f"  stepped {sdt * 1e3:.3f} ms/call ({n_samples / sdt:.3e} samples/s)")
+    sctx.close()
+    del sres
+
+
+# The proxy energy / EDP model on the bulk traces (single pass).
+def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, pick, args,
+                dev, extra, checks):
+    n_samples = int(offsets[-1])
+    log("proxy energy / EDP model on the bulk workload ...")
+    model = synth.proxy_model()
+    pctx = magus.Context(0)
+    pctx.proxy(s, o, cfg_arr, model)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pst, pme = pctx.proxy(s, o, cfg_arr, model)
+    torch.cuda.synchronize()
+    pdt = (time.perf_counter() - t0) / reps
+    pctx.check()
+    pst_np, pme_np = pst.cpu().numpy(), pme.cpu().numpy()
+
+    def check_proxy(oracle):
+        for t in pick[:3]:
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            want_st, _ = oracle.proxy_trace(x, cfg, model)
+            if magus.proxy_stats_dict(pst_np[t]) != want_st:
+                raise SystemExit(f"proxy parity failure on trace {t}")
+        extra["proxy"]["parity"] = "ok: 3 sampled traces' statistics equal the oracle"
+    checks.append(check_proxy)
+    mean = {k: [float(v) for v in pme_np[:, 3 * i:3 * i + 3].mean(axis=0)]
+            for i, k in enumerate(magus.PROXY_METRIC_KEYS)}
+    extra["proxy"] = {
+        "workload": "bulk traces, synthetic proxy model (17 rungs 0.8-2.4 GHz, cap 50 MB/s "
+                    "per MHz, uncore 15-40 W, core 60 W, GPU 250 W, 100 ms intervals)",
+        "ms_per_call": pdt * 1e3, "samples_per_s": n_samples / pdt,
+        # the single pass reads every sample once
+        "hbm_frac": 4.0 * n_samples / pdt / (HBM_PEAK_GBS * 1e9),
+        "columns": ["magus", "always_max", "always_min"],
+        "mean_over_traces": {k: mean[k] for k in ("perf_loss", "pkg_power_saving",
+                                                  "energy_saving", "edp_saving")},
+        "parity": "not checked (--no-cpu)"}
+    log(f"  proxy {pdt * 1e3:.3f} ms/call; MAGUS mean perf loss "
+        f"{mean['perf_loss'][0]:.4f}, energy saving {mean['energy_saving'][0]:.4f}, "
+        f"EDP saving {mean['edp_saving'][0]:.4f}")
+    pctx.close()
+    del pst, pme
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +210,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only run the configuration sweep and print its figures")
+    ap.add_argument("--only", choices=["stepped", "proxy"],
+                    help="only run this report on the bulk workload (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy kernel over as many bytes as the "
                          "bulk workload (read 4 B + write 4 B per sample), for scaling HBM "
@@ -169,6 +259,14 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     cfg_arr = magus.config_array([cfg])
+    if args.only:
+        extra = {}
+        fn = bench_stepped if args.only == "stepped" else bench_proxy
+        fn(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, [0], args, dev, extra,
+           [])
+        ctx.close()
+        print(json.dumps({"extra": extra}), flush=True)
+        return
     # eager launches (plan, chunk and fold kernels per call), for reference
     for _ in range(max(args.warmup, 1)):
         ctx.replay(s, o, cfg_arr, results=results)
@@ -208,17 +306,22 @@ def main():
         f"{avg_kernel_ms:.4f} ms ({achieved:.0f} GB/s, {launches} timed launches), "
         f"{value:.3e} samples/s")
 
-    # parity spot check of the timed launch against the oracle
-    import oracle
+    # checks against the oracle, run by the host leg at the end (the only
+    # part of this script that touches the oracle); each takes the oracle
+    # module and fills in its report
+    checks = []
     got = results.cpu().numpy().view(np.uint64)
     rng = np.random.default_rng(0)
     pick = sorted(set(rng.integers(0, args.traces, 8).tolist()))
-    for t in pick:
-        x = samples[int(offsets[t]):int(offsets[t + 1])]
-        r, _ = oracle.replay_trace(x, cfg, want_bytes=False)
-        if list(got[t]) != [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]]:
-            raise SystemExit(f"parity failure on trace {t}")
-    parity = f"ok: {len(pick)} sampled traces equal the oracle"
+
+    def check_replay(oracle):
+        for t in pick:
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            r, _ = oracle.replay_trace(x, cfg, want_bytes=False)
+            if list(got[t]) != [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]]:
+                raise SystemExit(f"parity failure on trace {t}")
+        out["parity"] = f"ok: {len(pick)} sampled traces of the timed launch equal the oracle"
+    checks.append(check_replay)
 
     out = {
         "metric": "trace-samples x configs evaluated/s at 1 GPU",
@@ -239,7 +342,7 @@ def main():
                    "chunk_steps": ctx.chunk,
                    "launch": "hipGraph" if not args.no_graphs else "eager",
                    "eager_ms_per_step": eager_ms},
-        "parity": parity,
+        "parity": "not checked (--no-cpu)",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(n_samples),
@@ -247,46 +350,21 @@ def main():
                      "bytes_per_launch": bytes_per_launch},
     }
 
-    if not args.no_cpu:
-        # the oracle as it is, one call per slice of traces on each host thread
-        # (its ctypes calls release the interpreter lock); several passes so
-        # the sample is ~10 s of CPU work
-        from concurrent.futures import ThreadPoolExecutor
-        threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        passes = 3
-        log(f"oracle baseline on the host: {threads} threads x {passes} passes ...")
-        bounds = np.linspace(0, args.traces, threads + 1).astype(np.int64)
-
-        def slice_run(i):
-            a, b = int(bounds[i]), int(bounds[i + 1])
-            oracle.replay_batch(samples[int(offsets[a]):int(offsets[b])],
-                                offsets[a:b + 1] - offsets[a], [cfg])
-
-        t0 = time.perf_counter()
-        with ThreadPoolExecutor(max_workers=threads) as pool:
-            for _ in range(passes):
-                list(pool.map(slice_run, range(threads)))
-        dt = (time.perf_counter() - t0) / passes
-        out["cpu_baseline"] = {"value": n_samples / dt, "unit": "samples*configs/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"all {args.traces} traces x {args.length} samples, "
-                                         f"1 config, {threads} threads over trace slices, "
-                                         f"{passes} passes of {dt:.2f} s"}
-        log(f"  oracle {n_samples / dt:.3e} samples/s ({dt:.2f} s per pass)")
-
     if not args.no_extra:
         extra = {}
-        # FP64 side-form vs the exact Q16.16 form
-        dp = dl = tot = 0
-        for t in range(0, args.traces, max(1, args.traces // 32)):
-            x = samples[int(offsets[t]):int(offsets[t + 1])]
-            _, be = oracle.replay_trace(x, cfg)
-            _, bf = oracle.replay_trace_fp64(x, cfg, 0.1, -0.1)
-            dp += int(((be >> 6) != (bf >> 6)).sum())
-            dl += int(((be & 31) != (bf & 31)).sum())
-            tot += len(x)
-        extra["fp64_side_form"] = {"pred_disagreement_rate": dp / tot,
-                                   "level_disagreement_rate": dl / tot, "steps": tot}
+        # FP64 side-form vs the exact Q16.16 form (an oracle-only study)
+        def check_fp64(oracle):
+            dp = dl = tot = 0
+            for t in range(0, args.traces, max(1, args.traces // 32)):
+                x = samples[int(offsets[t]):int(offsets[t + 1])]
+                _, be = oracle.replay_trace(x, cfg)
+                _, bf = oracle.replay_trace_fp64(x, cfg, 0.1, -0.1)
+                dp += int(((be >> 6) != (bf >> 6)).sum())
+                dl += int(((be & 31) != (bf & 31)).sum())
+                tot += len(x)
+            extra["fp64_side_form"] = {"pred_disagreement_rate": dp / tot,
+                                       "level_disagreement_rate": dl / tot, "steps": tot}
+        checks.append(check_fp64)
 
         # context for the roofline: plain torch kernels over the same bytes (a
         # max reduction reads them; a device copy reads and writes them)
@@ -314,72 +392,10 @@ def main():
             f"({bytes_per_launch / amax_ms / 1e6:.0f} GB/s); device copy {copy_ms:.4f} ms "
             f"({2 * bytes_per_launch / copy_ms / 1e6:.0f} GB/s read + write)")
 
-        log("stepped actuation (up 2 rungs, down 1 rung) on the bulk workload ...")
-        scfg = synth.default_config(up_step=2, down_step=1)
-        sarr = magus.config_array([scfg])
-        sctx = magus.Context(0)
-        sres = torch.empty((args.traces, 4), dtype=torch.int64, device=dev)
-        for _ in range(2):
-            sctx.replay(s, o, sarr, results=sres)
-        torch.cuda.synchronize()
-        reps = 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            sctx.replay(s, o, sarr, results=sres)
-        torch.cuda.synchronize()
-        sdt = (time.perf_counter() - t0) / reps
-        sctx.check()
-        sgot = sres.cpu().numpy().view(np.uint64)
-        for t in pick[:3]:
-            x = samples[int(offsets[t]):int(offsets[t + 1])]
-            r, _ = oracle.replay_trace(x, scfg, want_bytes=False)
-            if list(sgot[t]) != [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]]:
-                raise SystemExit(f"stepped parity failure on trace {t}")
-        extra["stepped"] = {
-            "workload": "bulk traces, default config with up_step 2, down_step 1",
-            "ms_per_call": sdt * 1e3, "samples_per_s": n_samples / sdt,
-            # two passes read every sample
-            "hbm_frac": 8.0 * n_samples / sdt / (HBM_PEAK_GBS * 1e9),
-            "parity": "ok: 3 sampled traces equal the oracle"}
-        log(f"  stepped {sdt * 1e3:.3f} ms/call ({n_samples / sdt:.3e} samples/s)")
-        sctx.close()
-        del sres
-
-        log("proxy energy / EDP model on the bulk workload ...")
-        model = synth.proxy_model()
-        pctx = magus.Context(0)
-        pctx.proxy(s, o, cfg_arr, model)
-        torch.cuda.synchronize()
-        reps = 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            pst, pme = pctx.proxy(s, o, cfg_arr, model)
-        torch.cuda.synchronize()
-        pdt = (time.perf_counter() - t0) / reps
-        pctx.check()
-        pst_np, pme_np = pst.cpu().numpy(), pme.cpu().numpy()
-        for t in pick[:3]:
-            x = samples[int(offsets[t]):int(offsets[t + 1])]
-            want_st, _ = oracle.proxy_trace(x, cfg, model)
-            if magus.proxy_stats_dict(pst_np[t]) != want_st:
-                raise SystemExit(f"proxy parity failure on trace {t}")
-        mean = {k: [float(v) for v in pme_np[:, 3 * i:3 * i + 3].mean(axis=0)]
-                for i, k in enumerate(magus.PROXY_METRIC_KEYS)}
-        extra["proxy"] = {
-            "workload": "bulk traces, synthetic proxy model (17 rungs 0.8-2.4 GHz, cap 50 MB/s "
-                        "per MHz, uncore 15-40 W, core 60 W, GPU 250 W, 100 ms intervals)",
-            "ms_per_call": pdt * 1e3, "samples_per_s": n_samples / pdt,
-            # the single pass reads every sample once
-            "hbm_frac": 4.0 * n_samples / pdt / (HBM_PEAK_GBS * 1e9),
-            "columns": ["magus", "always_max", "always_min"],
-            "mean_over_traces": {k: mean[k] for k in ("perf_loss", "pkg_power_saving",
-                                                      "energy_saving", "edp_saving")},
-            "parity": "ok: 3 sampled traces' statistics equal the oracle"}
-        log(f"  proxy {pdt * 1e3:.3f} ms/call; MAGUS mean perf loss "
-            f"{mean['perf_loss'][0]:.4f}, energy saving {mean['energy_saving'][0]:.4f}, "
-            f"EDP saving {mean['edp_saving'][0]:.4f}")
-        pctx.close()
-        del pst, pme
+        bench_stepped(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, pick, args,
+                      dev, extra, checks)
+        bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, pick, args,
+                    dev, extra, checks)
         del s, o
         torch.cuda.empty_cache()
 
@@ -408,18 +424,24 @@ def main():
         dt = (time.perf_counter() - t0) / reps
         uctx.check()
         ugot = ures.cpu().numpy().view(np.uint64)
-        for t in (0, int(np.argmax(np.diff(uoff.astype(np.int64)))), len(uoff) - 2):
-            r, _ = oracle.replay_trace(usmp[int(uoff[t]):int(uoff[t + 1])], grid[int(ucot[t])],
-                                       want_bytes=False)
-            if list(ugot[t]) != [r["score"], r["level_sum"], r["transitions"], r["ticks_high"]]:
-                raise SystemExit(f"uneven parity failure on trace {t}")
+        upick = {t: (usmp[int(uoff[t]):int(uoff[t + 1])].copy(), grid[int(ucot[t])])
+                 for t in (0, int(np.argmax(np.diff(uoff.astype(np.int64)))), len(uoff) - 2)}
+
+        def check_uneven(oracle):
+            for t, (x, c) in upick.items():
+                r, _ = oracle.replay_trace(x, c, want_bytes=False)
+                if list(ugot[t]) != [r["score"], r["level_sum"], r["transitions"],
+                                     r["ticks_high"]]:
+                    raise SystemExit(f"uneven parity failure on trace {t}")
+            extra["uneven"]["parity"] = f"ok: {len(upick)} sampled traces equal the oracle"
+        checks.append(check_uneven)
         ideal_ms = 4.0 * len(usmp) / (HBM_PEAK_GBS * 1e9) * 1e3
         extra["uneven"] = {
             "workload": "20,000 bursty traces, log-normal lengths 1,000..1,000,000, "
                         "a grid config per trace, one launch (hipGraph)",
             "samples": int(len(usmp)), "ms_per_call": dt * 1e3,
             "samples_per_s": len(usmp) / dt, "hbm_frac": ideal_ms / (dt * 1e3),
-            "makespan_vs_ideal": dt * 1e3 / ideal_ms,
+            "makespan_vs_ideal": dt * 1e3 / ideal_ms, "parity": "not checked (--no-cpu)",
             "autotuned": {"chunk_steps": chosen["chunk_steps"],
                           "persistent_workgroups": chosen["persistent_blocks"],
                           "default_ms": chosen["default_ms"], "best_ms": chosen["best_ms"]}}
@@ -439,11 +461,18 @@ def main():
         lat_ms = lat[served].astype(np.float64) * 1e-6
         # parity of sampled nodes against the oracle replay of their served samples
         sids = np.unique(ev["stream"][served])[::4099]
+        snodes = []
         for sid in sids:
             m = served & (ev["stream"] == sid)
-            _, want = oracle.replay_trace(ev["value"][m], grid[int(cfg_of_stream[sid])])
-            if not (dec[m] == want).all():
-                raise SystemExit(f"serving parity failure on node {sid}")
+            snodes.append((sid, ev["value"][m].copy(), grid[int(cfg_of_stream[sid])], dec[m].copy()))
+
+        def check_serve(oracle):
+            for sid, x, c, d in snodes:
+                _, want = oracle.replay_trace(x, c)
+                if not (d == want).all():
+                    raise SystemExit(f"serving parity failure on node {sid}")
+            extra["serve"]["parity"] = f"ok: {len(snodes)} sampled nodes equal the oracle"
+        checks.append(check_serve)
         dec2, lat2, st2 = srv.run(ev, n_streams, grid_arr, realtime=False, depth=3)
         srv.close()
         extra["serve"] = {
@@ -455,10 +484,42 @@ def main():
             "joins_admitted": st["joins_admitted"], "joins_waited": st["joins_waited"],
             "samples_dropped": st["samples_dropped"],
             "flat_out_samples_per_s": st2["samples_served"] / st2["wall_s"],
-            "parity": f"ok: {len(sids)} sampled nodes equal the oracle"}
+            "parity": "not checked (--no-cpu)"}
         log(f"  serve p50 {extra['serve']['p50_ms']:.3f} ms p99 {extra['serve']['p99_ms']:.3f} ms, "
             f"flat-out {extra['serve']['flat_out_samples_per_s']:.3e} samples/s")
         out["extra"] = extra
+
+    if not args.no_cpu:
+        # the host leg: the oracle as it is, one call per slice of traces on each host thread
+        # (its ctypes calls release the interpreter lock); several passes so
+        # the sample is ~10 s of CPU work
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        passes = 3
+        log(f"oracle baseline on the host: {threads} threads x {passes} passes ...")
+        bounds = np.linspace(0, args.traces, threads + 1).astype(np.int64)
+
+        def slice_run(i):
+            a, b = int(bounds[i]), int(bounds[i + 1])
+            oracle.replay_batch(samples[int(offsets[a]):int(offsets[b])],
+                                offsets[a:b + 1] - offsets[a], [cfg])
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as pool:
+            for _ in range(passes):
+                list(pool.map(slice_run, range(threads)))
+        dt = (time.perf_counter() - t0) / passes
+        out["cpu_baseline"] = {"value": n_samples / dt, "unit": "samples*configs/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"all {args.traces} traces x {args.length} samples, "
+                                         f"1 config, {threads} threads over trace slices, "
+                                         f"{passes} passes of {dt:.2f} s"}
+        log(f"  oracle {n_samples / dt:.3e} samples/s ({dt:.2f} s per pass)")
+        # then the oracle checks of the GPU results kept above
+        for check in checks:
+            check(oracle)
 
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -392,8 +392,8 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         if ((rc = ctx->step_funcs.ensure((size_t)max_chunks * sizeof(ClampAdd))) ||
             (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
             (rc = ctx->step_sums.ensure((size_t)max_chunks * sizeof(StepSum))) ||
-            (rc = ctx->step_masks.ensure(
-                 (size_t)stepped_mask_blocks(n_samples, n_traces) * 3 * sizeof(uint64_t))))
+            (rc = ctx->step_masks.ensure((size_t)stepped_mask_blocks(n_samples, n_traces) *
+                                         (3 * sizeof(uint64_t) + sizeof(uint32_t)))))
             return rc;
     } else {
         if ((rc = ctx->sums.ensure((size_t)max_chunks * sizeof(ChunkSum)))) return rc;
@@ -409,7 +409,7 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(), max_chunks,
                 ctx->step_funcs.as<ClampAdd>(), ctx->step_enter.as<uint32_t>(),
                 ctx->step_sums.as<StepSum>(), ctx->step_masks.as<uint64_t>(), d_results,
-                d_levels, ctx->err.as<uint32_t>(), q, e0, e1);
+                d_levels, ctx->err.as<uint32_t>(), any_base, q, e0, e1);
         return launch_replay(d_samples, n_samples, d_offsets, n_traces, ctx->cfgs.as<DevCfg>(),
                              n_cfgs, d_cfg_of_trace, ctx->chunk, ctx->chunk_base.as<uint32_t>(),
                              ctx->sums.as<ChunkSum>(), max_chunks,
@@ -559,7 +559,8 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         HIP_TRY(launch_proxy_fused(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
                                    max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
                                    ctx->proxy_model.as<magus_proxy_model>(),
-                                   ctx->proxy_sums.as<ProxySum>(), d_stats, d_metrics, stream));
+                                   ctx->proxy_sums.as<ProxySum>(), d_stats, d_metrics, any_base,
+                                   stream));
         return MAGUS_OK;
     }
     // stepped actuation: the replay writes every step's level, then a pass

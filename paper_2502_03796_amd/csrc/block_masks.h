@@ -29,12 +29,15 @@ struct BlockMasks {
 // One block: x = this block's samples, xprev = the block before (lane i holds
 // step tb+i).  fps carries (flags of the block before) >> 1 and is updated.
 // valid = lanes whose step exists; steps before W-1 of the trace never predict.
+// all_high = ~0 when the count threshold is 0 (every step is high), else 0.
 // kFull: every lane's step exists and the trace's FIFO is already full (the
 // block does not end the chunk and does not start the trace), so no lane mask
-// is needed.
-template <bool kFull = false>
+// is needed.  kAnyBase: the config may use another derivative base than the
+// smaller sample (else that base is assumed).
+template <bool kFull = false, bool kAnyBase = true>
 __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, uint32_t tb,
                                                   uint64_t valid, const DevCfg& c,
+                                                  uint64_t all_high, uint32_t k16,
                                                   uint64_t& fps, uint32_t lane)
 {
     const uint32_t W = c.W, H = c.H;
@@ -46,12 +49,10 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, ui
     uint64_t vm = kFull ? ~0ull : valid;
     if (!kFull && tb < W - 1) vm &= ~mask_below(W - 1 - tb);
     BlockMasks r;
-    if (c.base == 0) {
+    if (!kAnyBase || c.base == 0) {
         // the smaller sample is the base: a rise is an event iff
         // b 2^16 > a (2^16 + W q_inc), a fall iff a 2^16 > b (2^16 + W |q_dec|)
-        // (2^16 as an opaque scalar keeps x 2^16 one 32x32->64 multiply)
-        uint32_t k16;
-        asm volatile("s_mov_b32 %0, 0x10000" : "=s"(k16));
+        // (k16 = 2^16 as an opaque scalar keeps x 2^16 one 32x32->64 multiply)
         const uint64_t up = lane_ballot((uint64_t)b * k16 > (uint64_t)a * (65536u + c.mu)) & vm;
         const uint64_t dn = lane_ballot((uint64_t)a * k16 > (uint64_t)b * (65536u + c.md)) & vm;
         r.E = up | dn;
@@ -66,11 +67,11 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, ui
         r.R = lane_ballot(rising);
     }
     // events among the last H steps (this block's flags and the last H-1 of
-    // the block before), for all 64 steps; with none of them and a non-zero
-    // count threshold no step is high
+    // the block before), for all 64 steps; with none of them a step is high
+    // only if the count threshold is 0
     const uint64_t B = fps >> (64 - H);
-    if ((r.E | B) == 0 && c.thr != 0) {
-        r.HM = 0;
+    if ((r.E | B) == 0) {
+        r.HM = all_high & (kFull ? ~0ull : valid);
     } else {
         const uint64_t nG = ~((r.E << (H - 1)) | B);
         const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(r.E & 1ull);
@@ -88,6 +89,8 @@ struct ChunkView {
     uint32_t t, s, e, wbeg;
     uint64_t tbase;
     DevCfg c;
+    uint64_t all_high;       // ~0 when the count threshold is 0
+    uint32_t k16;            // 2^16, opaque to the compiler
     __amdgpu_buffer_rsrc_t rsrc;
 };
 
@@ -107,6 +110,8 @@ __device__ __forceinline__ ChunkView chunk_view(
     v.s = (g - chunk_base[v.t]) * chunk;
     v.e = min(v.s + chunk, n);
     v.c = cfgs[cfg_of_trace ? cfg_of_trace[v.t] : 0];
+    v.all_high = v.c.thr == 0 ? ~0ull : 0ull;
+    asm volatile("s_mov_b32 %0, 0x10000" : "=s"(v.k16));
     v.wbeg = v.s >= 64 ? v.s - 64 : 0;
     const uint64_t base = (uint64_t)(samples + v.tbase + v.wbeg);
     const uint64_t base_u = ((uint64_t)bm_uniform((uint32_t)(base >> 32)) << 32) |
@@ -117,13 +122,20 @@ __device__ __forceinline__ ChunkView chunk_view(
     return v;
 }
 
+struct NoGroupEnd {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // Walks the blocks of a chunk, calling body(block masks, first step of the
 // block, valid-lane mask, this lane's sample) for every real block (the
-// warm-up block only feeds the FIFOs).  Lanes past the chunk's end read 0.
-// A group of kAhead blocks is loaded while the group before it is
-// evaluated, so a wave keeps that many loads in flight.
-template <uint32_t kAhead = 8, class Body>
-__device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane, Body&& body) {
+// warm-up block only feeds the FIFOs), and group_end() after every group of
+// kAhead loaded blocks (code that should not be repeated per block goes
+// there).  Lanes past the chunk's end read 0.  A group of kAhead blocks is
+// loaded while the group before it is evaluated, so a wave keeps that many
+// loads in flight.
+template <uint32_t kAhead = 8, bool kAnyBase = true, class Body, class GroupEnd = NoGroupEnd>
+__device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane, Body&& body,
+                                               GroupEnd&& group_end = GroupEnd{}) {
     const uint32_t first_real = v.s >= 64 ? 1u : 0u;
     const uint32_t nblk = (v.e - v.wbeg + 63) >> 6;
     auto load = [&](uint32_t blk) -> uint32_t {
@@ -135,7 +147,8 @@ __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane
         constexpr bool kFull = decltype(full_tag)::value;
         const uint32_t tb = v.wbeg + blk * 64;
         const uint64_t valid = kFull ? ~0ull : mask_below(min(64u, v.e - tb));
-        const BlockMasks m = block_masks<kFull>(x, xprev, tb, valid, v.c, fps, lane);
+        const BlockMasks m = block_masks<kFull, kAnyBase>(x, xprev, tb, valid, v.c, v.all_high,
+                                                          v.k16, fps, lane);
         xprev = x;
         if (kFull || blk >= first_real) body(m, tb, valid, x);
     };
@@ -150,6 +163,7 @@ __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane
             for (uint32_t k = 0; k < kAhead; ++k)
                 if (g * kAhead + k < nblk) step(g * kAhead + k, cur[k], std::false_type{});
         }
+        group_end();
     };
     // two alternating groups of kAhead blocks: one is evaluated while the
     // other is loaded (loads past the end read 0)

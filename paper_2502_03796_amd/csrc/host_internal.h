@@ -65,7 +65,7 @@ struct magus_ctx {
     magus::DevBuf step_funcs;   // stepped replay: ClampAdd per chunk
     magus::DevBuf step_enter;   // stepped replay: entering level per chunk
     magus::DevBuf step_sums;    // stepped replay: StepSum per chunk
-    magus::DevBuf step_masks;   // stepped replay: 3 x 8 B of step masks per block
+    magus::DevBuf step_masks;   // stepped replay: 28 B of step masks and map per block
     std::vector<magus::DevCfg> cfg_host;        // last uploaded table
     std::vector<magus_config> cfg_raw;          // ... and the configs it came from
     magus::DevBuf keys;         // sweep: arg-min keys + status

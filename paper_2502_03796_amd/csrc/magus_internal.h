@@ -145,9 +145,9 @@ hipError_t launch_fixup(uint32_t n_traces, const uint32_t* chunk_base, const Chu
                         uint32_t max_chunks, uint8_t* levels, hipStream_t stream);
 
 // Replay for configs with stepped actuation (stepped.hip): pass 1 reads the
-// samples once and writes the chunk's clamp-add map and the masks of the
-// steps that can move the level (`masks`: three arrays of
-// stepped_mask_blocks() words); pass 2 accumulates with the entering level
+// samples once and writes the chunk's clamp-add map, the masks of the steps
+// that can move the level and each block's map (`masks`: 28 B per slot of
+// stepped_mask_blocks()); pass 2 accumulates with the entering level
 // that the per-trace fold derived, from the masks, or from the samples when
 // `levels` is not null.
 hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
@@ -156,9 +156,10 @@ hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
                                  uint32_t* entering, StepSum* sums, uint64_t* masks,
                                  magus_result* results, uint8_t* levels, uint32_t* err,
-                                 hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
-// Length of each of the three block-mask arrays of the stepped replay
-// (3 x this many uint64 words of scratch): one slot per 64-step block.
+                                 bool any_base, hipStream_t stream, hipEvent_t ev0,
+                                 hipEvent_t ev1);
+// Slots per array of the stepped replay's block scratch (one slot per
+// 64-step block): three uint64 step-mask arrays and one uint32 map array.
 inline uint64_t stepped_mask_blocks(uint64_t n_samples, uint32_t n_traces) {
     return n_samples / 64 + n_traces + 1;
 }

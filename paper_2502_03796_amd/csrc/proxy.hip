@@ -215,6 +215,33 @@ __device__ __forceinline__ uint32_t sat_sub(uint32_t x, uint32_t cap) {
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) { return wave_sum(v); }
 
+// Carries into the 64 bit positions of a + b + cin (cin 0 or 1) and the carry
+// out, in scalar registers (a, b wave-uniform).
+__device__ __forceinline__ uint64_t carries_into(uint64_t a, uint64_t b, uint32_t cin,
+                                                 uint32_t& cout) {
+    uint32_t s0, s1, k;
+    asm("s_add_u32 %0, %3, %5\n\t"
+        "s_addc_u32 %1, %4, %6\n\t"
+        "s_cselect_b32 %2, 1, 0\n\t"
+        "s_add_u32 %0, %0, %7\n\t"
+        "s_addc_u32 %1, %1, 0\n\t"
+        "s_cselect_b32 %2, 1, %2"
+        : "=&s"(s0), "=&s"(s1), "=&s"(k)
+        : "s"(uniform((uint32_t)a)), "s"(uniform((uint32_t)(a >> 32))),
+          "s"(uniform((uint32_t)b)), "s"(uniform((uint32_t)(b >> 32))), "s"(uniform(cin))
+        : "scc");
+    cout = k;
+    return ((((uint64_t)s1 << 32) | s0) ^ a) ^ b;
+}
+
+// a in the lanes whose bit of the wave-uniform mask is set, else b
+__device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_t b) {
+    const uint64_t m = ((uint64_t)uniform((uint32_t)(mask >> 32)) << 32) | uniform((uint32_t)mask);
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
+    return r;
+}
+
 // v in the lanes whose bit of the wave-uniform mask is set, else 0
 __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
     const uint64_t m = ((uint64_t)uniform((uint32_t)(mask >> 32)) << 32) | uniform((uint32_t)mask);
@@ -225,6 +252,7 @@ __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
 
 // Fused pass, one wave per chunk (blocks loaded four at a time: the per-lane
 // sums leave fewer registers for loads in flight than the plain replay has).
+template <bool kAnyBase>
 __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -243,47 +271,67 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     bool seen = false;        // a decisive step earlier in this chunk
     uint32_t ppre = v.e - v.s;  // steps up to and including the first decisive step
     uint32_t lvl = 0;         // level bit after the last step (once seen)
-    for_each_block<4>(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid, uint32_t x) {
-        const uint64_t UP = m.HM | (m.E & m.R);          // high or +1 -> max
-        const uint64_t DN = (m.E & ~m.R) & ~m.HM;        // -1 executed -> min
-        const uint64_t D = UP | DN;
+    uint64_t lvl_mask = 0;    // lvl as a lane mask (all or none)
+    // The run since the last decisive block is summed at its level without
+    // per-lane masks and moved to a_hi or a_lo at the next decisive block or
+    // the end (before the chunk's first decisive step it is discarded: those
+    // steps are summed after the walk).
+    uint64_t a_run = 0;
+    uint32_t n_run = 0;
+    for_each_block<4, kAnyBase>(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid,
+                                             uint32_t x) {
         const uint32_t e_hi = sat_sub(x, c_hi), e_lo = sat_sub(x, c_lo);
         a_max += e_hi;                                   // lanes past the end read 0
         a_min += e_lo;
-        // level bit before each step: the carries into the bits of
-        // ~DN + UP + lvl, formed from 32-bit halves so that everything
-        // stays in scalar registers
-        const uint32_t n0 = ~(uint32_t)DN, n1 = ~(uint32_t)(DN >> 32);
-        const uint32_t u0 = (uint32_t)UP, u1 = (uint32_t)(UP >> 32);
-        const uint32_t s0 = n0 + u0;
-        const uint32_t k0 = s0 < n0;
-        const uint32_t t0 = s0 + lvl;
-        const uint32_t cin1 = k0 | (t0 < s0);
-        const uint32_t s1 = n1 + u1;
-        const uint32_t k1 = s1 < n1;
-        const uint32_t t1 = s1 + cin1;
-        const uint32_t cout = k1 | (t1 < s1);
-        const uint64_t C = ~((((uint64_t)t1 << 32) | t0) ^ D);
-        // steps whose interval level is known: after the chunk's first
-        // decisive step (the ones up to it are summed after the walk)
-        uint64_t det = valid;
-        if (!seen) {
-            if (D) {
-                const uint32_t p = (uint32_t)__builtin_ctzll(D);
-                ppre = tb + p + 1 - v.s;
-                det &= ~mask_below(p + 1);
-                seen = true;
-            } else {
-                det = 0;
-            }
+        if ((m.E | m.HM) == 0) {
+            // no decisive step: the block runs at the level it was entered at
+            a_run += lane_pick(lvl_mask, e_hi, e_lo);
+            n_run += (uint32_t)__builtin_popcountll(valid);
+            return;
         }
-        const uint64_t hi_m = C & det, lo_m = ~C & det;
+        const uint64_t UP = m.HM | (m.E & m.R);          // high or +1 -> max
+        const uint64_t DN = m.E & ~(m.R | m.HM);         // -1 executed -> min
+        const uint64_t D = UP | DN;
+        uint64_t det = valid;
+        if (seen) {
+            if (lvl) {
+                a_hi += a_run;
+                n_hi += n_run;
+            } else {
+                a_lo += a_run;
+                n_lo += n_run;
+            }
+        } else {
+            // steps up to and including the first decisive one are summed
+            // after the walk at each possible entering level
+            const uint32_t p = (uint32_t)__builtin_ctzll(D);
+            ppre = tb + p + 1 - v.s;
+            det &= ~mask_below(p + 1);
+            seen = true;
+        }
+        a_run = 0;
+        n_run = 0;
+        // level bit before each step: the carries into the bits of
+        // ~DN + UP + lvl (UP generates, DN kills)
+        uint32_t cout;
+        const uint64_t C = carries_into(~DN, UP, lvl, cout);
+        const uint64_t hi_m = C & det, lo_m = det & ~C;
         n_hi += (uint32_t)__builtin_popcountll(hi_m);
         n_lo += (uint32_t)__builtin_popcountll(lo_m);
         a_hi += lane_sel(hi_m, e_hi);
         a_lo += lane_sel(lo_m, e_lo);
-        lvl = seen ? cout : 0u;                          // level after the block's last step
+        lvl = cout;                                      // level after the block's last step
+        lvl_mask = cout ? ~0ull : 0ull;
     });
+    if (seen) {
+        if (lvl) {
+            a_hi += a_run;
+            n_hi += n_run;
+        } else {
+            a_lo += a_run;
+            n_lo += n_run;
+        }
+    }
     // the steps up to and including the first decisive step, at each of the
     // three levels the chunk can be entered at (usually a block or two)
     {
@@ -430,13 +478,14 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                               const magus_proxy_model* model, ProxySum* psums,
                               magus_proxy_stats* stats, magus_proxy_metrics* metrics,
-                              hipStream_t stream)
+                              bool any_base, hipStream_t stream)
 {
     if (n_traces == 0) return hipSuccess;
     const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
     if (blocks)
-        proxy_chunk_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
-            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, model, psums);
+        (any_base ? proxy_chunk_kernel<true> : proxy_chunk_kernel<false>)
+            <<<blocks, kStatsWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base,
+                                                         cfgs, cfg_of_trace, chunk, model, psums);
     proxy_fold_kernel<<<(n_traces + kStatsWaves - 1) / kStatsWaves, kStatsWaves * kWave, 0,
                         stream>>>(n_traces, chunk_base, psums, cfgs, cfg_of_trace, stats);
     if (metrics)

@@ -33,7 +33,7 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                               const magus_proxy_model* model, ProxySum* psums,
                               magus_proxy_stats* stats, magus_proxy_metrics* metrics,
-                              hipStream_t stream);
+                              bool any_base, hipStream_t stream);
 
 // Runs after a replay of the same batch that wrote the decision bytes
 // `levels` with the chunk plan in `chunk_base` (chunk steps per chunk).

@@ -32,6 +32,7 @@ namespace magus {
 namespace {
 
 constexpr int kWaves = 4;
+constexpr uint32_t kGroupBlocks = 8;   // blocks the walker loads ahead
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -180,6 +181,29 @@ __device__ __forceinline__ ClampAdd wave_scan(ClampAdd f, uint32_t lane) {
     return f;
 }
 
+// A block map in one word for pass 2.  A move of 32 rungs or more saturates
+// every level of a 0..31 ladder, so a in [-64, 64] represents the map
+// exactly, and so does every composition with it.
+__device__ __forceinline__ int32_t clamp_move(int32_t a) { return min(max(a, -64), 64); }
+
+__device__ __forceinline__ uint32_t pack_map(const ClampAdd& f) {
+    return (uint32_t)(clamp_move(f.a) + 64) | ((uint32_t)f.lo << 8) | ((uint32_t)f.hi << 16);
+}
+
+__device__ __forceinline__ ClampAdd unpack_map(uint32_t w) {
+    return ClampAdd{(int32_t)(w & 0xFFu) - 64, (int32_t)((w >> 8) & 0xFFu), (int32_t)(w >> 16)};
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
 // Index of the first block of a chunk in the mask arrays: blocks of one trace
 // start 64 steps apart, so (absolute first step) / 64 + trace is one-to-one
 // over all blocks of a batch and stays below n_samples / 64 + n_traces.
@@ -188,6 +212,7 @@ __device__ __forceinline__ uint64_t first_block(uint64_t tbase, uint32_t s, uint
 }
 
 // Pass 1: masks of every block, the map and the high steps of every chunk.
+template <bool kAnyBase>
 __global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -201,25 +226,32 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
     const ChunkView v = chunk_view(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
                                    chunk, g);
     const Moves mv = moves_of(v.c);
-    uint64_t* out = masks + first_block(v.tbase, v.s, v.t);
+    const uint64_t b0 = first_block(v.tbase, v.s, v.t);
+    uint64_t* out = masks + b0;
+    uint32_t* out_map = reinterpret_cast<uint32_t*>(masks + 3 * n_blocks) + b0;
     ClampAdd F{0, mv.lmin, mv.lmax};                   // identity
     uint32_t th = 0, j = 0;
     uint64_t hm_before = 0;
     ParkedMasks pk{0, 0, 0, 0, 0, 0};
     auto flush = [&](uint32_t cnt) {
         const StepMasks s = pk.get();
+        const ClampAdd f = block_map(s, mv);
         if (lane < cnt) {
             out[lane] = s.hs;
             out[n_blocks + lane] = s.up;
             out[2 * n_blocks + lane] = s.dn;
+            out_map[lane] = pack_map(f);
         }
         out += cnt;
-        F = compose(F, wave_compose(block_map(s, mv), lane));
+        out_map += cnt;
+        F = compose(F, wave_compose(f, lane));
+        F.a = clamp_move(F.a);
         pk = ParkedMasks{0, 0, 0, 0, 0, 0};
     };
-    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t, uint32_t) {
-        th += (uint32_t)__popcll(m.HM);
+    for_each_block<kGroupBlocks, kAnyBase>(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t,
+                                                        uint32_t) {
         if ((m.E | m.HM) != 0) {
+            th += (uint32_t)__popcll(m.HM);
             const StepMasks s = step_masks(m, hm_before);
             writelane_into(pk.hs0, (uint32_t)s.hs, j);
             writelane_into(pk.hs1, (uint32_t)(s.hs >> 32), j);
@@ -227,10 +259,15 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
             writelane_into(pk.up1, (uint32_t)(s.up >> 32), j);
             writelane_into(pk.dn0, (uint32_t)s.dn, j);
             writelane_into(pk.dn1, (uint32_t)(s.dn >> 32), j);
+            hm_before = m.HM >> 63;
+        } else {
+            hm_before = 0;     // a block with no event has no high step
         }
-        hm_before = m.HM >> 63;
-        if (++j == 64) {
-            flush(64);
+        ++j;
+    }, [&]() {
+        // a group adds at most kGroupBlocks blocks, so lane j stays below 64
+        if (j > 64 - kGroupBlocks) {
+            flush(j);
             j = 0;
         }
     });
@@ -258,21 +295,25 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_walk_kernel(
     const uint32_t s = (g - chunk_base[t]) * chunk;
     const uint32_t len = min(s + chunk, n) - s;
     const Moves mv = moves_of(cfgs[cfg_of_trace ? cfg_of_trace[t] : 0]);
-    const uint64_t* in = masks + first_block(tbase, s, t);
+    const uint64_t b0 = first_block(tbase, s, t);
+    const uint64_t* in = masks + b0;
+    const uint32_t* in_map = reinterpret_cast<const uint32_t*>(masks + 3 * n_blocks) + b0;
     const uint32_t nblk = (len + 63) >> 6;
     int32_t x = (int32_t)entering[g];                  // level before the group
     uint32_t lsum = 0, trans = 0;
     for (uint32_t b0 = 0; b0 < nblk; b0 += 64) {
         const uint32_t j = b0 + lane;
         StepMasks sm{0, 0, 0};
+        ClampAdd f{0, mv.lmin, mv.lmax};
         uint32_t steps = 0;
         if (j < nblk) {
             sm.hs = in[j];
             sm.up = in[n_blocks + j];
             sm.dn = in[2 * n_blocks + j];
+            f = unpack_map(in_map[j]);
             steps = min(64u, len - 64 * j);
         }
-        const ClampAdd incl = wave_scan(block_map(sm, mv), lane);
+        const ClampAdd incl = wave_scan(f, lane);
         int32_t after = apply(incl, x);                // level after this lane's block
         int32_t before = __shfl_up(after, 1, 64);
         if (lane == 0) before = x;
@@ -291,22 +332,37 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_walk_kernel(
     }
 }
 
-// Fold 1: the level entering every chunk.
-__global__ __launch_bounds__(256) void stepped_enter_kernel(
+// Fold 1: the level entering every chunk.  One wave per trace; lane k takes
+// chunk k of each group of 64 chunks and an inclusive wave scan composes
+// their maps.
+__global__ __launch_bounds__(kWaves * kWave) void stepped_enter_kernel(
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
     const ClampAdd* __restrict__ funcs, uint32_t* __restrict__ entering)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * kWaves + wave_uniform(threadIdx.x >> 6);
     if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
-    int32_t x = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0].linit;
-    for (uint32_t k = chunk_base[t]; k < chunk_base[t + 1]; ++k) {
-        entering[k] = (uint32_t)x;
-        x = apply(funcs[k], x);
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    int32_t x = (int32_t)c.linit;
+    const uint32_t k1 = chunk_base[t + 1];
+    for (uint32_t k0 = chunk_base[t]; k0 < k1; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        ClampAdd f{0, (int32_t)c.lmin, (int32_t)c.lmax};
+        if (k < k1) {
+            f = funcs[k];
+            f.a = clamp_move(f.a);
+        }
+        const int32_t after = apply(wave_scan(f, lane), x);
+        int32_t before = __shfl_up(after, 1, 64);
+        if (lane == 0) before = x;
+        if (k < k1) entering[k] = (uint32_t)before;
+        x = __builtin_amdgcn_readlane(after, 63);
     }
 }
 
 // Pass 2 from the samples: levels, sums and decision bytes of every chunk.
+template <bool kAnyBase>
 __global__ __launch_bounds__(kWaves * kWave) void stepped_levels_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -322,7 +378,8 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_levels_kernel(
     int32_t x = (int32_t)entering[g];                 // level before the block
     uint64_t lsum = 0;                                 // per lane
     uint32_t trans = 0, th = 0;
-    for_each_block(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid, uint32_t) {
+    for_each_block<8, kAnyBase>(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid,
+                                             uint32_t) {
         int32_t lv;
         if (((m.E | m.HM)) == 0) {
             lv = x;                                    // 64 identity steps
@@ -372,24 +429,31 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_levels_kernel(
     }
 }
 
-__global__ __launch_bounds__(256) void stepped_fold_kernel(
+// One wave per trace: lane k adds chunks k, k + 64, ...
+__global__ __launch_bounds__(kWaves * kWave) void stepped_fold_kernel(
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const StepSum* __restrict__ sums, magus_result* __restrict__ results)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * kWaves + wave_uniform(threadIdx.x >> 6);
     if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
     uint64_t level_sum = 0, trans = 0, th = 0;
-    for (uint32_t k = chunk_base[t]; k < chunk_base[t + 1]; ++k) {
+    for (uint32_t k = chunk_base[t] + lane; k < chunk_base[t + 1]; k += 64) {
         level_sum += sums[k].level_sum;
         trans += sums[k].transitions;
         th += sums[k].ticks_high;
     }
-    magus_result r;
-    r.score = level_sum + 1000ull * trans;
-    r.level_sum = level_sum;
-    r.transitions = trans;
-    r.ticks_high = th;
-    results[t] = r;
+    level_sum = wave_sum_u64(level_sum);
+    trans = wave_sum_u64(trans);
+    th = wave_sum_u64(th);
+    if (lane == 0) {
+        magus_result r;
+        r.score = level_sum + 1000ull * trans;
+        r.level_sum = level_sum;
+        r.transitions = trans;
+        r.ticks_high = th;
+        results[t] = r;
+    }
 }
 
 }  // namespace
@@ -400,7 +464,8 @@ hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
                                  uint32_t* entering, StepSum* sums, uint64_t* masks,
                                  magus_result* results, uint8_t* levels, uint32_t* err,
-                                 hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
+                                 bool any_base, hipStream_t stream, hipEvent_t ev0,
+                                 hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
     hipError_t e = launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk,
@@ -409,22 +474,23 @@ hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
     const uint32_t blocks = (max_chunks + kWaves - 1) / kWaves;
     const uint64_t n_blocks = stepped_mask_blocks(n_samples, n_traces);
     if ((e = record_timing_event(ev0, stream)) != hipSuccess) return e;
-    stepped_mask_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
-        samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, n_blocks, funcs, sums,
-        masks);
-    stepped_enter_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
+    (any_base ? stepped_mask_kernel<true> : stepped_mask_kernel<false>)
+        <<<blocks, kWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base, cfgs,
+                                                cfg_of_trace, chunk, n_blocks, funcs, sums, masks);
+    const uint32_t trace_blocks = (n_traces + kWaves - 1) / kWaves;
+    stepped_enter_kernel<<<trace_blocks, kWaves * kWave, 0, stream>>>(
         n_traces, chunk_base, cfgs, cfg_of_trace, funcs, entering);
     if (levels)
-        stepped_levels_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
-            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, sums,
-            levels);
+        (any_base ? stepped_levels_kernel<true> : stepped_levels_kernel<false>)
+            <<<blocks, kWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base, cfgs,
+                                                    cfg_of_trace, chunk, entering, sums, levels);
     else
         stepped_walk_kernel<<<blocks, kWaves * kWave, 0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, n_blocks, entering, masks,
             sums);
     if ((e = record_timing_event(ev1, stream)) != hipSuccess) return e;
-    stepped_fold_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(n_traces, chunk_base, sums,
-                                                                    results);
+    stepped_fold_kernel<<<trace_blocks, kWaves * kWave, 0, stream>>>(n_traces, chunk_base, sums,
+                                                                     results);
     return hipGetLastError();
 }
 
