@@ -113,24 +113,36 @@ hipError_t record_timing_event(hipEvent_t ev, hipStream_t stream) {
 
 }  // namespace magus
 
-std::pair<hipEvent_t, hipEvent_t> magus_ctx::timing_pair(int kernel) {
-    if (!prof) return {nullptr, nullptr};
+magus_ctx::Timing::Timing(magus_ctx* c, int k) : ctx(c), kernel(k) {
+    if (!ctx->prof) return;
     hipEvent_t e[2] = {nullptr, nullptr};
     for (auto& ev : e) {
-        if (!ev_pool.empty()) {
-            ev = ev_pool.back();
-            ev_pool.pop_back();
+        if (!ctx->ev_pool.empty()) {
+            ev = ctx->ev_pool.back();
+            ctx->ev_pool.pop_back();
         } else if (hipEventCreate(&ev) != hipSuccess) {
             ev = nullptr;
         }
     }
     if (!e[0] || !e[1]) {
         for (auto ev : e)
-            if (ev) ev_pool.push_back(ev);
-        return {nullptr, nullptr};
+            if (ev) ctx->ev_pool.push_back(ev);
+        return;
     }
-    recorded[kernel].push_back({e[0], e[1]});
-    return {e[0], e[1]};
+    first = e[0];
+    second = e[1];
+}
+
+void magus_ctx::Timing::commit() {
+    if (first) ctx->recorded[kernel].push_back({first, second});
+    first = second = nullptr;
+}
+
+magus_ctx::Timing::~Timing() {
+    if (first) {
+        ctx->ev_pool.push_back(first);
+        ctx->ev_pool.push_back(second);
+    }
 }
 
 void magus_ctx::drop_graphs() {
@@ -387,7 +399,7 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     if (rc != MAGUS_OK) return rc;
     const void* before[7] = {ctx->chunk_base.p, ctx->sums.p, ctx->fix.p, ctx->step_funcs.p,
                              ctx->step_enter.p, ctx->step_sums.p, ctx->step_masks.p};
-    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4))) return rc;
+    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4))) return rc;
     if (stepped) {
         if ((rc = ctx->step_funcs.ensure((size_t)max_chunks * sizeof(ClampAdd))) ||
             (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
@@ -417,9 +429,10 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                              ctx->err.as<uint32_t>(), ctx->persistent_blocks, any_base, q, e0,
                              e1);
     };
-    const auto tp = ctx->timing_pair(MAGUS_KERNEL_REPLAY);
+    magus_ctx::Timing tp(ctx, MAGUS_KERNEL_REPLAY);
     if (!ctx->use_graphs) {
         HIP_TRY(launch(stream, tp.first, tp.second));
+        tp.commit();
         return MAGUS_OK;
     }
     // hipGraph path: the kernels of a call with these exact arguments are
@@ -493,6 +506,7 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
             return fail(MAGUS_EDEVICE, "graph timing node %d: %s", k, hipGetErrorString(se));
     }
     HIP_TRY(hipGraphLaunch(exec, stream));
+    tp.commit();
     return MAGUS_OK;
 }
 
@@ -549,7 +563,7 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     if (!stepped) {
         // one pass over the samples: plan, fused chunk pass, fold, metrics
         const void* before = ctx->chunk_base.p;
-        if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 3) * 4)) ||
+        if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
             (rc = ctx->proxy_sums.ensure((size_t)max_chunks * sizeof(ProxySum))))
             return rc;
         if (ctx->chunk_base.p != before) ctx->drop_graphs();
@@ -785,10 +799,11 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         return fail(MAGUS_EINVAL, "traces x config blocks too large for one call");
     int rc;
     if ((rc = ctx->keys.ensure(((size_t)n_traces + 1) * 8))) return rc;
-    const auto tp = ctx->timing_pair(MAGUS_KERNEL_SWEEP);
+    magus_ctx::Timing tp(ctx, MAGUS_KERNEL_SWEEP);
     HIP_TRY(launch_sweep(d_samples, n_samples, d_offsets, n_traces, ctx->plan, n_cfgs, d_scores,
                          d_argmin, ctx->keys.as<uint64_t>(), ctx->err.as<uint32_t>(), stream,
                          tp.first, tp.second));
+    tp.commit();
     return MAGUS_OK;
 }
 
@@ -945,10 +960,11 @@ int magus_serve_step(magus_server* s, const uint32_t* h_slots, const uint32_t* h
     if (n)
         HIP_TRY(hipMemcpyAsync(st.d_pairs.p, st.h_pairs, (size_t)n * 8, hipMemcpyHostToDevice,
                                stream));
-    const auto tp = s->ctx->timing_pair(MAGUS_KERNEL_SERVE);
+    magus_ctx::Timing tp(s->ctx, MAGUS_KERNEL_SERVE);
     HIP_TRY(launch_serve(s->st.as<SlotState>(), s->acc.as<SlotAcc>(), s->slot_cfg.as<DevCfg>(),
                          st.d_inits.as<ServeInit>(), n_inits, st.d_pairs.as<uint32_t>(), n,
                          st.d_dec.as<uint8_t>(), stream, tp.first, tp.second));
+    tp.commit();
     if (n)
         HIP_TRY(hipMemcpyAsync(h_decisions, st.d_dec.p, n, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipEventRecord(st.done, stream));

@@ -98,8 +98,19 @@ struct magus_ctx {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> recorded[3];
 
-    // Returns a pair of events to record for `kernel`, or nulls when off.
-    std::pair<hipEvent_t, hipEvent_t> timing_pair(int kernel);
+    // A pair of events to record around one launch of `kernel` (nulls when
+    // timing is off).  The pair counts for magus_ctx_kernel_time only once
+    // commit() says the launch was queued; otherwise it returns to the pool.
+    struct Timing {
+        magus_ctx* ctx;
+        int kernel;
+        hipEvent_t first = nullptr, second = nullptr;
+        Timing(magus_ctx* c, int k);
+        Timing(const Timing&) = delete;
+        Timing& operator=(const Timing&) = delete;
+        void commit();
+        ~Timing();
+    };
 };
 
 struct magus_server {

@@ -19,6 +19,19 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Inclusive wave scan (sum) with DPP: prefix sums within each row of 16
+// lanes, then the last lane of row 0 / of rows 0-1 is added into the rows
+// after it.  Lanes outside a row's shifted range read 0.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ uint64_t low_mask(uint32_t n) {   // n in [0, 64]
     return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
 }
@@ -30,85 +43,98 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
     const uint32_t* __restrict__ cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
     uint32_t max_chunks, uint32_t* __restrict__ chunk_base, uint32_t* __restrict__ err)
 {
-    // Thread i owns the contiguous traces [i*per, (i+1)*per): one pass counts
-    // their chunks, one block-wide scan places them, a second pass writes.
-    // Up to kCache traces per thread (8,192 traces) the offsets are loaded
-    // once, all at the same time, and the counts stay in registers.
-    constexpr uint32_t kCache = 8;
-    __shared__ uint32_t wave_sum[kPlanThreads / kWave];
+    // Rows of 1,024 consecutive traces; thread i takes trace i of every row,
+    // so each load and store of a row is coalesced.  Up to kRows rows (a
+    // "band") are counted at once with their counts in registers; a wave scan
+    // per row and one exchange of wave totals through LDS place them, and the
+    // band's total carries into the next band.
+    constexpr uint32_t kRows = 16;
+    constexpr uint32_t kPlanWaves = kPlanThreads / kWave;
+    __shared__ uint32_t wave_pre[kRows][kPlanWaves];   // wave totals, then bases
+    __shared__ uint32_t band_total;
     __shared__ uint32_t s_err;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_err = 0;
-    const uint32_t per = (n_traces + kPlanThreads - 1) / kPlanThreads;
-    const uint32_t t0 = min(tid * per, n_traces), t1 = min(t0 + per, n_traces);
-    auto count = [&](uint32_t t, uint64_t o0, uint64_t o1, uint32_t& e) -> uint32_t {
-        if (cfg_of_trace && cfg_of_trace[t] >= n_cfgs) e |= kErrCfgIndex;
-        if (o1 < o0 || o1 > n_samples) {
-            e |= kErrOffsets;
-            return 0;
-        }
-        if (o1 - o0 > MAGUS_MAX_TRACE_LEN) {
-            e |= kErrTooLong;
-            return 0;
-        }
-        return ((uint32_t)(o1 - o0) + chunk - 1) / chunk;   // both below 2^31
+    // a power-of-two chunk (the usual case) divides with a shift
+    const uint32_t chunk_shift = (chunk & (chunk - 1)) == 0 ? 31u - __builtin_clz(chunk) : 32u;
+    // chunks of a trace from its offsets and config index, with the checks
+    auto count = [&](uint64_t o0, uint64_t o1, uint32_t cfg, uint32_t& e) -> uint32_t {
+        if (cfg >= n_cfgs) e |= kErrCfgIndex;
+        const bool bad = o1 < o0 || o1 > n_samples;
+        const bool too_long = !bad && o1 - o0 > MAGUS_MAX_TRACE_LEN;
+        e |= (bad ? kErrOffsets : 0u) | (too_long ? kErrTooLong : 0u);
+        const uint32_t len = bad || too_long ? 0u : (uint32_t)(o1 - o0) + chunk - 1;
+        return chunk_shift < 32 ? len >> chunk_shift : len / chunk;
     };
-    const bool cached = per <= kCache;
-    uint32_t cnt[kCache];
-    uint32_t e = 0, mine = 0;
-    if (cached) {
-        uint64_t o[kCache + 1];
+    uint32_t e = 0, carry = 0;
+    for (uint32_t band = 0; band < n_traces; band += kRows * kPlanThreads) {
+        // all loads of the band first (an index past the end reads the last
+        // trace again), then the counts
+        uint64_t o0[kRows], o1[kRows];
+        uint32_t cf[kRows];
 #pragma unroll
-        for (uint32_t k = 0; k <= kCache; ++k) o[k] = t0 + k <= t1 ? offsets[t0 + k] : 0;
-#pragma unroll
-        for (uint32_t k = 0; k < kCache; ++k) {
-            cnt[k] = t0 + k < t1 ? count(t0 + k, o[k], o[k + 1], e) : 0u;
-            mine += cnt[k];
-        }
-    } else {
-        for (uint32_t t = t0; t < t1; ++t) mine += count(t, offsets[t], offsets[t + 1], e);
-    }
-    __syncthreads();
-    if (e) atomicOr(&s_err, e);
-    // exclusive scan of `mine` over the block
-    uint32_t v = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += o;
-    }
-    if (lane == 63) wave_sum[wv] = v;
-    __syncthreads();
-    if (wv == 0) {
-        uint32_t w = lane < kPlanThreads / kWave ? wave_sum[lane] : 0;
-#pragma unroll
-        for (int d = 1; d < kPlanThreads / kWave; d <<= 1) {
-            const uint32_t o = __shfl_up(w, d, 64);
-            if (lane >= (uint32_t)d) w += o;
-        }
-        if (lane < kPlanThreads / kWave) wave_sum[lane] = w;   // inclusive
-    }
-    __syncthreads();
-    uint32_t run = (wv ? wave_sum[wv - 1] : 0) + v - mine;
-    if (cached) {
-#pragma unroll
-        for (uint32_t k = 0; k < kCache; ++k)
-            if (t0 + k < t1) {
-                chunk_base[t0 + k] = run;
-                run += cnt[k];
+        for (uint32_t r = 0; r < kRows; ++r) {
+            const uint32_t row = band + r * kPlanThreads;   // uniform
+            o0[r] = o1[r] = 0;
+            cf[r] = 0;
+            if (row < n_traces) {
+                const uint32_t t = min(row + tid, n_traces - 1);
+                o0[r] = offsets[t];
+                o1[r] = offsets[t + 1];
+                if (cfg_of_trace) cf[r] = cfg_of_trace[t];
             }
-    } else {
-        for (uint32_t t = t0; t < t1; ++t) {
-            uint32_t dummy = 0;
-            chunk_base[t] = run;
-            run += count(t, offsets[t], offsets[t + 1], dummy);
         }
+        uint32_t excl[kRows];           // chunks of this row before the trace
+#pragma unroll
+        for (uint32_t r = 0; r < kRows; ++r)
+            excl[r] = band + r * kPlanThreads + tid < n_traces ? count(o0[r], o1[r], cf[r], e)
+                                                               : 0u;
+#pragma unroll
+        for (uint32_t r = 0; r < kRows; ++r) {
+            const uint32_t c = excl[r];
+            uint32_t v = c;
+            if (band + r * kPlanThreads < n_traces) v = wave_inclusive_sum(v);
+            excl[r] = v - c;
+            if (lane == 63) wave_pre[r][wv] = v;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            // lane r: exclusive prefix of row r's wave totals, then the rows
+            uint32_t row_total = 0;
+            if (lane < kRows)
+                for (uint32_t w = 0; w < kPlanWaves; ++w) row_total += wave_pre[lane][w];
+            uint32_t x = lane < kRows ? row_total : 0u;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_up(x, d, 64);
+                if (lane >= (uint32_t)d) x += o;
+            }
+            if (lane < kRows) {
+                uint32_t run = carry + x - row_total;
+                for (uint32_t w = 0; w < kPlanWaves; ++w) {
+                    const uint32_t tot = wave_pre[lane][w];
+                    wave_pre[lane][w] = run;
+                    run += tot;
+                }
+            }
+            if (lane == kRows - 1) band_total = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < kRows; ++r) {
+            const uint32_t row = band + r * kPlanThreads;
+            if (row < n_traces && row + tid < n_traces)
+                chunk_base[row + tid] = wave_pre[r][wv] + excl[r];
+        }
+        carry += band_total;
+        __syncthreads();                 // wave_pre and band_total are reused
     }
-    if (tid == kPlanThreads - 1) {
-        const uint32_t total = wave_sum[kPlanThreads / kWave - 1];
+    if (e) atomicOr(&s_err, e);
+    __syncthreads();
+    if (tid == 0) {
         uint32_t ee = s_err;
-        if (total > max_chunks) ee |= kErrOffsets;
-        chunk_base[n_traces] = ee ? 0u : total;
+        if (carry > max_chunks) ee |= kErrOffsets;
+        chunk_base[n_traces] = ee ? 0u : carry;
         chunk_base[n_traces + 1] = ee;           // status of this call
         if (ee) atomicOr(err, ee);
     }

@@ -212,11 +212,12 @@ extern "C" int magus_server_run(magus_server* srv, const magus_event* ev, uint64
                                srv->s_h2d));
         HIP_TRY(hipEventRecord(S.h2d, srv->s_h2d));
         HIP_TRY(hipStreamWaitEvent(srv->s_comp, S.h2d, 0));
-        const auto tp = srv->ctx->timing_pair(MAGUS_KERNEL_SERVE);
+        magus_ctx::Timing tp(srv->ctx, MAGUS_KERNEL_SERVE);
         HIP_TRY(launch_serve(srv->st.as<SlotState>(), srv->acc.as<SlotAcc>(),
                              srv->slot_cfg.as<DevCfg>(), S.d_inits.as<ServeInit>(), n_inits,
                              S.d_pairs.as<uint32_t>(), n, S.d_dec.as<uint8_t>(), srv->s_comp,
                              tp.first, tp.second));
+        tp.commit();
         HIP_TRY(hipEventRecord(S.kern, srv->s_comp));
         HIP_TRY(hipStreamWaitEvent(srv->s_d2h, S.kern, 0));
         HIP_TRY(hipMemcpyAsync(S.h_dec, S.d_dec.p, n, hipMemcpyDeviceToHost, srv->s_d2h));

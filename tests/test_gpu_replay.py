@@ -263,6 +263,22 @@ def test_persistent_grid_and_graph_replays_match(ctx, oracle_mod):
         ctx.set_persistent(0)
 
 
+@pytest.mark.parametrize("n_traces", [33000, 70000])
+def test_many_short_traces(ctx, oracle_mod, n_traces):
+    """More traces than the plan keeps in registers (32 per plan thread), with
+    empty and one-block traces among them, every result and decision byte."""
+    rng = np.random.default_rng(n_traces)
+    lens = rng.integers(0, 90, n_traces)
+    lens[rng.integers(0, n_traces, 50)] = rng.integers(4000, 9000, 50)
+    flat = rng.integers(1000, 60000, int(lens.sum())).astype(np.uint32)
+    bounds = np.concatenate([[0], np.cumsum(lens)])
+    traces = [flat[bounds[i]:bounds[i + 1]] for i in range(n_traces)]
+    grid = synth.sweep_grid()
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), 64)]
+    cot = rng.integers(0, len(cfgs), n_traces).astype(np.uint32)
+    run_both(ctx, oracle_mod, traces, cfgs, cot)
+
+
 def test_kernel_timing_inside_graphs(ctx, oracle_mod):
     """With timing on, each graph launch times its own chunk kernel: one
     launch per call, eager and graph calls alike, and the results stay right."""
