@@ -157,10 +157,14 @@ __global__ __launch_bounds__(kFoldWaves * kWave) void fold_kernel(
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kFoldWaves + uniform(threadIdx.x >> 6);
-    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
-    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
-    const uint64_t lmin = c.lmin, lmax = c.lmax;
+    if (t >= n_traces) return;
+    // the status, the chunk range and the config index load together
+    const uint32_t status = chunk_base[n_traces + 1];
     const uint32_t k0 = chunk_base[t], k1 = chunk_base[t + 1];
+    const uint32_t ci = cfg_of_trace ? cfg_of_trace[t] : 0;
+    if (status != 0) return;
+    const DevCfg c = cfgs[ci];
+    const uint64_t lmin = c.lmin, lmax = c.lmax;
     uint64_t level = c.linit;                 // level entering the current group
     uint64_t level_sum = 0, trans = 0, th = 0;
     for (uint32_t kb = k0; kb < k1; kb += 64) {
