@@ -196,7 +196,8 @@ int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t
 int magus_ctx_check(magus_ctx* ctx, hipStream_t stream);
 
 /*
- * Replay: runs every trace of a CSR batch through the controller.
+ * Replay: runs every trace of a CSR batch through the controller described
+ * above (Alg. 1, the event FIFO and Alg. 2 of Sec. 3.2, the decision rule).
  *   d_samples       uint32 throughput samples (MB/s), n_samples of them.
  *   d_offsets       n_traces+1 uint64, non-decreasing, trace t is
  *                   samples[offsets[t] .. offsets[t+1]), offsets[n_traces] <=
@@ -216,7 +217,9 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                  uint8_t* d_levels, hipStream_t stream);
 
 /*
- * Parameter sweep: every trace against every config.
+ * Parameter sweep: every trace against every config (the same controller as
+ * magus_replay for every pair; Alg. 1's window and thresholds and Alg. 2's
+ * FIFO length are the swept parameters).
  *   d_scores   NULL or n_traces * n_cfgs uint64, row-major [trace][config].
  *   d_argmin   n_traces uint32: index of the config with the lowest score,
  *              the lowest index among equal scores.
