@@ -12,13 +12,13 @@
 // Clamp-add maps are closed under composition (see compose()), so a time
 // chunk has one map.
 //
-// Pass 1 streams the samples once.  Per 64-step block it keeps only the
-// steps that can move the level, as three lane masks (raise by up_step, lower
-// by down_step, set level_max at the start of a run of high steps), parks
-// them in lane j of six registers for block j of a group of 64 blocks, and
-// per group writes them out (24 B per block) and composes the group's map:
-// lane j walks the set bits of its block, then a wave-wide tree composes the
-// 64 block maps.  A per-trace fold applies the chunk maps in order to find
+// Pass 1 streams the samples once.  Per 64-step block it parks the Alg. 1 /
+// Alg. 2 lane masks (events, rises, high steps) in lane j of six registers
+// for block j of a group of 64 blocks.  Per group each lane derives the steps
+// of its block that can move the level, as three masks (raise by up_step,
+// lower by down_step, set level_max at the start of a run of high steps),
+// writes them out (24 B per block) and walks their set bits to form the
+// block's map; a wave-wide tree composes the 64 block maps.  A per-trace fold applies the chunk maps in order to find
 // the level entering every chunk.  Pass 2 reads only the masks: lane j
 // composes its block's map again, an inclusive wave scan of the block maps
 // gives the level entering every block, and lane j walks its block once more
@@ -141,44 +141,55 @@ __device__ __forceinline__ void block_walk(const StepMasks& s, const Moves& mv, 
     lsum += (uint32_t)lv * (n - last);
 }
 
-// The masks of 64 blocks, block j in lane j, as three pairs of halves.
+// The Alg. 1 / Alg. 2 masks of 64 blocks (events, rises, high steps), block
+// j in lane j, as pairs of 32-bit halves.
 struct ParkedMasks {
-    uint32_t hs0, hs1, up0, up1, dn0, dn1;
-    __device__ __forceinline__ StepMasks get() const {
-        return StepMasks{((uint64_t)hs1 << 32) | hs0, ((uint64_t)up1 << 32) | up0,
-                         ((uint64_t)dn1 << 32) | dn0};
+    uint32_t e0, e1, r0, r1, h0, h1;
+    __device__ __forceinline__ BlockMasks get() const {
+        BlockMasks m;
+        m.E = ((uint64_t)e1 << 32) | e0;
+        m.R = ((uint64_t)r1 << 32) | r0;
+        m.HM = ((uint64_t)h1 << 32) | h0;
+        return m;
     }
 };
 
-// Ordered wave reduction: the composition of the maps of lanes 0..63 (lane 0
-// first), wave-uniform.
-__device__ __forceinline__ ClampAdd wave_compose(ClampAdd f, uint32_t lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        ClampAdd o;
-        o.a = __shfl_down(f.a, d, 64);
-        o.lo = __shfl_down(f.lo, d, 64);
-        o.hi = __shfl_down(f.hi, d, 64);
-        if (lane + d < 64) f = compose(f, o);
-    }
-    ClampAdd r;
-    r.a = __builtin_amdgcn_readfirstlane(f.a);
-    r.lo = __builtin_amdgcn_readfirstlane(f.lo);
-    r.hi = __builtin_amdgcn_readfirstlane(f.hi);
-    return r;
+// f of an earlier lane picked by a DPP control (row shift or row broadcast);
+// lanes with no such lane, or outside the rows of kRowMask, get `id`.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ ClampAdd dpp_earlier(const ClampAdd& f, const ClampAdd& id) {
+    ClampAdd o;
+    o.a = __builtin_amdgcn_update_dpp(id.a, f.a, kCtrl, kRowMask, 0xf, false);
+    o.lo = __builtin_amdgcn_update_dpp(id.lo, f.lo, kCtrl, kRowMask, 0xf, false);
+    o.hi = __builtin_amdgcn_update_dpp(id.hi, f.hi, kCtrl, kRowMask, 0xf, false);
+    return o;
 }
 
-// Inclusive wave scan: lane i gets the composition of the maps of lanes 0..i.
-__device__ __forceinline__ ClampAdd wave_scan(ClampAdd f, uint32_t lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        ClampAdd o;
-        o.a = __shfl_up(f.a, d, 64);
-        o.lo = __shfl_up(f.lo, d, 64);
-        o.hi = __shfl_up(f.hi, d, 64);
-        if (lane >= (uint32_t)d) f = compose(o, f);
-    }
+// Inclusive wave scan: lane i gets the composition of the maps of lanes 0..i
+// (lane 0 first).  Within each row of 16 lanes by shifts of 1, 2, 4 and 8,
+// then the last lane of row 0 / 2 is composed into rows 1 / 3 and the last
+// lane of row 1 into rows 2 and 3.  `id` is the identity map of the level
+// range; composing with it changes the representation of a map but not the
+// map on that range.
+__device__ __forceinline__ ClampAdd wave_scan(ClampAdd f, const ClampAdd& id) {
+    f = compose(dpp_earlier<0x111, 0xf>(f, id), f);   // row_shr:1
+    f = compose(dpp_earlier<0x112, 0xf>(f, id), f);   // row_shr:2
+    f = compose(dpp_earlier<0x114, 0xf>(f, id), f);   // row_shr:4
+    f = compose(dpp_earlier<0x118, 0xf>(f, id), f);   // row_shr:8
+    f = compose(dpp_earlier<0x142, 0xa>(f, id), f);   // row_bcast:15 into rows 1, 3
+    f = compose(dpp_earlier<0x143, 0xc>(f, id), f);   // row_bcast:31 into rows 2, 3
     return f;
+}
+
+// Ordered wave reduction: the composition of the maps of lanes 0..63,
+// wave-uniform.
+__device__ __forceinline__ ClampAdd wave_compose(ClampAdd f, const ClampAdd& id) {
+    f = wave_scan(f, id);
+    ClampAdd r;
+    r.a = __builtin_amdgcn_readlane(f.a, 63);
+    r.lo = __builtin_amdgcn_readlane(f.lo, 63);
+    r.hi = __builtin_amdgcn_readlane(f.hi, 63);
+    return r;
 }
 
 // A block map in one word for pass 2.  A move of 32 rungs or more saturates
@@ -230,38 +241,43 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
     uint64_t* out = masks + b0;
     uint32_t* out_map = reinterpret_cast<uint32_t*>(masks + 3 * n_blocks) + b0;
     ClampAdd F{0, mv.lmin, mv.lmax};                   // identity
-    uint32_t th = 0, j = 0;
-    uint64_t hm_before = 0;
+    uint32_t j = 0, th = 0;                            // th: per lane
+    uint32_t hm_carry = 0;     // the last block of the previous group ended high
+    // raw masks of block j in lane j (E, R, HM as halves); the step masks are
+    // derived per lane at the flush, once per 64 blocks
     ParkedMasks pk{0, 0, 0, 0, 0, 0};
     auto flush = [&](uint32_t cnt) {
-        const StepMasks s = pk.get();
-        const ClampAdd f = block_map(s, mv);
+        const BlockMasks m = pk.get();
+        th += (uint32_t)__popcll(m.HM);
+        // high before the block: the last step of block j-1 (lane j-1)
+        uint32_t before = (uint32_t)__shfl_up((int)(pk.h1 >> 31), 1, 64);
+        if (lane == 0) before = hm_carry;
+        hm_carry = (uint32_t)__builtin_amdgcn_readlane((int)(pk.h1 >> 31), (int)(cnt - 1));
+        const StepMasks sm = step_masks(m, before);
+        const ClampAdd f = block_map(sm, mv);
         if (lane < cnt) {
-            out[lane] = s.hs;
-            out[n_blocks + lane] = s.up;
-            out[2 * n_blocks + lane] = s.dn;
+            out[lane] = sm.hs;
+            out[n_blocks + lane] = sm.up;
+            out[2 * n_blocks + lane] = sm.dn;
             out_map[lane] = pack_map(f);
         }
         out += cnt;
         out_map += cnt;
-        F = compose(F, wave_compose(f, lane));
+        F = compose(F, wave_compose(f, ClampAdd{0, mv.lmin, mv.lmax}));
         F.a = clamp_move(F.a);
         pk = ParkedMasks{0, 0, 0, 0, 0, 0};
     };
     for_each_block<kGroupBlocks, kAnyBase>(v, lane, [&](const BlockMasks& m, uint32_t, uint64_t,
                                                         uint32_t) {
+        // a block with no event and no high step moves nothing; its lane
+        // stays zero
         if ((m.E | m.HM) != 0) {
-            th += (uint32_t)__popcll(m.HM);
-            const StepMasks s = step_masks(m, hm_before);
-            writelane_into(pk.hs0, (uint32_t)s.hs, j);
-            writelane_into(pk.hs1, (uint32_t)(s.hs >> 32), j);
-            writelane_into(pk.up0, (uint32_t)s.up, j);
-            writelane_into(pk.up1, (uint32_t)(s.up >> 32), j);
-            writelane_into(pk.dn0, (uint32_t)s.dn, j);
-            writelane_into(pk.dn1, (uint32_t)(s.dn >> 32), j);
-            hm_before = m.HM >> 63;
-        } else {
-            hm_before = 0;     // a block with no event has no high step
+            writelane_into(pk.e0, (uint32_t)m.E, j);
+            writelane_into(pk.e1, (uint32_t)(m.E >> 32), j);
+            writelane_into(pk.r0, (uint32_t)m.R, j);
+            writelane_into(pk.r1, (uint32_t)(m.R >> 32), j);
+            writelane_into(pk.h0, (uint32_t)m.HM, j);
+            writelane_into(pk.h1, (uint32_t)(m.HM >> 32), j);
         }
         ++j;
     }, [&]() {
@@ -272,6 +288,7 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
         }
     });
     if (j) flush(j);
+    th = (uint32_t)wave_sum_u64(th);
     if (lane == 0) {
         funcs[g] = F;
         sums[g].ticks_high = th;
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_walk_kernel(
             f = unpack_map(in_map[j]);
             steps = min(64u, len - 64 * j);
         }
-        const ClampAdd incl = wave_scan(f, lane);
+        const ClampAdd incl = wave_scan(f, ClampAdd{0, mv.lmin, mv.lmax});
         int32_t after = apply(incl, x);                // level after this lane's block
         int32_t before = __shfl_up(after, 1, 64);
         if (lane == 0) before = x;
@@ -353,7 +370,8 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_enter_kernel(
             f = funcs[k];
             f.a = clamp_move(f.a);
         }
-        const int32_t after = apply(wave_scan(f, lane), x);
+        const int32_t after =
+            apply(wave_scan(f, ClampAdd{0, (int32_t)c.lmin, (int32_t)c.lmax}), x);
         int32_t before = __shfl_up(after, 1, 64);
         if (lane == 0) before = x;
         if (k < k1) entering[k] = (uint32_t)before;
@@ -384,16 +402,9 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_levels_kernel(
         if (((m.E | m.HM)) == 0) {
             lv = x;                                    // 64 identity steps
         } else {
-            ClampAdd f = step_map(m, v.c, lane);
-            // inclusive scan: lane i gets the map of steps 0..i of the block
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                ClampAdd o;
-                o.a = __shfl_up(f.a, d, 64);
-                o.lo = __shfl_up(f.lo, d, 64);
-                o.hi = __shfl_up(f.hi, d, 64);
-                if (lane >= (uint32_t)d) f = compose(o, f);
-            }
+            // lane i gets the map of steps 0..i of the block
+            const ClampAdd f = wave_scan(step_map(m, v.c, lane),
+                                         ClampAdd{0, (int32_t)v.c.lmin, (int32_t)v.c.lmax});
             lv = apply(f, x);
         }
         int32_t before = __shfl_up(lv, 1, 64);
