@@ -26,8 +26,9 @@ struct BlockMasks {
     uint64_t HM;     // high state
 };
 
-// One block: x = this block's samples, xprev = the block before (lane i holds
-// step tb+i).  fps carries (flags of the block before) >> 1 and is updated.
+// One block: lane i holds step tb+i, b = its sample x[t] and a = x[t-W+1]
+// (from this block or the one before).  fps carries (flags of the block
+// before) >> 1 and is updated.
 // valid = lanes whose step exists; steps before W-1 of the trace never predict.
 // all_high = ~0 when the count threshold is 0 (every step is high), else 0.
 // kFull: every lane's step exists and the trace's FIFO is already full (the
@@ -35,17 +36,12 @@ struct BlockMasks {
 // is needed.  kAnyBase: the config may use another derivative base than the
 // smaller sample (else that base is assumed).
 template <bool kFull = false, bool kAnyBase = true>
-__device__ __forceinline__ BlockMasks block_masks(uint32_t x, uint32_t xprev, uint32_t tb,
+__device__ __forceinline__ BlockMasks block_masks(uint32_t a, uint32_t b, uint32_t tb,
                                                   uint64_t valid, const DevCfg& c,
                                                   uint64_t all_high, uint32_t k16,
                                                   uint64_t& fps, uint32_t lane)
 {
     const uint32_t W = c.W, H = c.H;
-    const int addr = (int)(((lane - (W - 1)) & 63u) << 2);
-    const uint32_t ac = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)x);
-    const uint32_t ap = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)xprev);
-    const uint32_t a = lane >= W - 1 ? ac : ap;      // x[t-W+1]
-    const uint32_t b = x;
     uint64_t vm = kFull ? ~0ull : valid;
     if (!kFull && tb < W - 1) vm &= ~mask_below(W - 1 - tb);
     BlockMasks r;
@@ -142,27 +138,40 @@ __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane
         return __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)((blk * 64 + lane) * 4), 0, 0);
     };
     uint64_t fps = 0;
-    uint32_t xprev = 0;
-    auto step = [&](uint32_t blk, uint32_t x, auto full_tag) {
+    uint32_t xprev = 0;                 // the last block of the group before
+    const int addr = (int)(((lane - (v.c.W - 1)) & 63u) << 2);
+    const bool from_cur = lane >= v.c.W - 1;
+    auto step = [&](uint32_t blk, uint32_t a, uint32_t x, auto full_tag) {
         constexpr bool kFull = decltype(full_tag)::value;
         const uint32_t tb = v.wbeg + blk * 64;
         const uint64_t valid = kFull ? ~0ull : mask_below(min(64u, v.e - tb));
-        const BlockMasks m = block_masks<kFull, kAnyBase>(x, xprev, tb, valid, v.c, v.all_high,
+        const BlockMasks m = block_masks<kFull, kAnyBase>(a, x, tb, valid, v.c, v.all_high,
                                                           v.k16, fps, lane);
-        xprev = x;
         if (kFull || blk >= first_real) body(m, tb, valid, x);
     };
     // blocks [1, nfull) hold 64 steps each and never start the trace
     const uint32_t nfull = (v.e - v.wbeg) >> 6;
     auto group = [&](uint32_t g, const uint32_t (&cur)[kAhead]) {
+        // x[t-W+1] of every step of the group, all lane exchanges issued
+        // before any block is evaluated
+        uint32_t a[kAhead];
+#pragma unroll
+        for (uint32_t k = 0; k < kAhead; ++k) {
+            const uint32_t ac = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)cur[k]);
+            const uint32_t ap =
+                (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(k ? cur[k - 1] : xprev));
+            a[k] = from_cur ? ac : ap;
+        }
         if (g >= 1 && (g + 1) * kAhead <= nfull) {
 #pragma unroll
-            for (uint32_t k = 0; k < kAhead; ++k) step(g * kAhead + k, cur[k], std::true_type{});
+            for (uint32_t k = 0; k < kAhead; ++k)
+                step(g * kAhead + k, a[k], cur[k], std::true_type{});
         } else {
 #pragma unroll
             for (uint32_t k = 0; k < kAhead; ++k)
-                if (g * kAhead + k < nblk) step(g * kAhead + k, cur[k], std::false_type{});
+                if (g * kAhead + k < nblk) step(g * kAhead + k, a[k], cur[k], std::false_type{});
         }
+        xprev = cur[kAhead - 1];
         group_end();
     };
     // two alternating groups of kAhead blocks: one is evaluated while the
