@@ -202,6 +202,48 @@ def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, p
     del pst, pme
 
 
+# Serving: 65,536 simulated nodes through the continuous-batching loop, in
+# real time (decision latency) and flat out (throughput).
+def bench_serve(magus, synth, np, ctx, grid, grid_arr, args, extra, checks):
+    log("serving: 65,536 nodes, continuous batching in real time ...")
+    t0 = time.time()
+    ev, n_streams, cfg_of_stream = synth.serve_fleet_events(65536, args.serve_ticks)
+    n_ev_samples = int((ev["kind"] == synth.EV_SAMPLE).sum())
+    log(f"  {len(ev)} events ({n_ev_samples} samples) generated in {time.time() - t0:.1f} s")
+    srv = magus.Server(ctx, (65536 + 256) * magus.Server.slot_bytes())
+    dec, lat, st = srv.run(ev, n_streams, grid_arr, realtime=True, depth=2)
+    served = (ev["kind"] == synth.EV_SAMPLE) & (dec != 0xFF)
+    lat_ms = lat[served].astype(np.float64) * 1e-6
+    # parity of sampled nodes against the oracle replay of their served samples
+    sids = np.unique(ev["stream"][served])[::4099]
+    snodes = []
+    for sid in sids:
+        m = served & (ev["stream"] == sid)
+        snodes.append((sid, ev["value"][m].copy(), grid[int(cfg_of_stream[sid])], dec[m].copy()))
+
+    def check_serve(oracle):
+        for sid, x, c, d in snodes:
+            _, want = oracle.replay_trace(x, c)
+            if not (d == want).all():
+                raise SystemExit(f"serving parity failure on node {sid}")
+        extra["serve"]["parity"] = f"ok: {len(snodes)} sampled nodes equal the oracle"
+    checks.append(check_serve)
+    dec2, lat2, st2 = srv.run(ev, n_streams, grid_arr, realtime=False, depth=3)
+    srv.close()
+    extra["serve"] = {
+        "workload": f"65,536 nodes + Poisson joins/leaves 50/s, {args.serve_ticks} ticks of "
+                    "100 ms +- 10 ms, memory budget 65,792 slots",
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "samples_per_s_realtime": st["samples_served"] / st["wall_s"],
+        "batches": st["batches"], "max_batch": st["max_batch"],
+        "joins_admitted": st["joins_admitted"], "joins_waited": st["joins_waited"],
+        "samples_dropped": st["samples_dropped"],
+        "flat_out_samples_per_s": st2["samples_served"] / st2["wall_s"],
+        "parity": "not checked (--no-cpu)"}
+    log(f"  serve p50 {extra['serve']['p50_ms']:.3f} ms p99 {extra['serve']['p99_ms']:.3f} ms, "
+        f"flat-out {extra['serve']['flat_out_samples_per_s']:.3e} samples/s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,7 +258,7 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only run the configuration sweep and print its figures")
-    ap.add_argument("--only", choices=["stepped", "proxy"],
+    ap.add_argument("--only", choices=["stepped", "proxy", "serve"],
                     help="only run this report on the bulk workload (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy kernel over as many bytes as the "
@@ -267,9 +309,13 @@ def main():
     cfg_arr = magus.config_array([cfg])
     if args.only:
         extra = {}
-        fn = bench_stepped if args.only == "stepped" else bench_proxy
-        fn(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, [0], args, dev, extra,
-           [])
+        if args.only == "serve":
+            grid = synth.sweep_grid()
+            bench_serve(magus, synth, np, ctx, grid, magus.config_array(grid), args, extra, [])
+        else:
+            fn = bench_stepped if args.only == "stepped" else bench_proxy
+            fn(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, [0], args, dev,
+               extra, [])
         ctx.close()
         print(json.dumps({"extra": extra}), flush=True)
         return
@@ -456,43 +502,7 @@ def main():
         uctx.close()
         del us, uo, uc, usmp
 
-        log("serving: 65,536 nodes, continuous batching in real time ...")
-        t0 = time.time()
-        ev, n_streams, cfg_of_stream = synth.serve_fleet_events(65536, args.serve_ticks)
-        n_ev_samples = int((ev["kind"] == synth.EV_SAMPLE).sum())
-        log(f"  {len(ev)} events ({n_ev_samples} samples) generated in {time.time() - t0:.1f} s")
-        srv = magus.Server(ctx, (65536 + 256) * magus.Server.slot_bytes())
-        dec, lat, st = srv.run(ev, n_streams, grid_arr, realtime=True, depth=2)
-        served = (ev["kind"] == synth.EV_SAMPLE) & (dec != 0xFF)
-        lat_ms = lat[served].astype(np.float64) * 1e-6
-        # parity of sampled nodes against the oracle replay of their served samples
-        sids = np.unique(ev["stream"][served])[::4099]
-        snodes = []
-        for sid in sids:
-            m = served & (ev["stream"] == sid)
-            snodes.append((sid, ev["value"][m].copy(), grid[int(cfg_of_stream[sid])], dec[m].copy()))
-
-        def check_serve(oracle):
-            for sid, x, c, d in snodes:
-                _, want = oracle.replay_trace(x, c)
-                if not (d == want).all():
-                    raise SystemExit(f"serving parity failure on node {sid}")
-            extra["serve"]["parity"] = f"ok: {len(snodes)} sampled nodes equal the oracle"
-        checks.append(check_serve)
-        dec2, lat2, st2 = srv.run(ev, n_streams, grid_arr, realtime=False, depth=3)
-        srv.close()
-        extra["serve"] = {
-            "workload": f"65,536 nodes + Poisson joins/leaves 50/s, {args.serve_ticks} ticks of "
-                        "100 ms +- 10 ms, memory budget 65,792 slots",
-            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-            "samples_per_s_realtime": st["samples_served"] / st["wall_s"],
-            "batches": st["batches"], "max_batch": st["max_batch"],
-            "joins_admitted": st["joins_admitted"], "joins_waited": st["joins_waited"],
-            "samples_dropped": st["samples_dropped"],
-            "flat_out_samples_per_s": st2["samples_served"] / st2["wall_s"],
-            "parity": "not checked (--no-cpu)"}
-        log(f"  serve p50 {extra['serve']['p50_ms']:.3f} ms p99 {extra['serve']['p99_ms']:.3f} ms, "
-            f"flat-out {extra['serve']['flat_out_samples_per_s']:.3e} samples/s")
+        bench_serve(magus, synth, np, ctx, grid, grid_arr, args, extra, checks)
         out["extra"] = extra
 
     if not args.no_cpu:

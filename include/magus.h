@@ -365,9 +365,10 @@ int magus_stream_result(magus_server* srv, uint32_t slot, magus_result* h_out);
  * time; realtime == 0 runs flat out (latency from the start of the run).
  * Every dispatch forms one batch of at most max_batch pairs (0: the server's
  * capacity) from the oldest pending sample of each admitted node, and up to
- * `depth` (1..4) batches are in flight: copies in, the state-update kernel and
- * the copy out run on three server-owned streams, so one batch's copies
- * overlap another's kernel; kernels run in arrival order.
+ * `depth` (1..4) batches are in flight.  The state-update kernel reads each
+ * batch from pinned host memory and writes its decisions back into pinned
+ * host memory directly (no copies), on a server-owned stream, so kernels
+ * run in arrival order.
  * Per event i: h_decisions[i] = decision byte of a served sample (0xFF for
  * other events and dropped samples), h_latency_ns[i] = event time to
  * decision visible in host memory (UINT64_MAX if none).  Stream ids must be

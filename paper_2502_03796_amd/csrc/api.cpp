@@ -954,16 +954,13 @@ int magus_serve_step(magus_server* s, const uint32_t* h_slots, const uint32_t* h
     }
     std::memcpy(st.h_pairs, h_slots, (size_t)n * 4);
     std::memcpy(st.h_pairs + n, h_samples, (size_t)n * 4);
-    if (n_inits)
-        HIP_TRY(hipMemcpyAsync(st.d_inits.p, st.h_inits, (size_t)n_inits * sizeof(ServeInit),
-                               hipMemcpyHostToDevice, stream));
-    if (n)
-        HIP_TRY(hipMemcpyAsync(st.d_pairs.p, st.h_pairs, (size_t)n * 8, hipMemcpyHostToDevice,
-                               stream));
+    // the kernel reads the pairs and slot inits from the pinned staging
+    // buffers directly; the decisions come back with one copy (the caller's
+    // buffer may be pageable)
     magus_ctx::Timing tp(s->ctx, MAGUS_KERNEL_SERVE);
     HIP_TRY(launch_serve(s->st.as<SlotState>(), s->acc.as<SlotAcc>(), s->slot_cfg.as<DevCfg>(),
-                         st.d_inits.as<ServeInit>(), n_inits, st.d_pairs.as<uint32_t>(), n,
-                         st.d_dec.as<uint8_t>(), stream, tp.first, tp.second));
+                         st.h_inits, n_inits, st.h_pairs, n, st.d_dec.as<uint8_t>(), stream,
+                         tp.first, tp.second));
     tp.commit();
     if (n)
         HIP_TRY(hipMemcpyAsync(h_decisions, st.d_dec.p, n, hipMemcpyDeviceToHost, stream));

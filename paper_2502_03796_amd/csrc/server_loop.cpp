@@ -2,11 +2,13 @@
 //
 // Telemetry events (samples, joins, leaves of simulated nodes) are ingested as
 // they arrive; every dispatch forms one batch from the oldest pending sample
-// of each live stream and sends it through three server-owned streams: the
-// host-to-device copy, the state-update kernel and the decision copy back run
-// as a pipeline, so the copies of one batch overlap the kernel of another,
-// while the kernels themselves stay in arrival order (a stream's state update
-// of step k+1 needs the one of step k).  Joins are admitted while slots (the
+// of each live stream in a pinned host buffer of one of up to `depth` stages
+// and launches the state-update kernel on a server-owned stream.  The kernel
+// reads the batch and writes the decisions through the pinned buffers
+// directly, so a batch costs one launch and no copy-engine round trips;
+// batches of several stages are in flight at once, and the kernels stay in
+// arrival order (a stream's state update of step k+1 needs the one of step
+// k).  Joins are admitted while slots (the
 // memory budget) allow, otherwise they wait for a leave; a leave closes the
 // slot once the stream's pending samples are served.
 
@@ -205,23 +207,15 @@ extern "C" int magus_server_run(magus_server* srv, const magus_event* ev, uint64
             ++q;
         }
         srv->pending.clear();
-        if (n_inits)
-            HIP_TRY(hipMemcpyAsync(S.d_inits.p, S.h_inits, (size_t)n_inits * sizeof(ServeInit),
-                                   hipMemcpyHostToDevice, srv->s_h2d));
-        HIP_TRY(hipMemcpyAsync(S.d_pairs.p, S.h_pairs, (size_t)n * 8, hipMemcpyHostToDevice,
-                               srv->s_h2d));
-        HIP_TRY(hipEventRecord(S.h2d, srv->s_h2d));
-        HIP_TRY(hipStreamWaitEvent(srv->s_comp, S.h2d, 0));
+        // the kernel reads the batch (slot inits, pairs) from the stage's
+        // pinned host buffers and writes the decisions back into pinned host
+        // memory: no copy-engine round trips between arrival and decision
         magus_ctx::Timing tp(srv->ctx, MAGUS_KERNEL_SERVE);
         HIP_TRY(launch_serve(srv->st.as<SlotState>(), srv->acc.as<SlotAcc>(),
-                             srv->slot_cfg.as<DevCfg>(), S.d_inits.as<ServeInit>(), n_inits,
-                             S.d_pairs.as<uint32_t>(), n, S.d_dec.as<uint8_t>(), srv->s_comp,
-                             tp.first, tp.second));
+                             srv->slot_cfg.as<DevCfg>(), S.h_inits, n_inits, S.h_pairs, n,
+                             S.h_dec, srv->s_comp, tp.first, tp.second));
         tp.commit();
-        HIP_TRY(hipEventRecord(S.kern, srv->s_comp));
-        HIP_TRY(hipStreamWaitEvent(srv->s_d2h, S.kern, 0));
-        HIP_TRY(hipMemcpyAsync(S.h_dec, S.d_dec.p, n, hipMemcpyDeviceToHost, srv->s_d2h));
-        HIP_TRY(hipEventRecord(S.done, srv->s_d2h));
+        HIP_TRY(hipEventRecord(S.done, srv->s_comp));
         ++st.batches;
         st.max_batch = std::max<uint64_t>(st.max_batch, n);
         flight.push_back(std::move(b));
