@@ -25,6 +25,18 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// v + w + this lane's bit of the wave-uniform mask m, as one add with carry-in
+// (the mask is the carry), so a lane-mask bit needs no conversion to 0/1.
+__device__ __forceinline__ uint32_t add_bit(uint32_t v, uint32_t w, uint64_t m) {
+    uint32_t r;
+    uint64_t carry_out;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %3, %4"
+        : "=v"(r), "=s"(carry_out) : "v"(v), "v"(w), "s"(m));
+    return r;
+}
+
+__device__ __forceinline__ uint64_t wave_mask(bool p) { return __ballot(p); }
+
 // Quotients of step t (t >= W-1) of trace x.  The derivative's base is the
 // smaller sample by default (a for a rise, b for a fall), or always the
 // oldest (base 1) or always the newest (base 2) sample.
@@ -143,33 +155,28 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
                 lvl = nl;
             }
         } else {
+            // the decisions of all lanes as wave masks (every lane runs
+            // every step): the logic is scalar, and each mask bit enters the
+            // lane's history and counters as the carry of one add
+            const uint32_t zero = 0;
+            uint64_t lvl_m = wave_mask(lvl);
+            auto one_step = [&](const int2 v) {
+                const uint64_t up = wave_mask(inc < v.x), dn = wave_mask(dec > v.y);
+                hist = add_bit(hist, hist, up | dn) & hmask;
+                const uint64_t high = wave_mask((uint32_t)__popc(hist) >= thr);
+                const uint64_t nl = high | up | (lvl_m & ~dn);
+                trans = add_bit(trans, zero, nl ^ lvl_m);
+                cmax = add_bit(cmax, zero, nl);
+                lvl_m = nl;
+            };
             uint32_t i = 0;
 #pragma unroll 1
             for (; i + 4 <= nt; i += 4) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int2 v = q[i + k];
-                    const bool up = inc < v.x, dn = dec > v.y;
-                    hist = ((hist << 1) | (uint32_t)(up | dn)) & hmask;
-                    const bool high = (uint32_t)__popc(hist) >= thr;
-                    const bool upx = high | up;
-                    const bool nl = upx | (lvl & !dn);
-                    trans += (uint32_t)(nl != lvl);
-                    cmax += (uint32_t)nl;
-                    lvl = nl;
-                }
+                for (int k = 0; k < 4; ++k) one_step(q[i + k]);
             }
-            for (; i < nt; ++i) {
-                const int2 v = q[i];
-                const bool up = inc < v.x, dn = dec > v.y;
-                hist = ((hist << 1) | (uint32_t)(up | dn)) & hmask;
-                const bool high = (uint32_t)__popc(hist) >= thr;
-                const bool upx = high | up;
-                const bool nl = upx | (lvl & !dn);
-                trans += (uint32_t)(nl != lvl);
-                cmax += (uint32_t)nl;
-                lvl = nl;
-            }
+            for (; i < nt; ++i) one_step(q[i]);
+            lvl = (lvl_m >> (threadIdx.x & 63)) & 1ull;
         }
         if (tile0 + kTile < n) prepass(tile0 + kTile, buf ^ 1);
         __syncthreads();
