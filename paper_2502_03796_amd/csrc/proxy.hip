@@ -62,6 +62,25 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 
 __device__ __forceinline__ uint32_t over(uint32_t x, uint32_t cap) { return x > cap ? x - cap : 0u; }
 
+// Inclusive wave sum with DPP (row shifts, then row broadcasts); the total is
+// in lane 63.
+__device__ __forceinline__ uint32_t dpp_wave_sum(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Sum over the wave of 32-bit values (up to 2^38 in all): the two 16-bit
+// halves are summed separately so that each fits in 32 bits.
+__device__ __forceinline__ uint64_t wave_sum_u32(uint32_t v) {
+    const uint64_t lo = dpp_wave_sum(v & 0xFFFFu), hi = dpp_wave_sum(v >> 16);
+    return (hi << 16) + lo;
+}
+
 __global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -112,8 +131,8 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
             const uint32_t x = xs[k], l = ls[k];
             const uint32_t o_hi = over(x, cap_hi), o_lo = over(x, cap_lo);
             const bool at_lo = live && l == lmin, at_hi = live && l == lmax;
-            n_lo += at_lo;
-            n_hi += at_hi;
+            n_lo += (uint32_t)__builtin_popcountll(__ballot(at_lo));    // wave-uniform
+            n_hi += (uint32_t)__builtin_popcountll(__ballot(at_hi));
             x_lo += at_lo ? o_lo : 0u;
             x_hi += at_hi ? o_hi : 0u;
             ex_max += o_hi;                   // 0 for lanes past the end (x = 0)
@@ -122,10 +141,11 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
             // initial level inside the range): one pass per distinct level
             uint64_t other = __ballot(live && !at_lo && !at_hi);
             while (other) {
-                const uint32_t l0 = uniform(__shfl(l, (int)__builtin_ctzll(other), 64));
+                const uint32_t l0 =
+                    (uint32_t)__builtin_amdgcn_readlane((int)l, (int)__builtin_ctzll(other));
                 const bool mine = live && l == l0;
                 const uint64_t m = __ballot(mine);
-                const uint64_t sx = wave_sum(mine ? over(x, s_cap[l0]) : 0u);
+                const uint64_t sx = wave_sum_u32(mine ? over(x, s_cap[l0]) : 0u);
                 if (lane == l0) {
                     bin_n += (uint64_t)__builtin_popcountll(m);
                     bin_x += sx;
@@ -134,8 +154,6 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
             }
         }
     }
-    n_lo = wave_sum(n_lo);
-    n_hi = wave_sum(n_hi);
     x_lo = wave_sum(x_lo);
     x_hi = wave_sum(x_hi);
     ex_max = wave_sum(ex_max);
