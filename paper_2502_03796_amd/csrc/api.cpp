@@ -245,8 +245,8 @@ int magus_ctx_destroy(magus_ctx* ctx) {
         (void)hipDeviceSynchronize();
         for (DevBuf* b : {&ctx->err, &ctx->chunk_base, &ctx->sums, &ctx->fix, &ctx->cfgs,
                           &ctx->keys, &ctx->sweep_tab, &ctx->step_funcs, &ctx->step_enter,
-                          &ctx->step_sums, &ctx->step_masks, &ctx->status, &ctx->proxy_levels,
-                          &ctx->proxy_results, &ctx->proxy_model, &ctx->proxy_sums})
+                          &ctx->step_sums, &ctx->step_masks, &ctx->status,
+                          &ctx->proxy_model, &ctx->proxy_sums})
             b->release();
         for (auto& r : ctx->recorded)
             for (auto& pr : r) {
@@ -577,19 +577,32 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                    stream));
         return MAGUS_OK;
     }
-    // stepped actuation: the replay writes every step's level, then a pass
-    // over samples and levels
-    if ((rc = ctx->proxy_levels.ensure(std::max<uint64_t>(n_samples, 1))) ||
-        (rc = ctx->proxy_results.ensure((size_t)n_traces * sizeof(magus_result))))
+    // stepped actuation: pass 1 of the stepped replay (plan, step masks, the
+    // level entering every chunk), then one pass over samples and masks
+    const void* before[5] = {ctx->chunk_base.p, ctx->step_funcs.p, ctx->step_enter.p,
+                             ctx->step_sums.p, ctx->step_masks.p};
+    if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
+        (rc = ctx->step_funcs.ensure((size_t)max_chunks * sizeof(ClampAdd))) ||
+        (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
+        (rc = ctx->step_sums.ensure((size_t)max_chunks * sizeof(StepSum))) ||
+        (rc = ctx->step_masks.ensure((size_t)stepped_mask_blocks(n_samples, n_traces) *
+                                     (3 * sizeof(uint64_t) + sizeof(uint32_t)))))
         return rc;
-    if ((rc = magus_replay(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
-                           d_cfg_of_trace, ctx->proxy_results.as<magus_result>(),
-                           ctx->proxy_levels.as<uint8_t>(), stream)))
-        return rc;
-    HIP_TRY(launch_proxy(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
-                         max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
-                         ctx->proxy_levels.as<uint8_t>(),
-                         ctx->proxy_model.as<magus_proxy_model>(), d_stats, d_metrics, stream));
+    const void* after[5] = {ctx->chunk_base.p, ctx->step_funcs.p, ctx->step_enter.p,
+                            ctx->step_sums.p, ctx->step_masks.p};
+    if (std::memcmp(before, after, sizeof before) != 0) ctx->drop_graphs();
+    HIP_TRY(launch_stepped_prepare(d_samples, n_samples, d_offsets, n_traces,
+                                   ctx->cfgs.as<DevCfg>(), n_cfgs, d_cfg_of_trace, ctx->chunk,
+                                   ctx->chunk_base.as<uint32_t>(), max_chunks,
+                                   ctx->step_funcs.as<ClampAdd>(), ctx->step_enter.as<uint32_t>(),
+                                   ctx->step_sums.as<StepSum>(), ctx->step_masks.as<uint64_t>(),
+                                   ctx->err.as<uint32_t>(), any_base, stream));
+    HIP_TRY(launch_proxy_stepped(d_samples, n_samples, d_offsets, n_traces,
+                                 ctx->chunk_base.as<uint32_t>(), max_chunks,
+                                 ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
+                                 ctx->step_enter.as<uint32_t>(), ctx->step_masks.as<uint64_t>(),
+                                 ctx->proxy_model.as<magus_proxy_model>(), d_stats, d_metrics,
+                                 stream));
     return MAGUS_OK;
 }
 

@@ -73,8 +73,6 @@ struct magus_ctx {
     magus::DevBuf sweep_tab;    // sweep: lane tables
     std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
     magus::SweepPlan plan{};
-    magus::DevBuf proxy_levels;   // proxy: decision bytes of the replay
-    magus::DevBuf proxy_results;  // proxy: replay results (not returned)
     magus::DevBuf proxy_model;    // proxy: the model in device memory
     magus::DevBuf proxy_sums;     // proxy: per-chunk summaries of the fused pass
     magus_proxy_model proxy_model_host{};   // ... as last uploaded

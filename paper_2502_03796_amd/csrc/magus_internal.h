@@ -159,10 +159,29 @@ hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  bool any_base, hipStream_t stream, hipEvent_t ev0,
                                  hipEvent_t ev1);
 // Slots per array of the stepped replay's block scratch (one slot per
-// 64-step block): three uint64 step-mask arrays and one uint32 map array.
+// 64-step block): three uint64 step-mask arrays (moves up, down, set max) and
+// one uint32 map array.
 inline uint64_t stepped_mask_blocks(uint64_t n_samples, uint32_t n_traces) {
     return n_samples / 64 + n_traces + 1;
 }
+// Slot of the first block of a chunk starting at step s of trace t (first
+// sample tbase): blocks of one trace start 64 steps apart, so
+// (absolute first step) / 64 + trace is one-to-one over all blocks of a batch
+// and stays below stepped_mask_blocks().
+__host__ __device__ __forceinline__ uint64_t first_block(uint64_t tbase, uint32_t s, uint32_t t) {
+    return (tbase + s) / 64 + t;
+}
+// Pass 1 of the stepped replay and the fold of the chunk maps: the step
+// masks of every block, the map of every chunk and the level entering every
+// chunk (what the proxy statistics need without the replay's pass 2).  ev0,
+// if not null, is recorded after the plan kernel.
+hipError_t launch_stepped_prepare(const uint32_t* samples, uint64_t n_samples,
+                                  const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
+                                  uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
+                                  uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
+                                  uint32_t* entering, StepSum* sums, uint64_t* masks,
+                                  uint32_t* err, bool any_base, hipStream_t stream,
+                                  hipEvent_t ev0 = nullptr);
 
 // Counter readings to MB/s samples (frontend.hip).
 hipError_t launch_counters(const uint64_t* counts, const uint64_t* ts, const uint64_t* offsets,

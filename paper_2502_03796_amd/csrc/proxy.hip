@@ -23,14 +23,17 @@
 //               excess sums per level -> ProxySum
 //   fused fold  one wave per trace -> magus_proxy_stats
 //   metrics     as below
-// Stepped configs take the general path:
-// Kernels, in stream order (after the replay that wrote the decision bytes):
+// Stepped configs take the path over the stepped replay's pass 1 (its step
+// masks and the level entering every chunk, stepped.hip):
 //   zero     clears the statistics (no memset node, so the sequence can be
 //            captured into a graph)
-//   stats    one wave per replay chunk, HBM-bound: reads 4 B of sample and
-//            1 B of decision per step, integer sums in registers (levels
-//            strictly between the bounds: lane l keeps level l's sums), one
-//            atomic add per non-zero sum per chunk
+//   stepped  one wave per chunk: reads the samples and the step masks, walks
+//            the level through each block in scalar registers from the chunk's
+//            entering level, and sums per level: a block at one level adds to
+//            a run at that level (per lane); a block whose level changes scans
+//            its per-step excess once and takes each segment's sum from the
+//            scan at the segment's ends; one atomic add per non-zero sum per
+//            chunk
 //   metrics  one thread per trace: the seven figures of each policy in FP64
 
 #include "block_masks.h"
@@ -44,7 +47,6 @@ static_assert(sizeof(magus_proxy_stats) == 16 + 8 * 64, "magus_proxy_stats layou
 static_assert(sizeof(magus_proxy_metrics) == 7 * 3 * 8, "magus_proxy_metrics layout");
 
 constexpr int kStatsWaves = 4;
-constexpr uint32_t kUnroll = 4;        // steps per lane in flight
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -62,44 +64,68 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 
 __device__ __forceinline__ uint32_t over(uint32_t x, uint32_t cap) { return x > cap ? x - cap : 0u; }
 
-// Inclusive wave sum with DPP (row shifts, then row broadcasts); the total is
-// in lane 63.
-__device__ __forceinline__ uint32_t dpp_wave_sum(uint32_t v) {
+// Inclusive wave scan with DPP: row shifts build the scan within each row of
+// 16 lanes, row broadcasts carry the totals of the rows before.
+__device__ __forceinline__ uint32_t dpp_scan(uint32_t v) {
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    return v;
 }
 
-// Sum over the wave of 32-bit values (up to 2^38 in all): the two 16-bit
-// halves are summed separately so that each fits in 32 bits.
-__device__ __forceinline__ uint64_t wave_sum_u32(uint32_t v) {
-    const uint64_t lo = dpp_wave_sum(v & 0xFFFFu), hi = dpp_wave_sum(v >> 16);
-    return (hi << 16) + lo;
+// v plus the value of the lane the DPP control names, in 64 bits
+template <int kCtrl, int kRowMask, bool kBound>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl,
+                                                              kRowMask, 0xf, kBound);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32),
+                                                              kCtrl, kRowMask, 0xf, kBound);
+    return v + (((uint64_t)hi << 32) | lo);
 }
 
-__global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+// Wave sum of 64-bit values with the steps of dpp_scan (no LDS traffic).
+__device__ __forceinline__ uint64_t dpp_wave_sum64(uint64_t v) {
+    v = dpp_add64<0x111, 0xf, true>(v);
+    v = dpp_add64<0x112, 0xf, true>(v);
+    v = dpp_add64<0x114, 0xf, true>(v);
+    v = dpp_add64<0x118, 0xf, true>(v);
+    v = dpp_add64<0x142, 0xa, false>(v);
+    v = dpp_add64<0x143, 0xc, false>(v);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
 }
 
-// One wave per chunk of the replay that produced `levels` (same chunk plan).
-__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
+// a in the lanes whose bit of the wave-uniform mask is set, else b
+__device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_t b) {
+    const uint64_t m = ((uint64_t)uniform((uint32_t)(mask >> 32)) << 32) | uniform((uint32_t)mask);
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
+    return r;
+}
+
+constexpr uint32_t kStepGroup = 8;     // blocks loaded ahead by the stepped pass
+
+// Statistics of stepped configs from the stepped replay's pass 1: one wave per
+// chunk.  The level before every step follows from the chunk's entering level
+// and the blocks' step masks (moves up by up_step, down by down_step, set to
+// level_max, each clamped to the range); the interval of step i runs at the
+// level before step i.  Lane l keeps the sums of level l.
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
-    uint32_t chunk, const uint8_t* __restrict__ levels,
+    uint32_t chunk, const uint32_t* __restrict__ entering,
+    const uint64_t* __restrict__ masks, uint64_t n_blocks,
     const magus_proxy_model* __restrict__ model, magus_proxy_stats* __restrict__ stats)
 {
     __shared__ uint32_t s_cap[MAGUS_PROXY_LEVELS];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x < MAGUS_PROXY_LEVELS) s_cap[threadIdx.x] = model->cap_mbps[threadIdx.x];
     __syncthreads();
-    if (chunk_base[n_traces + 1] != 0) return;            // the replay rejected the batch
+    if (chunk_base[n_traces + 1] != 0) return;            // the plan rejected the batch
     const uint32_t g = blockIdx.x * kStatsWaves + uniform(wv);
     if (g >= chunk_base[n_traces]) return;
 
@@ -107,72 +133,165 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stats_kernel(
     const uint64_t tbase = offsets[t];
     const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
     const uint32_t s = (g - chunk_base[t]) * chunk;
-    const uint32_t e = min(s + chunk, n);
+    const uint32_t len = min(s + chunk, n) - s;
     const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
-    const uint32_t lmin = c.lmin, lmax = c.lmax;
-    const uint32_t cap_lo = s_cap[lmin], cap_hi = s_cap[lmax];
-    const uint32_t* x_t = samples + tbase;
-    const uint8_t* lv_t = levels + tbase;
+    const int32_t lmin = c.lmin, lmax = c.lmax;
+    const int32_t up = c.up ? (int32_t)c.up : 64, down = c.down ? (int32_t)c.down : 64;
+    const uint32_t cap_hi = s_cap[lmax], cap_lo = s_cap[lmin];
+    const uint64_t mb = first_block(tbase, s, t);
+    const uint64_t* m_hs = masks + mb;
+    const uint64_t* m_up = masks + n_blocks + mb;
+    const uint64_t* m_dn = masks + 2 * n_blocks + mb;
+    const uint32_t nblk = (len + 63) >> 6;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(samples + tbase + s), (short)0, (int)(len * 4u), 0x00020000);
 
-    uint64_t n_lo = 0, n_hi = 0, x_lo = 0, x_hi = 0, ex_max = 0, ex_min = 0;
-    uint64_t bin_n = 0, bin_x = 0;      // lane l: level l strictly inside the bounds
-    for (uint32_t base = s; base < e; base += 64 * kUnroll) {
-        uint32_t xs[kUnroll], ls[kUnroll];
-#pragma unroll
-        for (uint32_t k = 0; k < kUnroll; ++k) {
-            const uint32_t i = base + k * 64 + lane;
-            xs[k] = i < e ? x_t[i] : 0u;
-            ls[k] = i < e ? (i == 0 ? c.linit : (uint32_t)(lv_t[i - 1] & 31u)) : lmin;
+    int32_t cur = (int32_t)uniform(entering[g]);         // level before the next step
+    // a run: consecutive blocks at one level (run_lv), summed per lane
+    uint32_t run_lv = (uint32_t)cur, cap_run = s_cap[cur], run_n = 0;
+    uint64_t ex_max = 0, ex_min = 0, run_x = 0;          // per lane
+    uint64_t bin_n = 0, bin_x = 0;                       // lane l: level l
+    auto credit = [&](uint32_t level, uint64_t steps, uint64_t sum) {
+        if (lane == level) {
+            bin_n += steps;
+            bin_x += sum;
         }
-#pragma unroll
-        for (uint32_t k = 0; k < kUnroll; ++k) {
-            const uint32_t i = base + k * 64 + lane;
-            const bool live = i < e;
-            const uint32_t x = xs[k], l = ls[k];
-            const uint32_t o_hi = over(x, cap_hi), o_lo = over(x, cap_lo);
-            const bool at_lo = live && l == lmin, at_hi = live && l == lmax;
-            n_lo += (uint32_t)__builtin_popcountll(__ballot(at_lo));    // wave-uniform
-            n_hi += (uint32_t)__builtin_popcountll(__ballot(at_hi));
-            x_lo += at_lo ? o_lo : 0u;
-            x_hi += at_hi ? o_hi : 0u;
-            ex_max += o_hi;                   // 0 for lanes past the end (x = 0)
-            ex_min += o_lo;
-            // levels strictly between the bounds (stepped actuation, or an
-            // initial level inside the range): one pass per distinct level
-            uint64_t other = __ballot(live && !at_lo && !at_hi);
-            while (other) {
-                const uint32_t l0 =
-                    (uint32_t)__builtin_amdgcn_readlane((int)l, (int)__builtin_ctzll(other));
-                const bool mine = live && l == l0;
-                const uint64_t m = __ballot(mine);
-                const uint64_t sx = wave_sum_u32(mine ? over(x, s_cap[l0]) : 0u);
-                if (lane == l0) {
-                    bin_n += (uint64_t)__builtin_popcountll(m);
-                    bin_x += sx;
-                }
-                other &= ~m;
+    };
+    // the step masks of a span of 2 * kStepGroup blocks: lane j holds block
+    // b0 + j's (vector loads, issued a span ahead)
+    struct SpanMasks {
+        uint64_t hs, up, dn;
+    };
+    auto load_masks = [&](uint32_t b0) -> SpanMasks {
+        const uint32_t b = b0 + lane;
+        SpanMasks m{0, 0, 0};
+        if (lane < 2 * kStepGroup && b < nblk) {
+            m.hs = m_hs[b];
+            m.up = m_up[b];
+            m.dn = m_dn[b];
+        }
+        return m;
+    };
+    auto lane_u64 = [](uint64_t v, uint32_t k) -> uint64_t {
+        return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), (int)k) << 32) |
+               (uint32_t)__builtin_amdgcn_readlane((int)v, (int)k);
+    };
+    // adds a block whose every step runs at `level` to the run
+    auto join_run = [&](uint32_t level, uint32_t x, uint32_t nv) {
+        if (level != run_lv) {
+            if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
+            run_n = 0;
+            run_x = 0;
+            run_lv = level;
+            cap_run = s_cap[level];
+        }
+        run_x += over(x, cap_run);
+        run_n += nv;
+    };
+    // block b of the chunk, lane k of the span's masks; `moving`: the span's
+    // blocks that hold a move
+    auto block = [&](uint32_t b, uint32_t k, uint32_t x, const SpanMasks& sm,
+                     uint64_t moving) {
+        const uint32_t nv = min(64u, len - b * 64);      // steps in the block
+        ex_max += over(x, cap_hi);                       // lanes past the end read 0
+        ex_min += over(x, cap_lo);
+        const int32_t entry = cur;
+        if (((moving >> k) & 1ull) == 0) {
+            // no move: every step runs at `cur`
+            join_run((uint32_t)entry, x, nv);
+            return;
+        }
+        const uint64_t hs = lane_u64(sm.hs, k), mu = lane_u64(sm.up, k),
+                       md = lane_u64(sm.dn, k);
+        uint64_t moves = hs | mu | md;
+        // the level before each step of the block: a move at step p that
+        // changes the level sets it for the steps after p (bit p of `chg`)
+        uint32_t lv = (uint32_t)cur;
+        uint64_t chg = 0;
+        while (moves) {
+            const uint32_t p = (uint32_t)__builtin_ctzll(moves);
+            moves &= moves - 1;
+            const int32_t d = ((hs >> p) & 1ull) ? 64 : (((mu >> p) & 1ull) ? up : -down);
+            const int32_t nl = min(max(cur + d, lmin), lmax);
+            if (nl != cur) {
+                const uint64_t after = p < 63 ? ~0ull << (p + 1) : 0ull;
+                lv = lane_pick(after, (uint32_t)nl, lv);
+                chg |= 1ull << p;
+                cur = nl;
             }
         }
+        // segments of steps at one level end at the changes before the
+        // block's last step, and at its last step
+        const uint64_t last = 1ull << (nv - 1);
+        const uint64_t ends = (chg & (last - 1)) | last;
+        if (ends == last) {                              // one level: `entry`
+            join_run((uint32_t)entry, x, nv);
+            return;
+        }
+        // the excess of each step at its own level (0 past the end), scanned
+        // in 16-bit halves; a segment's sum is the difference of the scans
+        // at its two ends
+        const uint32_t e = over(x, s_cap[lv]);
+        const uint32_t p_lo = dpp_scan(e & 0xFFFFu), p_hi = dpp_scan(e >> 16);
+        uint32_t prev_lo = 0, prev_hi = 0, prev_end = 0;   // prev_end: first step
+        uint64_t rest = ends;
+        while (rest) {
+            const uint32_t p = (uint32_t)__builtin_ctzll(rest);
+            rest &= rest - 1;
+            const uint32_t level = (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)p);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)p_lo, (int)p);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)p_hi, (int)p);
+            credit(level, p + 1 - prev_end, ((uint64_t)(hi - prev_hi) << 16) + (lo - prev_lo));
+            prev_lo = lo;
+            prev_hi = hi;
+            prev_end = p + 1;
+        }
+    };
+    // groups of kStepGroup blocks; the next group's samples load while one
+    // group is summed (loads past the chunk's end read 0), the next span's
+    // masks while a span is summed
+    auto load = [&](uint32_t b) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((b * 64 + lane) * 4), 0, 0);
+    };
+    uint32_t xa[kStepGroup], xb[kStepGroup];
+    SpanMasks sm = load_masks(0);
+#pragma unroll
+    for (uint32_t k = 0; k < kStepGroup; ++k) xa[k] = load(k);
+    for (uint32_t b0 = 0; b0 < nblk; b0 += 2 * kStepGroup) {
+#pragma unroll
+        for (uint32_t k = 0; k < kStepGroup; ++k) xb[k] = load(b0 + kStepGroup + k);
+        const SpanMasks next = load_masks(b0 + 2 * kStepGroup);
+        const uint64_t moving = __ballot((sm.hs | sm.up | sm.dn) != 0);
+#pragma unroll
+        for (uint32_t k = 0; k < kStepGroup; ++k)
+            if (b0 + k < nblk) block(b0 + k, k, xa[k], sm, moving);
+        if (b0 + kStepGroup >= nblk) break;
+#pragma unroll
+        for (uint32_t k = 0; k < kStepGroup; ++k) xa[k] = load(b0 + 2 * kStepGroup + k);
+#pragma unroll
+        for (uint32_t k = 0; k < kStepGroup; ++k)
+            if (b0 + kStepGroup + k < nblk)
+                block(b0 + kStepGroup + k, kStepGroup + k, xb[k], sm, moving);
+        sm = next;
     }
-    x_lo = wave_sum(x_lo);
-    x_hi = wave_sum(x_hi);
-    ex_max = wave_sum(ex_max);
-    ex_min = wave_sum(ex_min);
-    magus_proxy_stats* st = stats + t;
+    if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
+    ex_max = dpp_wave_sum64(ex_max);
+    ex_min = dpp_wave_sum64(ex_min);
+    unsigned long long* st = reinterpret_cast<unsigned long long*>(stats + t);
     if (lane == 0) {
-        unsigned long long* p = reinterpret_cast<unsigned long long*>(st);
-        if (ex_max) atomicAdd(p + 0, (unsigned long long)ex_max);
-        if (ex_min) atomicAdd(p + 1, (unsigned long long)ex_min);
-        if (n_lo) atomicAdd(p + 2 + lmin, (unsigned long long)n_lo);
-        if (n_hi) atomicAdd(p + 2 + lmax, (unsigned long long)n_hi);
-        if (x_lo) atomicAdd(p + 2 + MAGUS_PROXY_LEVELS + lmin, (unsigned long long)x_lo);
-        if (x_hi) atomicAdd(p + 2 + MAGUS_PROXY_LEVELS + lmax, (unsigned long long)x_hi);
+        if (ex_max) atomicAdd(st + 0, (unsigned long long)ex_max);
+        if (ex_min) atomicAdd(st + 1, (unsigned long long)ex_min);
     }
     if (lane < MAGUS_PROXY_LEVELS) {
-        unsigned long long* p = reinterpret_cast<unsigned long long*>(st);
-        if (bin_n) atomicAdd(p + 2 + lane, (unsigned long long)bin_n);
-        if (bin_x) atomicAdd(p + 2 + MAGUS_PROXY_LEVELS + lane, (unsigned long long)bin_x);
+        if (bin_n) atomicAdd(st + 2 + lane, (unsigned long long)bin_n);
+        if (bin_x) atomicAdd(st + 2 + MAGUS_PROXY_LEVELS + lane, (unsigned long long)bin_x);
     }
+}
+
+__global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // Stretched length of `steps` intervals of which the samples exceed `cap` by
@@ -250,14 +369,6 @@ __device__ __forceinline__ uint64_t carries_into(uint64_t a, uint64_t b, uint32_
         : "scc");
     cout = k;
     return ((((uint64_t)s1 << 32) | s0) ^ a) ^ b;
-}
-
-// a in the lanes whose bit of the wave-uniform mask is set, else b
-__device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_t b) {
-    const uint64_t m = ((uint64_t)uniform((uint32_t)(mask >> 32)) << 32) | uniform((uint32_t)mask);
-    uint32_t r;
-    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
-    return r;
 }
 
 // v in the lanes whose bit of the wave-uniform mask is set, else 0
@@ -470,11 +581,13 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
 
 }  // namespace
 
-hipError_t launch_proxy(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
-                        const uint32_t* chunk_base, uint32_t max_chunks, const DevCfg* cfgs,
-                        const uint32_t* cfg_of_trace, uint32_t chunk, const uint8_t* levels,
-                        const magus_proxy_model* model, magus_proxy_stats* stats,
-                        magus_proxy_metrics* metrics, hipStream_t stream)
+hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
+                                const uint64_t* offsets, uint32_t n_traces,
+                                const uint32_t* chunk_base, uint32_t max_chunks,
+                                const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
+                                const uint32_t* entering, const uint64_t* masks,
+                                const magus_proxy_model* model, magus_proxy_stats* stats,
+                                magus_proxy_metrics* metrics, hipStream_t stream)
 {
     if (n_traces == 0) return hipSuccess;
     const uint64_t words = (uint64_t)n_traces * (sizeof(magus_proxy_stats) / 8);
@@ -482,9 +595,9 @@ hipError_t launch_proxy(const uint32_t* samples, const uint64_t* offsets, uint32
         reinterpret_cast<uint64_t*>(stats), words);
     const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
     if (blocks)
-        proxy_stats_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
-            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, levels, model,
-            stats);
+        proxy_stepped_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
+            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, masks,
+            stepped_mask_blocks(n_samples, n_traces), model, stats);
     if (metrics)
         proxy_metrics_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);

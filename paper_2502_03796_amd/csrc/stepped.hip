@@ -215,13 +215,6 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// Index of the first block of a chunk in the mask arrays: blocks of one trace
-// start 64 steps apart, so (absolute first step) / 64 + trace is one-to-one
-// over all blocks of a batch and stays below n_samples / 64 + n_traces.
-__device__ __forceinline__ uint64_t first_block(uint64_t tbase, uint32_t s, uint32_t t) {
-    return (tbase + s) / 64 + t;
-}
-
 // Pass 1: masks of every block, the map and the high steps of every chunk.
 template <bool kAnyBase>
 __global__ __launch_bounds__(kWaves * kWave) void stepped_mask_kernel(
@@ -469,6 +462,30 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_fold_kernel(
 
 }  // namespace
 
+hipError_t launch_stepped_prepare(const uint32_t* samples, uint64_t n_samples,
+                                  const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
+                                  uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
+                                  uint32_t* chunk_base, uint32_t max_chunks, ClampAdd* funcs,
+                                  uint32_t* entering, StepSum* sums, uint64_t* masks,
+                                  uint32_t* err, bool any_base, hipStream_t stream,
+                                  hipEvent_t ev0)
+{
+    if (n_traces == 0) return hipSuccess;
+    hipError_t e = launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk,
+                               max_chunks, chunk_base, err, stream);
+    if (e != hipSuccess) return e;
+    if ((e = record_timing_event(ev0, stream)) != hipSuccess) return e;
+    const uint32_t blocks = (max_chunks + kWaves - 1) / kWaves;
+    (any_base ? stepped_mask_kernel<true> : stepped_mask_kernel<false>)
+        <<<blocks, kWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base, cfgs,
+                                                cfg_of_trace, chunk,
+                                                stepped_mask_blocks(n_samples, n_traces), funcs,
+                                                sums, masks);
+    stepped_enter_kernel<<<(n_traces + kWaves - 1) / kWaves, kWaves * kWave, 0, stream>>>(
+        n_traces, chunk_base, cfgs, cfg_of_trace, funcs, entering);
+    return hipGetLastError();
+}
+
 hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  const uint64_t* offsets, uint32_t n_traces, const DevCfg* cfgs,
                                  uint32_t n_cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
@@ -479,18 +496,13 @@ hipError_t launch_replay_stepped(const uint32_t* samples, uint64_t n_samples,
                                  hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
-    hipError_t e = launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk,
-                               max_chunks, chunk_base, err, stream);
+    hipError_t e = launch_stepped_prepare(samples, n_samples, offsets, n_traces, cfgs, n_cfgs,
+                                          cfg_of_trace, chunk, chunk_base, max_chunks, funcs,
+                                          entering, sums, masks, err, any_base, stream, ev0);
     if (e != hipSuccess) return e;
     const uint32_t blocks = (max_chunks + kWaves - 1) / kWaves;
     const uint64_t n_blocks = stepped_mask_blocks(n_samples, n_traces);
-    if ((e = record_timing_event(ev0, stream)) != hipSuccess) return e;
-    (any_base ? stepped_mask_kernel<true> : stepped_mask_kernel<false>)
-        <<<blocks, kWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base, cfgs,
-                                                cfg_of_trace, chunk, n_blocks, funcs, sums, masks);
     const uint32_t trace_blocks = (n_traces + kWaves - 1) / kWaves;
-    stepped_enter_kernel<<<trace_blocks, kWaves * kWave, 0, stream>>>(
-        n_traces, chunk_base, cfgs, cfg_of_trace, funcs, entering);
     if (levels)
         (any_base ? stepped_levels_kernel<true> : stepped_levels_kernel<false>)
             <<<blocks, kWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base, cfgs,

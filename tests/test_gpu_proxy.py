@@ -18,7 +18,7 @@ import synth
 from synth import default_config, proxy_model
 from tests.gpu_util import to_dev
 from tests.test_gpu_replay import mixed_traces, LENGTHS
-from tests.test_gpu_stepped import stepped_configs
+from tests.test_gpu_stepped import dense_traces, stepped_configs
 
 pytestmark = pytest.mark.gpu
 
@@ -99,7 +99,7 @@ def test_mixed_traces_grid_configs(ctx, oracle_mod, chunk):
     check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
 
 
-@pytest.mark.parametrize("chunk", [64, 4096])
+@pytest.mark.parametrize("chunk", [64, 192, 4096, 0])
 def test_stepped_configs_and_inner_levels(ctx, oracle_mod, chunk):
     """Stepped actuation visits every rung; initial levels inside the range."""
     traces = mixed_traces(1300 + chunk, LENGTHS)
@@ -123,6 +123,33 @@ def test_stepped_configs_and_inner_levels(ctx, oracle_mod, chunk):
         ctx.set_chunk(0)
     check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
     assert (st.cpu().numpy() == st2.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("chunk", [64, 192, 4096, 65536])
+def test_stepped_dense_events(ctx, oracle_mod, chunk):
+    """Stepped configs on traces with a move at every step and long high runs:
+    levels change inside blocks (several per block), blocks whose moves are
+    all clamped, and chunks of one block up to many groups of blocks."""
+    traces = dense_traces(chunk + 3)
+    cfgs = stepped_configs(chunk + 7, 10) + [
+        default_config(window=2, hold=2, up_step=1, down_step=1),
+        default_config(window=2, hold=4, up_step=3, down_step=0, level_init=9),
+        default_config(up_step=0, down_step=2, level_min=2, level_max=29, level_init=20)]
+    cot = (np.arange(len(traces)) % len(cfgs)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    rng = np.random.default_rng(chunk + 5)
+    model = dict(n_levels=30, interval_us=int(rng.integers(1, 10**6)),
+                 cap_mbps=[int(v) for v in rng.integers(500, 6000, 32)],
+                 uncore_mw=[int(v) for v in rng.integers(0, 50000, 32)],
+                 core_mw=30000, gpu_mw=300000)
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, cfgs, model, c)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
 
 
 @pytest.mark.parametrize("chunk", [64, 128, 4096])
