@@ -113,7 +113,9 @@ constexpr uint32_t kStepGroup = 8;     // blocks loaded ahead by the stepped pas
 // and the blocks' step masks (moves up by up_step, down by down_step, set to
 // level_max, each clamped to the range); the interval of step i runs at the
 // level before step i.  Lane l keeps the sums of level l.
-__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
+// (eight waves per SIMD: the register budget that keeps the scalar unit fed)
+__global__ __launch_bounds__(kStatsWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+void proxy_stepped_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
@@ -147,14 +149,24 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
         (void*)(samples + tbase + s), (short)0, (int)(len * 4u), 0x00020000);
 
     int32_t cur = (int32_t)uniform(entering[g]);         // level before the next step
-    // a run: consecutive blocks at one level (run_lv), summed per lane
+    // the run: the steps since the level last changed, all at run_lv == cur
+    // (outside a block's walk); their excess is summed per lane
     uint32_t run_lv = (uint32_t)cur, cap_run = s_cap[cur], run_n = 0;
     uint64_t ex_max = 0, ex_min = 0, run_x = 0;          // per lane
     uint64_t bin_n = 0, bin_x = 0;                       // lane l: level l
-    auto credit = [&](uint32_t level, uint64_t steps, uint64_t sum) {
-        if (lane == level) {
-            bin_n += steps;
-            bin_x += sum;
+    auto credit = [&](uint32_t level, uint32_t steps, uint64_t sum) {
+        const bool mine = lane == level;
+        bin_n += mine ? steps : 0u;
+        bin_x += mine ? sum : 0ull;
+    };
+    // ends the run if the level changed and starts one at the new level
+    auto follow_level = [&]() {
+        if ((uint32_t)cur != run_lv) {
+            if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
+            run_n = 0;
+            run_x = 0;
+            run_lv = (uint32_t)cur;
+            cap_run = s_cap[cur];
         }
     };
     // the step masks of a span of 2 * kStepGroup blocks: lane j holds block
@@ -176,31 +188,9 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
         return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), (int)k) << 32) |
                (uint32_t)__builtin_amdgcn_readlane((int)v, (int)k);
     };
-    // adds a block whose every step runs at `level` to the run
-    auto join_run = [&](uint32_t level, uint32_t x, uint32_t nv) {
-        if (level != run_lv) {
-            if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
-            run_n = 0;
-            run_x = 0;
-            run_lv = level;
-            cap_run = s_cap[level];
-        }
-        run_x += over(x, cap_run);
-        run_n += nv;
-    };
-    // block b of the chunk, lane k of the span's masks; `moving`: the span's
-    // blocks that hold a move
-    auto block = [&](uint32_t b, uint32_t k, uint32_t x, const SpanMasks& sm,
-                     uint64_t moving) {
-        const uint32_t nv = min(64u, len - b * 64);      // steps in the block
-        ex_max += over(x, cap_hi);                       // lanes past the end read 0
-        ex_min += over(x, cap_lo);
-        const int32_t entry = cur;
-        if (((moving >> k) & 1ull) == 0) {
-            // no move: every step runs at `cur`
-            join_run((uint32_t)entry, x, nv);
-            return;
-        }
+    const int32_t neg_down = -down;
+    // a block of nv steps that holds a move (lane k of the span's masks)
+    auto moving_block = [&](uint32_t k, uint32_t x, const SpanMasks& sm, uint32_t nv) {
         const uint64_t hs = lane_u64(sm.hs, k), mu = lane_u64(sm.up, k),
                        md = lane_u64(sm.dn, k);
         uint64_t moves = hs | mu | md;
@@ -209,13 +199,22 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
         uint32_t lv = (uint32_t)cur;
         uint64_t chg = 0;
         while (moves) {
-            const uint32_t p = (uint32_t)__builtin_ctzll(moves);
-            moves &= moves - 1;
-            const int32_t d = ((hs >> p) & 1ull) ? 64 : (((mu >> p) & 1ull) ? up : -down);
+            // p: the next move; d: its rung move (up_step, -down_step, or 64
+            // for the set to level_max); the move leaves `moves`
+            uint32_t p;
+            int32_t d;
+            asm("s_ff1_i32_b64 %0, %2\n\t"
+                "s_bitcmp1_b64 %3, %0\n\t"
+                "s_cselect_b32 %1, %5, %6\n\t"
+                "s_bitcmp1_b64 %4, %0\n\t"
+                "s_cselect_b32 %1, 64, %1\n\t"
+                "s_bitset0_b64 %2, %0"
+                : "=&s"(p), "=&s"(d), "+s"(moves)
+                : "s"(mu), "s"(hs), "s"(up), "s"(neg_down)
+                : "scc");
             const int32_t nl = min(max(cur + d, lmin), lmax);
             if (nl != cur) {
-                const uint64_t after = p < 63 ? ~0ull << (p + 1) : 0ull;
-                lv = lane_pick(after, (uint32_t)nl, lv);
+                lv = lane_pick(~1ull << p, (uint32_t)nl, lv);
                 chg |= 1ull << p;
                 cur = nl;
             }
@@ -224,34 +223,80 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
         // block's last step, and at its last step
         const uint64_t last = 1ull << (nv - 1);
         const uint64_t ends = (chg & (last - 1)) | last;
-        if (ends == last) {                              // one level: `entry`
-            join_run((uint32_t)entry, x, nv);
-            return;
+        if (ends == last) {
+            // one level, the run's (a change at the last step only sets the
+            // level of the next block)
+            run_x += over(x, cap_run);
+            run_n += nv;
+        } else {
+            // the excess of each step at its own level (0 past the end),
+            // scanned in 16-bit halves; a segment's sum is the difference of
+            // the scans at its two ends
+            const uint32_t e = over(x, s_cap[lv]);
+            const uint32_t p_lo = dpp_scan(e & 0xFFFFu), p_hi = dpp_scan(e >> 16);
+            uint32_t prev_lo = 0, prev_hi = 0, prev_end = 0;   // prev_end: first step
+            uint64_t rest = ends;
+            while (rest) {
+                const uint32_t p = (uint32_t)__builtin_ctzll(rest);
+                rest &= rest - 1;
+                const uint32_t level = (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)p);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)p_lo, (int)p);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)p_hi, (int)p);
+                credit(level, p + 1 - prev_end,
+                       ((uint64_t)(hi - prev_hi) << 16) + (lo - prev_lo));
+                prev_lo = lo;
+                prev_hi = hi;
+                prev_end = p + 1;
+            }
         }
-        // the excess of each step at its own level (0 past the end), scanned
-        // in 16-bit halves; a segment's sum is the difference of the scans
-        // at its two ends
-        const uint32_t e = over(x, s_cap[lv]);
-        const uint32_t p_lo = dpp_scan(e & 0xFFFFu), p_hi = dpp_scan(e >> 16);
-        uint32_t prev_lo = 0, prev_hi = 0, prev_end = 0;   // prev_end: first step
-        uint64_t rest = ends;
-        while (rest) {
-            const uint32_t p = (uint32_t)__builtin_ctzll(rest);
-            rest &= rest - 1;
-            const uint32_t level = (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)p);
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)p_lo, (int)p);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)p_hi, (int)p);
-            credit(level, p + 1 - prev_end, ((uint64_t)(hi - prev_hi) << 16) + (lo - prev_lo));
-            prev_lo = lo;
-            prev_hi = hi;
-            prev_end = p + 1;
-        }
+        follow_level();
     };
     // groups of kStepGroup blocks; the next group's samples load while one
     // group is summed (loads past the chunk's end read 0), the next span's
     // masks while a span is summed
     auto load = [&](uint32_t b) -> uint32_t {
         return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((b * 64 + lane) * 4), 0, 0);
+    };
+    // a group of kStepGroup blocks starting at block b, lanes kb.. of the
+    // span's masks; a block without a move adds to the run
+    const uint32_t full = len >> 6;                      // blocks of 64 steps
+    auto group = [&](uint32_t b, uint32_t kb, const uint32_t (&x)[kStepGroup],
+                     const SpanMasks& sm, uint64_t moving) {
+        const uint32_t gm = (uint32_t)(moving >> kb) & ((1u << kStepGroup) - 1);
+#pragma unroll
+        for (uint32_t k = 0; k < kStepGroup; ++k) {
+            ex_max += over(x[k], cap_hi);                // lanes past the end read 0
+            ex_min += over(x[k], cap_lo);
+        }
+        if (b + kStepGroup <= full) {                    // whole blocks only
+            if (gm == 0) {
+#pragma unroll
+                for (uint32_t k = 0; k < kStepGroup; ++k) run_x += over(x[k], cap_run);
+                run_n += kStepGroup * 64;
+                return;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kStepGroup; ++k) {
+                if ((gm >> k) & 1u) {
+                    moving_block(kb + k, x[k], sm, 64);
+                } else {
+                    run_x += over(x[k], cap_run);
+                    run_n += 64;
+                }
+            }
+            return;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kStepGroup; ++k) {
+            if (b + k >= nblk) break;
+            const uint32_t nv = min(64u, len - (b + k) * 64);
+            if ((gm >> k) & 1u) {
+                moving_block(kb + k, x[k], sm, nv);
+            } else {
+                run_x += over(x[k], cap_run);
+                run_n += nv;
+            }
+        }
     };
     uint32_t xa[kStepGroup], xb[kStepGroup];
     SpanMasks sm = load_masks(0);
@@ -262,16 +307,11 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
         for (uint32_t k = 0; k < kStepGroup; ++k) xb[k] = load(b0 + kStepGroup + k);
         const SpanMasks next = load_masks(b0 + 2 * kStepGroup);
         const uint64_t moving = __ballot((sm.hs | sm.up | sm.dn) != 0);
-#pragma unroll
-        for (uint32_t k = 0; k < kStepGroup; ++k)
-            if (b0 + k < nblk) block(b0 + k, k, xa[k], sm, moving);
+        group(b0, 0, xa, sm, moving);
         if (b0 + kStepGroup >= nblk) break;
 #pragma unroll
         for (uint32_t k = 0; k < kStepGroup; ++k) xa[k] = load(b0 + 2 * kStepGroup + k);
-#pragma unroll
-        for (uint32_t k = 0; k < kStepGroup; ++k)
-            if (b0 + kStepGroup + k < nblk)
-                block(b0 + kStepGroup + k, kStepGroup + k, xb[k], sm, moving);
+        group(b0 + kStepGroup, kStepGroup, xb, sm, moving);
         sm = next;
     }
     if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
