@@ -168,8 +168,8 @@ def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, p
     pdt = (time.perf_counter() - t0) / reps
     pctx.check()
     pst_np, pme_np = pst.cpu().numpy(), pme.cpu().numpy()
-    # the same model with stepped actuation (up 2 rungs, down 1): the replay
-    # writes every step's decision byte, then a statistics pass
+    # the same model with stepped actuation (up 2 rungs, down 1): the stepped
+    # replay's mask pass, then a statistics pass over samples and step masks
     sarr = magus.config_array([synth.default_config(up_step=2, down_step=1)])
     pctx.proxy(s, o, sarr, model)
     torch.cuda.synchronize()

@@ -305,13 +305,17 @@ typedef struct magus_proxy_metrics {         /* [policy]: 0 MAGUS, 1 max, 2 min 
 int magus_proxy_model_check(const magus_proxy_model* model);
 
 /*
- * Runs the replay of magus_replay (same sample, offset and config rules; the
- * per-step levels go to a context-owned buffer of n_samples bytes) and then
- * the proxy for every trace.
+ * Evaluates the proxy for every trace under the controller of magus_replay
+ * (same sample, offset and config rules), without materialising per-step
+ * levels: configs that jump to the bound take one pass over the samples;
+ * stepped configs take the stepped replay's first pass (context-owned step
+ * masks, 28 B per 64 steps) and one statistics pass over samples and masks.
  *   h_model    the proxy model (host memory, read before return); an invalid
  *              model, or a config with level_max >= n_levels, is MAGUS_EINVAL.
  *   d_stats    n_traces magus_proxy_stats (written).
  *   d_metrics  NULL or n_traces magus_proxy_metrics (written).
+ * A batch that breaks the data rules (found on the device) leaves d_stats
+ * zero and d_metrics unwritten; magus_ctx_check reports it.
  */
 int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 const uint64_t* d_offsets, uint32_t n_traces,
