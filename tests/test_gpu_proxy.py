@@ -216,3 +216,21 @@ def test_bulk_workload_full_size_sampled(ctx, oracle_mod):
     # every interval is counted once
     steps = st.cpu().numpy()[:, 2:2 + magus.PROXY_LEVELS].sum(axis=1)
     assert (steps == np.diff(offsets.astype(np.int64))).all()
+
+
+def test_bulk_workload_full_size_stepped_sampled(ctx, oracle_mod):
+    """The stepped configuration the bench times (up 2 rungs, down 1) on the
+    4,096 x 100,000 bulk traces at full size; sampled traces against the
+    oracle, and every interval counted once in every trace."""
+    samples, offsets = synth.workload_bulk(4096, 100000)
+    s, o, _ = to_dev(samples, offsets)
+    model = proxy_model()
+    cfg = default_config(up_step=2, down_step=1)
+    st, me = ctx.proxy(s, o, [cfg], model)
+    ctx.check()
+    rng = np.random.default_rng(5)
+    pick = sorted(set(rng.integers(0, 4096, 6).tolist()) | {0, 4095})
+    check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me, traces=pick)
+    steps = st.cpu().numpy()[:, 2:2 + magus.PROXY_LEVELS].sum(axis=1)
+    assert (steps == np.diff(offsets.astype(np.int64))).all()
+
