@@ -52,16 +52,6 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
-        v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
-}
-
 __device__ __forceinline__ uint32_t over(uint32_t x, uint32_t cap) { return x > cap ? x - cap : 0u; }
 
 // Inclusive wave scan with DPP: row shifts build the scan within each row of
@@ -390,7 +380,6 @@ __device__ __forceinline__ uint32_t sat_sub(uint32_t x, uint32_t cap) {
     return __builtin_elementwise_sub_sat(x, cap);
 }
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) { return wave_sum(v); }
 
 // Carries into the 64 bit positions of a + b + cin (cin 0 or 1) and the carry
 // out, in scalar registers (a, b wave-uniform).
@@ -514,13 +503,13 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
             a_pre2 += lane_sel(in, sat_sub(x, c_in));
         }
     }
-    a_pre0 = wave_sum64(a_pre0);
-    a_pre1 = wave_sum64(a_pre1);
-    a_pre2 = wave_sum64(a_pre2);
-    a_lo = wave_sum64(a_lo);
-    a_hi = wave_sum64(a_hi);
-    a_max = wave_sum64(a_max);
-    a_min = wave_sum64(a_min);
+    a_pre0 = dpp_wave_sum64(a_pre0);
+    a_pre1 = dpp_wave_sum64(a_pre1);
+    a_pre2 = dpp_wave_sum64(a_pre2);
+    a_lo = dpp_wave_sum64(a_lo);
+    a_hi = dpp_wave_sum64(a_hi);
+    a_max = dpp_wave_sum64(a_max);
+    a_min = dpp_wave_sum64(a_min);
     if (lane == 0) {
         ProxySum r;
         r.len = v.e - v.s;
@@ -589,14 +578,14 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
         }
         if (E) level = (uint32_t)__shfl((int)end_level, 63 - __builtin_clzll(E), 64);
     }
-    n0 = wave_sum64(n0);
-    n1 = wave_sum64(n1);
-    n2 = wave_sum64(n2);
-    x0 = wave_sum64(x0);
-    x1 = wave_sum64(x1);
-    x2 = wave_sum64(x2);
-    emax = wave_sum64(emax);
-    emin = wave_sum64(emin);
+    n0 = dpp_wave_sum64(n0);
+    n1 = dpp_wave_sum64(n1);
+    n2 = dpp_wave_sum64(n2);
+    x0 = dpp_wave_sum64(x0);
+    x1 = dpp_wave_sum64(x1);
+    x2 = dpp_wave_sum64(x2);
+    emax = dpp_wave_sum64(emax);
+    emin = dpp_wave_sum64(emin);
     // every word of the trace's stats: 0 excess_max, 1 excess_min,
     // 2 + l steps[l], 2 + 32 + l excess[l]
     uint64_t* out = reinterpret_cast<uint64_t*>(stats + t);
