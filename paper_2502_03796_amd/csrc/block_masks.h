@@ -11,6 +11,30 @@ namespace magus {
 
 __device__ __forceinline__ uint64_t lane_ballot(bool p) { return __ballot(p); }
 
+// v plus the value of the lane the DPP control names, in 64 bits
+template <int kCtrl, int kRowMask, bool kBound>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl,
+                                                              kRowMask, 0xf, kBound);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32),
+                                                              kCtrl, kRowMask, 0xf, kBound);
+    return v + (((uint64_t)hi << 32) | lo);
+}
+
+// Wave sum of 64-bit values (every lane active): row shifts of 1, 2, 4 and 8
+// sum each row of 16 lanes, row broadcasts of lanes 15 and 31 carry the rows
+// before, and lane 63 holds the total (no LDS traffic).
+__device__ __forceinline__ uint64_t dpp_wave_sum64(uint64_t v) {
+    v = dpp_add64<0x111, 0xf, true>(v);
+    v = dpp_add64<0x112, 0xf, true>(v);
+    v = dpp_add64<0x114, 0xf, true>(v);
+    v = dpp_add64<0x118, 0xf, true>(v);
+    v = dpp_add64<0x142, 0xa, false>(v);
+    v = dpp_add64<0x143, 0xc, false>(v);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+}
+
 __device__ __forceinline__ uint64_t mask_below(uint32_t n) {   // n in [0, 64]
     return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
 }

@@ -66,28 +66,6 @@ __device__ __forceinline__ uint32_t dpp_scan(uint32_t v) {
     return v;
 }
 
-// v plus the value of the lane the DPP control names, in 64 bits
-template <int kCtrl, int kRowMask, bool kBound>
-__device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl,
-                                                              kRowMask, 0xf, kBound);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32),
-                                                              kCtrl, kRowMask, 0xf, kBound);
-    return v + (((uint64_t)hi << 32) | lo);
-}
-
-// Wave sum of 64-bit values with the steps of dpp_scan (no LDS traffic).
-__device__ __forceinline__ uint64_t dpp_wave_sum64(uint64_t v) {
-    v = dpp_add64<0x111, 0xf, true>(v);
-    v = dpp_add64<0x112, 0xf, true>(v);
-    v = dpp_add64<0x114, 0xf, true>(v);
-    v = dpp_add64<0x118, 0xf, true>(v);
-    v = dpp_add64<0x142, 0xa, false>(v);
-    v = dpp_add64<0x143, 0xc, false>(v);
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
-}
-
 // a in the lanes whose bit of the wave-uniform mask is set, else b
 __device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_t b) {
     const uint64_t m = ((uint64_t)uniform((uint32_t)(mask >> 32)) << 32) | uniform((uint32_t)mask);

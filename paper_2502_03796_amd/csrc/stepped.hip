@@ -205,15 +205,7 @@ __device__ __forceinline__ ClampAdd unpack_map(uint32_t w) {
     return ClampAdd{(int32_t)(w & 0xFFu) - 64, (int32_t)((w >> 8) & 0xFFu), (int32_t)(w >> 16)};
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, d, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
-        v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
-}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) { return dpp_wave_sum64(v); }
 
 // Pass 1: masks of every block, the map and the high steps of every chunk.
 template <bool kAnyBase>
@@ -330,12 +322,8 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_walk_kernel(
         block_walk(sm, mv, before, steps, lsum, trans);
         x = __builtin_amdgcn_readlane(after, 63);
     }
-    uint64_t ls = lsum;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        ls += __shfl_xor(ls, d, 64);
-        trans += __shfl_xor(trans, d, 64);
-    }
+    const uint64_t ls = dpp_wave_sum64(lsum);
+    trans = (uint32_t)dpp_wave_sum64(trans);
     if (lane == 0) {
         sums[g].level_sum = ls;
         sums[g].transitions = trans;
@@ -419,11 +407,8 @@ __global__ __launch_bounds__(kWaves * kWave) void stepped_levels_kernel(
         const uint32_t last = min(64u, v.e - tb) - 1;
         x = __builtin_amdgcn_readlane(lv, (int)last);
     });
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        lsum += __shfl_xor(lsum, d, 64);
-        trans += __shfl_xor(trans, d, 64);
-    }
+    lsum = dpp_wave_sum64(lsum);
+    trans = (uint32_t)dpp_wave_sum64(trans);
     if (lane == 0) {
         StepSum r;
         r.level_sum = lsum;
