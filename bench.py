@@ -216,6 +216,58 @@ def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, p
 
 # Serving: 65,536 simulated nodes through the continuous-batching loop, in
 # real time (decision latency) and flat out (throughput).
+def bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks):
+    """The uneven batch: 20,000 bursty traces of log-normal lengths, a grid
+    config per trace, autotuned chunk length, one hipGraph launch per call."""
+    log("uneven workload: 20,000 traces, autotuned, hipGraph ...")
+    t0 = time.time()
+    usmp, uoff, ucot = synth.workload_uneven()
+    log(f"  {len(usmp)} samples generated in {time.time() - t0:.1f} s")
+    us = torch.from_numpy(usmp.view(np.int32)).to(dev)
+    uo = torch.from_numpy(uoff.view(np.int64)).to(dev)
+    uc = torch.from_numpy(ucot.view(np.int32)).to(dev)
+    uctx = magus.Context(0)
+    ures = torch.empty((len(uoff) - 1, 4), dtype=torch.int64, device=dev)
+    chosen = uctx.autotune_replay(us, uo, grid_arr, uc, reps=3, results=ures)
+    uctx.set_graphs(True)
+    for _ in range(3):
+        uctx.replay(us, uo, grid_arr, uc, results=ures)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        uctx.replay(us, uo, grid_arr, uc, results=ures)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    uctx.check()
+    ugot = ures.cpu().numpy().view(np.uint64)
+    upick = {t: (usmp[int(uoff[t]):int(uoff[t + 1])].copy(), grid[int(ucot[t])])
+             for t in (0, int(np.argmax(np.diff(uoff.astype(np.int64)))), len(uoff) - 2)}
+
+    def check_uneven(oracle):
+        for t, (x, c) in upick.items():
+            r, _ = oracle.replay_trace(x, c, want_bytes=False)
+            if list(ugot[t]) != [r["score"], r["level_sum"], r["transitions"],
+                                 r["ticks_high"]]:
+                raise SystemExit(f"uneven parity failure on trace {t}")
+        extra["uneven"]["parity"] = f"ok: {len(upick)} sampled traces equal the oracle"
+    checks.append(check_uneven)
+    ideal_ms = 4.0 * len(usmp) / (HBM_PEAK_GBS * 1e9) * 1e3
+    extra["uneven"] = {
+        "workload": "20,000 bursty traces, log-normal lengths 1,000..1,000,000, "
+                    "a grid config per trace, one launch (hipGraph)",
+        "samples": int(len(usmp)), "ms_per_call": dt * 1e3,
+        "samples_per_s": len(usmp) / dt, "hbm_frac": ideal_ms / (dt * 1e3),
+        "makespan_vs_ideal": dt * 1e3 / ideal_ms, "parity": "not checked (--no-cpu)",
+        "autotuned": {"chunk_steps": chosen["chunk_steps"],
+                      "persistent_workgroups": chosen["persistent_blocks"],
+                      "default_ms": chosen["default_ms"], "best_ms": chosen["best_ms"]}}
+    log(f"  uneven {len(usmp) / dt:.3e} samples/s ({dt * 1e3:.3f} ms, "
+        f"{ideal_ms / (dt * 1e3):.2%} of HBM), chosen {chosen}")
+    uctx.close()
+    del us, uo, uc, usmp
+
+
 def bench_serve(magus, synth, np, ctx, grid, grid_arr, args, extra, checks):
     log("serving: 65,536 nodes, continuous batching in real time ...")
     t0 = time.time()
@@ -273,7 +325,7 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only run the configuration sweep and print its figures")
-    ap.add_argument("--only", choices=["stepped", "proxy", "serve"],
+    ap.add_argument("--only", choices=["stepped", "proxy", "serve", "uneven"],
                     help="only run this report on the bulk workload (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise copy kernel over as many bytes as the "
@@ -327,6 +379,9 @@ def main():
         if args.only == "serve":
             grid = synth.sweep_grid()
             bench_serve(magus, synth, np, ctx, grid, magus.config_array(grid), args, extra, [])
+        elif args.only == "uneven":
+            grid = synth.sweep_grid()
+            bench_uneven(magus, synth, np, torch, dev, grid, magus.config_array(grid), extra, [])
         else:
             fn = bench_stepped if args.only == "stepped" else bench_proxy
             fn(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, [0], args, dev,
@@ -469,53 +524,7 @@ def main():
         extra["sweep"], grid_arr = bench_sweep(magus, synth, ctx, dev)
         grid = synth.sweep_grid()
 
-        log("uneven workload: 20,000 traces, autotuned, hipGraph ...")
-        t0 = time.time()
-        usmp, uoff, ucot = synth.workload_uneven()
-        log(f"  {len(usmp)} samples generated in {time.time() - t0:.1f} s")
-        us = torch.from_numpy(usmp.view(np.int32)).to(dev)
-        uo = torch.from_numpy(uoff.view(np.int64)).to(dev)
-        uc = torch.from_numpy(ucot.view(np.int32)).to(dev)
-        uctx = magus.Context(0)
-        ures = torch.empty((len(uoff) - 1, 4), dtype=torch.int64, device=dev)
-        chosen = uctx.autotune_replay(us, uo, grid_arr, uc, reps=3, results=ures)
-        uctx.set_graphs(True)
-        for _ in range(3):
-            uctx.replay(us, uo, grid_arr, uc, results=ures)
-        torch.cuda.synchronize()
-        reps = 10
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            uctx.replay(us, uo, grid_arr, uc, results=ures)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        uctx.check()
-        ugot = ures.cpu().numpy().view(np.uint64)
-        upick = {t: (usmp[int(uoff[t]):int(uoff[t + 1])].copy(), grid[int(ucot[t])])
-                 for t in (0, int(np.argmax(np.diff(uoff.astype(np.int64)))), len(uoff) - 2)}
-
-        def check_uneven(oracle):
-            for t, (x, c) in upick.items():
-                r, _ = oracle.replay_trace(x, c, want_bytes=False)
-                if list(ugot[t]) != [r["score"], r["level_sum"], r["transitions"],
-                                     r["ticks_high"]]:
-                    raise SystemExit(f"uneven parity failure on trace {t}")
-            extra["uneven"]["parity"] = f"ok: {len(upick)} sampled traces equal the oracle"
-        checks.append(check_uneven)
-        ideal_ms = 4.0 * len(usmp) / (HBM_PEAK_GBS * 1e9) * 1e3
-        extra["uneven"] = {
-            "workload": "20,000 bursty traces, log-normal lengths 1,000..1,000,000, "
-                        "a grid config per trace, one launch (hipGraph)",
-            "samples": int(len(usmp)), "ms_per_call": dt * 1e3,
-            "samples_per_s": len(usmp) / dt, "hbm_frac": ideal_ms / (dt * 1e3),
-            "makespan_vs_ideal": dt * 1e3 / ideal_ms, "parity": "not checked (--no-cpu)",
-            "autotuned": {"chunk_steps": chosen["chunk_steps"],
-                          "persistent_workgroups": chosen["persistent_blocks"],
-                          "default_ms": chosen["default_ms"], "best_ms": chosen["best_ms"]}}
-        log(f"  uneven {len(usmp) / dt:.3e} samples/s ({dt * 1e3:.3f} ms, "
-            f"{ideal_ms / (dt * 1e3):.2%} of HBM), chosen {chosen}")
-        uctx.close()
-        del us, uo, uc, usmp
+        bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks)
 
         bench_serve(magus, synth, np, ctx, grid, grid_arr, args, extra, checks)
         out["extra"] = extra
