@@ -5,7 +5,7 @@ import pytest
 
 import paper_2502_03796_amd as magus
 import synth
-from synth import default_config
+from synth import default_config, proxy_model
 from tests.gpu_util import to_dev, results_np, describe_mismatch
 from tests.test_gpu_replay import mixed_traces, LENGTHS
 
@@ -85,6 +85,22 @@ def test_base_variants_replay_sweep_serve(ctx, oracle_mod, base):
     assert (results_np(res) == want_res).all()
     b = lv.cpu().numpy()
     assert (b == want_b).all(), describe_mismatch(b, want_b, offsets)
+    # without decision bytes (the stepped configs take the mask-pass walk)
+    res2, _ = ctx.replay(s, o, cfgs, c)
+    ctx.check()
+    assert (results_np(res2) == want_res).all()
+    # proxy statistics: with a stepped config in the batch (mask pass and
+    # statistics pass), and with every config jumping to the bound (one pass)
+    model = proxy_model()
+    jump = [dict(cf, up_step=0, down_step=0) for cf in cfgs]
+    for batch in (cfgs, jump):
+        st, _ = ctx.proxy(s, o, batch, model, c, metrics=False)
+        ctx.check()
+        stn = st.cpu().numpy()
+        for t in range(len(traces)):
+            x = samples[int(offsets[t]):int(offsets[t + 1])]
+            want_st, _ = oracle_mod.proxy_trace(x, batch[int(cot[t])], model)
+            assert magus.proxy_stats_dict(stn[t]) == want_st, (t, batch[int(cot[t])])
     # sweep: base variants grouped apart from the default base
     want_sc, want_arg = oracle_mod.sweep(samples, offsets, cfgs)
     sc, arg = ctx.sweep(s, o, cfgs, scores=True)
