@@ -517,7 +517,14 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
-    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
+    if (t >= n_traces) return;
+    uint64_t* out = reinterpret_cast<uint64_t*>(stats + t);
+    constexpr uint32_t kWords = sizeof(magus_proxy_stats) / 8;
+    if (chunk_base[n_traces + 1] != 0) {
+        // the plan rejected the batch: zero statistics, as the stepped path
+        for (uint32_t w = lane; w < kWords; w += 64) out[w] = 0;
+        return;
+    }
     const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
     const uint32_t lmin = c.lmin, lmax = c.lmax, linit = c.linit;
     const uint32_t k0 = chunk_base[t], k1 = chunk_base[t + 1];
@@ -566,8 +573,6 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
     emin = dpp_wave_sum64(emin);
     // every word of the trace's stats: 0 excess_max, 1 excess_min,
     // 2 + l steps[l], 2 + 32 + l excess[l]
-    uint64_t* out = reinterpret_cast<uint64_t*>(stats + t);
-    constexpr uint32_t kWords = sizeof(magus_proxy_stats) / 8;
     for (uint32_t w = lane; w < kWords; w += 64) {
         uint64_t val;
         if (w == 0) {

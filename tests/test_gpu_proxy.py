@@ -234,3 +234,29 @@ def test_bulk_workload_full_size_stepped_sampled(ctx, oracle_mod):
     steps = st.cpu().numpy()[:, 2:2 + magus.PROXY_LEVELS].sum(axis=1)
     assert (steps == np.diff(offsets.astype(np.int64))).all()
 
+
+@pytest.mark.parametrize("stepped", [False, True])
+def test_device_data_faults_leave_stats_zero(ctx, stepped):
+    """A batch the device-side checks reject (offsets not monotone, a config
+    index out of range) is reported by check() and leaves the statistics zero,
+    on the one-pass path and on the stepped path."""
+    import torch
+    samples, offsets = synth.make_batch(mixed_traces(1, [100, 100]))
+    s, o, _ = to_dev(samples, offsets)
+    cfg = default_config(up_step=2, down_step=1) if stepped else default_config()
+    model = proxy_model()
+    bad = torch.tensor([0, 150, 100], dtype=torch.int64, device="cuda")   # not monotone
+    st, _ = ctx.proxy(s, bad, [cfg], model, metrics=False)
+    with pytest.raises(magus.MagusError) as ei:
+        ctx.check()
+    assert ei.value.code == magus.EDATA
+    assert (st.cpu().numpy() == 0).all()
+    cot = torch.tensor([0, 5], dtype=torch.int32, device="cuda")      # index out of range
+    st, _ = ctx.proxy(s, o, [cfg], model, cot, metrics=False)
+    with pytest.raises(magus.MagusError):
+        ctx.check()
+    assert (st.cpu().numpy() == 0).all()
+    st, _ = ctx.proxy(s, o, [cfg], model)
+    ctx.check()
+    assert st.cpu().numpy()[:, 2:2 + magus.PROXY_LEVELS].sum() == 200
+
