@@ -72,6 +72,11 @@ def _load():
                                                 ctypes.c_uint32, P]
         lib.oracle_proxy_model_valid.argtypes = [P]
         lib.oracle_proxy_trace.argtypes = [P, ctypes.c_uint64, P, P, P, P]
+        lib.oracle_state_init.argtypes = [P, ctypes.POINTER(_Cfg)]
+        lib.oracle_state_init.restype = None
+        lib.oracle_step.argtypes = [P, ctypes.POINTER(_Cfg), ctypes.c_uint32, P]
+        lib.oracle_state_result.argtypes = [P, ctypes.POINTER(_Res)]
+        lib.oracle_serve_tick.argtypes = [P, P, ctypes.c_uint32, P, P, P, ctypes.c_uint32, P]
         _lib = lib
     return _lib
 
@@ -234,6 +239,54 @@ def proxy_trace(x, cfg: dict, model: dict):
              "steps": list(st.steps), "excess": list(st.excess)}
     metrics = {k: list(getattr(me, k)) for k in _METRIC_KEYS}
     return stats, metrics
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("mem_throughput_ls", ctypes.c_uint32 * 64), ("filled", ctypes.c_uint32),
+                ("level", ctypes.c_uint32), ("uncore_tune_ls", ctypes.c_uint8 * 64),
+                ("level_sum", ctypes.c_uint64), ("transitions", ctypes.c_uint64),
+                ("ticks_high", ctypes.c_uint64), ("steps", ctypes.c_uint64)]
+
+
+class Streams:
+    """Controller states of many streams, each stepped one sample at a time
+    (one invocation per monitoring interval, Sec. 3.2)."""
+
+    def __init__(self, cfgs, cfg_of_stream):
+        self.cfgs = _cfg_array(cfgs)
+        self.n_cfgs = len(cfgs)
+        self.cfg_of_stream = np.ascontiguousarray(cfg_of_stream, dtype=np.uint32)
+        n = len(self.cfg_of_stream)
+        if n and int(self.cfg_of_stream.max()) >= self.n_cfgs:
+            raise ValueError("oracle: config index out of range")
+        self.states = (_State * n)()
+        lib = _load()
+        for i in range(n):
+            lib.oracle_state_init(ctypes.byref(self.states[i]),
+                                  ctypes.byref(self.cfgs[int(self.cfg_of_stream[i])]))
+
+    def reset(self, stream: int) -> None:
+        _load().oracle_state_init(ctypes.byref(self.states[stream]),
+                                  ctypes.byref(self.cfgs[int(self.cfg_of_stream[stream])]))
+
+    def tick(self, streams, samples):
+        """One step for each (stream, sample) pair, in order; returns the decision bytes."""
+        st = np.ascontiguousarray(streams, dtype=np.uint32)
+        x = np.ascontiguousarray(samples, dtype=np.uint32)
+        if len(st) != len(x) or (len(st) and int(st.max()) >= len(self.cfg_of_stream)):
+            raise ValueError("oracle: bad stream ids")
+        out = np.empty(len(x), dtype=np.uint8)
+        rc = _load().oracle_serve_tick(ctypes.cast(self.states, ctypes.c_void_p), self.cfgs,
+                                       self.n_cfgs, _ptr(self.cfg_of_stream), _ptr(st), _ptr(x),
+                                       len(x), _ptr(out))
+        if rc != 0:
+            raise ValueError("oracle: invalid tick")
+        return out
+
+    def result(self, stream: int) -> dict:
+        r = _Res()
+        _load().oracle_state_result(ctypes.byref(self.states[stream]), ctypes.byref(r))
+        return _res_dict(r)
 
 
 def decode(byte_arr):

@@ -136,67 +136,123 @@ static int high_freq_detection(uint32_t hf_num, uint32_t hf_den,
 
 /* ----------------------------------------------------------- the controller */
 
+void oracle_state_init(oracle_state* s, const oracle_config* c)
+{
+    memset(s, 0, sizeof *s);             /* both FIFOs empty, uncore_tune_ls all 0 */
+    s->level = c->level_init;            /* idle nodes sit at the minimum */
+}
+
+/*
+ * One invocation of the controller (Sec. 3.2: the runtime is invoked once per
+ * monitoring interval with the newest throughput sample).  Returns the step's
+ * decision byte: bits 0-4 level, bit 5 high, bits 6-7 pred + 1.
+ */
+static uint8_t controller_step(oracle_state* s, const oracle_config* c, uint32_t sample,
+                               int use_fp64, double inc_threshold, double dec_threshold)
+{
+    uint32_t* mem_throughput_ls = s->mem_throughput_ls;
+    uint8_t* uncore_tune_ls = s->uncore_tune_ls;
+    const uint32_t W = c->direv_length;
+    const uint32_t H = c->tune_len;
+    uint32_t level = s->level;
+
+    /* 1. monitor: FIFO of the last W samples */
+    if (s->filled == W) {
+        memmove(mem_throughput_ls, mem_throughput_ls + 1, (W - 1) * sizeof(uint32_t));
+        mem_throughput_ls[W - 1] = sample;
+    } else {
+        mem_throughput_ls[s->filled++] = sample;
+    }
+
+    /* 2. predict (temporary decision) */
+    int pred = 0;
+    if (s->filled == W) {
+        pred = use_fp64 ? predict_fp64(inc_threshold, dec_threshold, mem_throughput_ls, W,
+                                       c->base)
+                        : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W, c->base);
+    }
+
+    /* 3. log whether a frequency change would be triggered */
+    memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);
+    uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);
+
+    /* 4. detect the high-frequency state */
+    int high = high_freq_detection(c->hf_num, c->hf_den, uncore_tune_ls, H);
+
+    /* 5. decide */
+    uint32_t next = level;
+    if (high) {
+        next = c->level_max;
+    } else if (pred == 1) {
+        next = c->up_step == 0 ? c->level_max
+             : (level + c->up_step > c->level_max ? c->level_max : level + c->up_step);
+    } else if (pred == -1) {
+        next = c->down_step == 0 ? c->level_min
+             : (level < c->level_min + c->down_step ? c->level_min : level - c->down_step);
+    }
+
+    s->transitions += (next != level);
+    level = next;
+    s->level = level;
+    s->level_sum += level;
+    s->ticks_high += (uint64_t)high;
+    s->steps += 1;
+    return (uint8_t)(level | ((uint32_t)high << 5) | ((uint32_t)(pred + 1) << 6));
+}
+
+static void state_result(const oracle_state* s, oracle_result* res)
+{
+    res->level_sum = s->level_sum;
+    res->transitions = s->transitions;
+    res->ticks_high = s->ticks_high;
+    res->score = s->level_sum + 1000u * s->transitions;
+}
+
 static void run_trace(const uint32_t* x, uint64_t n, const oracle_config* c,
                       int use_fp64, double inc_threshold, double dec_threshold,
                       uint8_t* bytes, oracle_result* res)
 {
-    uint32_t mem_throughput_ls[ORACLE_FIFO_MAX];
-    uint8_t uncore_tune_ls[ORACLE_FIFO_MAX];
-    uint32_t filled = 0;                 /* samples currently in the FIFO */
-    const uint32_t W = c->direv_length;
-    const uint32_t H = c->tune_len;
-    memset(uncore_tune_ls, 0, sizeof uncore_tune_ls);
-
-    uint32_t level = c->level_init;      /* idle nodes sit at the minimum */
-    uint64_t level_sum = 0, transitions = 0, ticks_high = 0;
-
+    oracle_state s;
+    oracle_state_init(&s, c);
     for (uint64_t t = 0; t < n; ++t) {
-        /* 1. monitor: FIFO of the last W samples */
-        if (filled == W) {
-            memmove(mem_throughput_ls, mem_throughput_ls + 1, (W - 1) * sizeof(uint32_t));
-            mem_throughput_ls[W - 1] = x[t];
-        } else {
-            mem_throughput_ls[filled++] = x[t];
-        }
-
-        /* 2. predict (temporary decision) */
-        int pred = 0;
-        if (filled == W) {
-            pred = use_fp64 ? predict_fp64(inc_threshold, dec_threshold, mem_throughput_ls, W,
-                                           c->base)
-                            : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W, c->base);
-        }
-
-        /* 3. log whether a frequency change would be triggered */
-        memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);
-        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);
-
-        /* 4. detect the high-frequency state */
-        int high = high_freq_detection(c->hf_num, c->hf_den, uncore_tune_ls, H);
-
-        /* 5. decide */
-        uint32_t next = level;
-        if (high) {
-            next = c->level_max;
-        } else if (pred == 1) {
-            next = c->up_step == 0 ? c->level_max
-                 : (level + c->up_step > c->level_max ? c->level_max : level + c->up_step);
-        } else if (pred == -1) {
-            next = c->down_step == 0 ? c->level_min
-                 : (level < c->level_min + c->down_step ? c->level_min : level - c->down_step);
-        }
-
-        transitions += (next != level);
-        level = next;
-        level_sum += level;
-        ticks_high += (uint64_t)high;
-        if (bytes)
-            bytes[t] = (uint8_t)(level | ((uint32_t)high << 5) | ((uint32_t)(pred + 1) << 6));
+        const uint8_t b = controller_step(&s, c, x[t], use_fp64, inc_threshold, dec_threshold);
+        if (bytes) bytes[t] = b;
     }
-    res->level_sum = level_sum;
-    res->transitions = transitions;
-    res->ticks_high = ticks_high;
-    res->score = level_sum + 1000u * transitions;
+    state_result(&s, res);
+}
+
+int oracle_step(oracle_state* s, const oracle_config* cfg, uint32_t sample, uint8_t* byte)
+{
+    if (!s || !oracle_config_valid(cfg)) return -1;
+    const uint8_t b = controller_step(s, cfg, sample, 0, 0.0, 0.0);
+    if (byte) *byte = b;
+    return 0;
+}
+
+int oracle_state_result(const oracle_state* s, oracle_result* res)
+{
+    if (!s || !res) return -1;
+    state_result(s, res);
+    return 0;
+}
+
+/*
+ * One serving tick: stream i (state states[stream[i]], config
+ * cfgs[cfg_of_stream[stream[i]]]) takes sample samples[i]; bytes[i] receives
+ * its decision byte.  Plain loop over the pairs in order.
+ */
+int oracle_serve_tick(oracle_state* states, const oracle_config* cfgs, uint32_t n_cfgs,
+                      const uint32_t* cfg_of_stream, const uint32_t* stream,
+                      const uint32_t* samples, uint32_t n, uint8_t* bytes)
+{
+    if (!states || !cfgs || !cfg_of_stream || (n && (!stream || !samples || !bytes)))
+        return -1;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t k = cfg_of_stream[stream[i]];
+        if (k >= n_cfgs || !oracle_config_valid(&cfgs[k])) return -1;
+        bytes[i] = controller_step(&states[stream[i]], &cfgs[k], samples[i], 0, 0.0, 0.0);
+    }
+    return 0;
 }
 
 int oracle_replay_trace(const uint32_t* x, uint64_t n, const oracle_config* cfg,

@@ -34,6 +34,31 @@ typedef struct oracle_result {
 
 int oracle_config_valid(const oracle_config* c);
 
+/*
+ * Controller state of one stream between invocations (Sec. 3.2: one
+ * invocation per monitoring interval): the two FIFOs, the level and the
+ * running sums.
+ */
+typedef struct oracle_state {
+    uint32_t mem_throughput_ls[64];   /* the last `filled` samples, oldest first  */
+    uint32_t filled;                  /* samples in mem_throughput_ls (<= W)      */
+    uint32_t level;                   /* current uncore level                     */
+    uint8_t uncore_tune_ls[64];       /* the last H event flags, oldest first      */
+    uint64_t level_sum;
+    uint64_t transitions;
+    uint64_t ticks_high;
+    uint64_t steps;                   /* invocations so far                       */
+} oracle_state;
+
+void oracle_state_init(oracle_state* s, const oracle_config* c);
+/* one invocation with the newest sample; *byte (optional) = decision byte */
+int oracle_step(oracle_state* s, const oracle_config* cfg, uint32_t sample, uint8_t* byte);
+int oracle_state_result(const oracle_state* s, oracle_result* res);
+/* one tick of many streams: bytes[i] = step of stream[i] with samples[i] */
+int oracle_serve_tick(oracle_state* states, const oracle_config* cfgs, uint32_t n_cfgs,
+                      const uint32_t* cfg_of_stream, const uint32_t* stream,
+                      const uint32_t* samples, uint32_t n, uint8_t* bytes);
+
 /* bytes (optional, n entries): bits 0-4 level, bit 5 high, bits 6-7 pred+1 */
 int oracle_replay_trace(const uint32_t* x, uint64_t n, const oracle_config* cfg,
                         uint8_t* bytes, oracle_result* res);

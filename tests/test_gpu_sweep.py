@@ -89,41 +89,64 @@ def test_sweep_equals_replay_on_the_gpu(ctx, oracle_mod):
 
 
 def test_sweep_workload_full_size(ctx, oracle_mod):
-    """1,024 traces x 50,000 samples x a window block of 4,096 configs (the
-    benchmark's sweep launch), for the first and the last window block: every
-    config on 16 traces, a stratified 1/16 (first block) or 1/64 (last block)
-    of the configs on every trace, and every trace's arg-min, against the
-    oracle.  The oracle runs in host threads (its ctypes calls release the
+    """The benchmark's sweep launch: 1,024 traces x 50,000 samples against all
+    16,384 grid configs (four window blocks) in ONE call, checked against the
+    oracle three ways:
+      - every config on 16 traces, and those traces' 16,384-wide arg-min
+        against the oracle's arg-min over the same configs;
+      - a stratified 1/16 of the configs (every 16th, so 256 in each window
+        block) on every trace;
+      - every trace's arg-min is the lowest index among the minimal scores
+        of the GPU score matrix (internal consistency of the arg-min
+        reduction with the scores, which the two checks above pin).
+    The oracle runs in host threads (its ctypes calls release the
     interpreter lock)."""
     samples, offsets = synth.workload_sweep_traces()
     grid = synth.sweep_grid()
+    n_cfg = len(grid)
+    assert n_cfg == 16384
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
     s, o, _ = to_dev(samples, offsets)
+    arr = magus.config_array(grid)
+    sc, arg = ctx.sweep(s, o, arr, scores=True)
+    ctx.check()
+    sc = sc.cpu().numpy().view(np.uint64)
+    arg = arg.cpu().numpy().astype(np.uint32)
+    assert sc.shape == (1024, n_cfg)
 
-    def oracle_scores(traces, cfgs):
-        part = synth.make_batch([samples[int(offsets[t]):int(offsets[t + 1])] for t in traces])
-        return oracle_mod.sweep(part[0], part[1], cfgs)[0]
+    def part(traces):
+        return synth.make_batch([samples[int(offsets[t]):int(offsets[t + 1])] for t in traces])
 
-    for wblock, stride in ((0, 16), (3, 64)):
-        cfgs = grid[wblock * 4096:(wblock + 1) * 4096]
-        sc, arg = ctx.sweep(s, o, cfgs, scores=True)
-        ctx.check()
-        sc = sc.cpu().numpy().view(np.uint64)
-        arg = arg.cpu().numpy()
-        rng = np.random.default_rng(wblock)
-        every16 = sorted(rng.choice(1024, 16, replace=False).tolist())
-        cpick = np.arange(int(rng.integers(0, stride)), 4096, stride)
-        sub_cfgs = [cfgs[i] for i in cpick]
-        with ThreadPoolExecutor(max_workers=threads) as pool:
-            # every config on 16 traces (one trace per task)
-            for t, row in zip(every16, pool.map(lambda t: oracle_scores([t], cfgs)[0], every16)):
-                assert (sc[t] == row).all(), (wblock, t)
-            # the stratified config sample on every trace
-            starts = list(range(0, 1024, 16))
-            rows = pool.map(lambda t0: oracle_scores(range(t0, t0 + 16), sub_cfgs), starts)
-            for t0, r in zip(starts, rows):
-                assert (sc[t0:t0 + 16][:, cpick] == r).all(), (wblock, t0)
-        # the arg-min of every trace: the lowest index among the minimal scores
-        mins = sc.min(axis=1)
-        assert (sc[np.arange(1024), arg] == mins).all()
-        assert (arg == np.argmax(sc == mins[:, None], axis=1)).all()
+    rng = np.random.default_rng(2024)
+    every = sorted(rng.choice(1024, 16, replace=False).tolist())
+    cpick = np.arange(int(rng.integers(0, 16)), n_cfg, 16)
+    assert all(((cpick >= 4096 * w) & (cpick < 4096 * (w + 1))).sum() == 256 for w in range(4))
+    sub_cfgs = [grid[i] for i in cpick]
+
+    # every config on 16 traces: one task per (trace, window block)
+    def full_row_block(tw):
+        t, w = tw
+        b = part([t])
+        return oracle_mod.sweep(b[0], b[1], grid[w * 4096:(w + 1) * 4096])[0][0]
+
+    def stratified(t0):
+        b = part(range(t0, t0 + 16))
+        return oracle_mod.sweep(b[0], b[1], sub_cfgs)[0]
+
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        tasks = [(t, w) for t in every for w in range(4)]
+        rows = {}
+        for (t, w), r in zip(tasks, pool.map(full_row_block, tasks)):
+            rows.setdefault(t, [None] * 4)[w] = r
+        starts = list(range(0, 1024, 16))
+        strat = list(pool.map(stratified, starts))
+    for t in every:
+        want = np.concatenate(rows[t])
+        assert (sc[t] == want).all(), (t, describe_mismatch(sc[t], want))
+        # the oracle's arg-min over all 16,384 configs: lowest index of the minimum
+        assert arg[t] == int(np.argmin(want)), (t, int(arg[t]), int(np.argmin(want)))
+    for t0, r in zip(starts, strat):
+        assert (sc[t0:t0 + 16][:, cpick] == r).all(), (t0, describe_mismatch(
+            sc[t0:t0 + 16][:, cpick].ravel(), r.ravel()))
+    mins = sc.min(axis=1)
+    assert (arg == np.argmax(sc == mins[:, None], axis=1)).all()

@@ -40,8 +40,8 @@ MUTANTS = [
      "if (lhs < -(int64_t)dec_q * den) return -1;"),
     ("Alg. 2 with > instead of >=", "return (uint64_t)sum * hf_den >= (uint64_t)hf_num * len;",
      "return (uint64_t)sum * hf_den > (uint64_t)hf_num * len;"),
-    ("high state does not override", "        if (high) {\n            next = c->level_max;",
-     "        if (0) {\n            next = c->level_max;"),
+    ("high state does not override", "    if (high) {\n        next = c->level_max;",
+     "    if (0) {\n        next = c->level_max;"),
     ("only increases are logged", "uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
      "uncore_tune_ls[H - 1] = (uint8_t)(pred == 1);"),
     ("decrease by one step instead of to the bound",
@@ -53,14 +53,14 @@ MUTANTS = [
     ("stepped decrease ignores the step size",
      ": (level < c->level_min + c->down_step ? c->level_min : level - c->down_step);",
      ": (level < c->level_min + 1 ? c->level_min : level - 1);"),
-    ("first transition from idle not counted", "transitions += (next != level);",
-     "transitions += (t > 0 && next != level);"),
-    ("transition weight wrong", "res->score = level_sum + 1000u * transitions;",
-     "res->score = level_sum + 100u * transitions;"),
+    ("first transition from idle not counted", "s->transitions += (next != level);",
+     "s->transitions += (s->steps > 0 && next != level);"),
+    ("transition weight wrong", "res->score = s->level_sum + 1000u * s->transitions;",
+     "res->score = s->level_sum + 100u * s->transitions;"),
     ("event FIFO one step short", "memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);\n"
-     "        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
+     "    uncore_tune_ls[H - 1] = (uint8_t)(pred != 0);",
      "memmove(uncore_tune_ls, uncore_tune_ls + 1, H - 1);\n"
-     "        uncore_tune_ls[H - 1] = (uint8_t)(pred != 0); if (H > 1) uncore_tune_ls[0] = 0;"),
+     "    uncore_tune_ls[H - 1] = (uint8_t)(pred != 0); if (H > 1) uncore_tune_ls[0] = 0;"),
     ("proxy: interval runs at the level set after its own step",
      "lv[0] = t == 0 ? cfg->level_init : (uint32_t)(bytes[t - 1] & 31u);",
      "lv[0] = (uint32_t)(bytes[t] & 31u);"),

@@ -510,3 +510,33 @@ def test_counters_against_exact_rationals(oracle_mod):
                 dt = int(ts[i + 1]) - int(ts[i])
                 want = 0 if dt == 0 else min(int(Fraction(d * bpc * 1000, dt)), 2**32 - 1)
                 assert out[i] == want, (bits, bpc, i)
+
+
+# ------------------------------------------------ per-interval invocation form
+
+def test_stream_steps_equal_trace_replay(oracle_mod):
+    """Stepping streams one sample per tick (interleaved, one invocation per
+    interval) gives the same decision bytes and results as replaying each
+    trace whole."""
+    rng = np.random.default_rng(12)
+    grid = synth.sweep_grid()
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), 5)] + \
+        [default_config(up_step=2, down_step=1, base=1)]
+    n_streams = 40
+    cot = rng.integers(0, len(cfgs), n_streams)
+    traces = [synth.geometric_phase_trace(int(rng.integers(0, 300)), synth.stream_key(77, i),
+                                          mean=20.0, short_prob=0.3) for i in range(n_streams)]
+    st = oracle_mod.Streams(cfgs, cot)
+    got = [[] for _ in range(n_streams)]
+    for k in range(max(len(x) for x in traces)):
+        ids = [i for i in range(n_streams) if k < len(traces[i])]
+        rng.shuffle(ids)
+        b = st.tick(ids, [traces[i][k] for i in ids])
+        for i, v in zip(ids, b):
+            got[i].append(int(v))
+    for i, x in enumerate(traces):
+        r, want = oracle_mod.replay_trace(x, cfgs[int(cot[i])])
+        assert bytes(got[i]) == want.tobytes(), i
+        assert st.result(i) == r, i
+    st.reset(3)
+    assert st.result(3)["score"] == 0
