@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chunk_kernel_bulk_traffic.json")
 SWEEP_COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_sweep_counters.json")
+# sources of the sweep kernel and of the VALU probe (the counters are keyed to them)
+SWEEP_SOURCES = ("sweep.hip", "sweep_step.h", "valu_probe.hip", "magus_internal.h")
 
 
 def log(*a):
@@ -62,13 +64,47 @@ def stored_sweep_counters():
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != source_hash(("sweep.hip", "magus_internal.h")):
+    if t.get("source_sha256") != source_hash(SWEEP_SOURCES):
         return None
     return t
 
 
-def bench_sweep(magus, synth, ctx, dev):
-    """The configuration sweep: 1,024 traces x 50,000 samples x 16,384 configs."""
+def host_threads():
+    """Host threads for the oracle: the cores this process may run on, capped
+    at the 16-core host share that one GPU of the box comes with."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def valu_probe(magus, ctx, dev, n_work=1024, blocks=64, steps=5000, reps=3):
+    """Times magus_valu_probe: `n_work * blocks` workgroups of 256 lanes, each
+    lane running the sweep's per-evaluation step `steps` times."""
+    import torch
+    wg = n_work * blocks
+    out = torch.empty(wg * 256, dtype=torch.int32, device=dev)
+    ctx.valu_probe(wg, steps, out)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    ctx.kernel_time(magus.KERNEL_PROBE)
+    for _ in range(reps):
+        ctx.valu_probe(wg, steps, out)
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    ms, n = ctx.kernel_time(magus.KERNEL_PROBE)
+    evals = float(wg) * 256 * steps
+    r = {"workgroups": wg, "steps": steps, "kernel_ms": ms / n,
+         "evals_per_s": evals / (ms / n * 1e-3)}
+    cnt = stored_sweep_counters()
+    if cnt and cnt.get("probe_valu_insts_per_launch") and cnt.get("probe_evals_per_launch"):
+        r["valu_insts_per_eval"] = cnt["probe_valu_insts_per_launch"] * 64 / \
+            cnt["probe_evals_per_launch"]
+    del out
+    return r
+
+
+def bench_sweep(magus, synth, ctx, dev, checks=None, cpu=None):
+    """The configuration sweep: 1,024 traces x 50,000 samples x 16,384 configs.
+    The oracle checks (and times) the timed call's arg-min and one call's
+    scores on 4 sampled traces over all 16,384 configs."""
     import numpy as np
     import torch
     log("sweep workload ...")
@@ -90,12 +126,19 @@ def bench_sweep(magus, synth, ctx, dev):
     ctx.set_profiling(False)
     kms, kn = ctx.kernel_time(magus.KERNEL_SWEEP)
     ctx.check()
+    arg_np = arg.cpu().numpy().astype(np.uint32)
+    pick = [0, 341, 682, 1023]
+    sc, _ = ctx.sweep(ss, so, grid_arr, scores=True)
+    ctx.check()
+    rows = sc[pick].cpu().numpy().view(np.uint64).copy()
+    del sc
     evals = float(len(ssmp)) * len(grid)
     kern_s = kms / kn * 1e-3
     res = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
            "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3, "kernel_ms": kern_s * 1e3,
            # lane-ops per evaluation the VALU could issue at peak in this time
-           "valu_lane_ops_per_eval_at_peak": VALU_PEAK_OPS * kern_s / evals}
+           "valu_lane_ops_per_eval_at_peak": VALU_PEAK_OPS * kern_s / evals,
+           "parity": "not checked (--no-cpu)"}
     cnt = stored_sweep_counters()
     if cnt:
         # wave instructions issued / (kernel time x 1 wave-instruction per
@@ -103,6 +146,61 @@ def bench_sweep(magus, synth, ctx, dev):
         res["valu_issue_frac"] = cnt["valu_insts_per_launch"] / (kern_s * 256 * 2.4e9)
         res["valu_lane_ops_per_eval"] = cnt["valu_insts_per_launch"] * 64 / evals
     log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
+    # the VALU ceiling of the sweep's per-evaluation step: the same step on
+    # register data (no LDS tiles, no pre-pass, no barriers) in as many
+    # workgroups as the sweep launches, timed the same way
+    probe = valu_probe(magus, ctx, dev, n_work=len(soff) - 1, blocks=64)
+    res["roofline"] = {
+        "bound": "valu", "kernel": "sweep_kernel",
+        "achieved": evals / kern_s, "peak": probe["evals_per_s"], "unit": "evals/s",
+        "frac": evals / kern_s / probe["evals_per_s"],
+        "peak_source": "valu_probe_kernel: the sweep's per-evaluation step (mask_step) on "
+                       "register data, 65,536 workgroups of 256 lanes, timed in this run",
+        "probe": probe}
+    if cnt and probe.get("valu_insts_per_eval"):
+        # issue rates in wave instructions per clock per compute unit at 2.4 GHz
+        res["roofline"]["valu_issue_per_clk_per_cu"] = {
+            "sweep": res["valu_issue_frac"],
+            "probe": probe["valu_insts_per_eval"] / 64 * probe["evals_per_s"] /
+            (256 * 2.4e9)}
+    log(f"  VALU probe {probe['evals_per_s']:.3e} evals/s: sweep at "
+        f"{res['roofline']['frac']:.1%} of the probe's rate")
+    traces = {t: ssmp[int(soff[t]):int(soff[t + 1])].copy() for t in pick}
+
+    def check_sweep(oracle):
+        # the oracle over all 16,384 configs on the sampled traces, one task
+        # per (trace, 1,024-config slice) on the host threads; timed, since it
+        # is also the oracle's sweep baseline
+        from concurrent.futures import ThreadPoolExecutor
+        tasks = [(t, k) for t in pick for k in range(16)]
+
+        def run(tk):
+            t, k = tk
+            b = synth.make_batch([traces[t]])
+            return oracle.sweep(b[0], b[1], grid[k * 1024:(k + 1) * 1024])[0][0]
+        n = host_threads()
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=n) as pool:
+            parts = list(pool.map(run, tasks))
+        odt = time.perf_counter() - t0
+        for i, t in enumerate(pick):
+            want = np.concatenate(parts[16 * i:16 * i + 16])
+            if not (rows[i] == want).all():
+                raise SystemExit(f"sweep parity failure (scores) on trace {t}")
+            if int(arg_np[t]) != int(np.argmin(want)):
+                raise SystemExit(f"sweep parity failure (arg-min) on trace {t}")
+        res["parity"] = (f"ok: {len(pick)} sampled traces x all 16,384 configs: scores and "
+                         "the timed call's arg-min equal the oracle")
+        if cpu is not None:
+            oev = float(len(pick)) * len(traces[pick[0]]) * len(grid)
+            cpu["sweep"] = {"value": oev / odt, "unit": "evals/s", "cores": n,
+                            "sample": f"{len(pick)} of the 1,024 sweep traces x all 16,384 "
+                                      f"configs ({oev:.3g} evals, 1/256 of the sweep) in "
+                                      f"{odt:.2f} s",
+                            "extrapolated_full_sweep_s": evals / (oev / odt)}
+        log(f"  oracle sweep: {oev / odt:.3e} evals/s on {n} threads")
+    if checks is not None:
+        checks.append(check_sweep)
     del ss, so
     torch.cuda.empty_cache()
     return res, grid_arr
@@ -216,7 +314,7 @@ def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, p
 
 # Serving: 65,536 simulated nodes through the continuous-batching loop, in
 # real time (decision latency) and flat out (throughput).
-def bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks):
+def bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks, cpu=None):
     """The uneven batch: 20,000 bursty traces of log-normal lengths, a grid
     config per trace, autotuned chunk length, one hipGraph launch per call."""
     log("uneven workload: 20,000 traces, autotuned, hipGraph ...")
@@ -241,16 +339,42 @@ def bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks):
     dt = (time.perf_counter() - t0) / reps
     uctx.check()
     ugot = ures.cpu().numpy().view(np.uint64)
-    upick = {t: (usmp[int(uoff[t]):int(uoff[t + 1])].copy(), grid[int(ucot[t])])
-             for t in (0, int(np.argmax(np.diff(uoff.astype(np.int64)))), len(uoff) - 2)}
+    # the first fifth of the traces (4,000, contiguous) for the oracle: every
+    # one of their results is checked, and the run is the oracle's baseline
+    # on this workload
+    n_part = (len(uoff) - 1) // 5
+    part_smp = usmp[:int(uoff[n_part])].copy()
+    part_off = uoff[:n_part + 1].copy()
+    part_cot = ucot[:n_part].copy()
+    n_total = len(usmp)
 
     def check_uneven(oracle):
-        for t, (x, c) in upick.items():
-            r, _ = oracle.replay_trace(x, c, want_bytes=False)
-            if list(ugot[t]) != [r["score"], r["level_sum"], r["transitions"],
-                                 r["ticks_high"]]:
-                raise SystemExit(f"uneven parity failure on trace {t}")
-        extra["uneven"]["parity"] = f"ok: {len(upick)} sampled traces equal the oracle"
+        from concurrent.futures import ThreadPoolExecutor
+        n = host_threads()
+        bounds = np.linspace(0, n_part, 4 * n + 1).astype(np.int64)
+
+        def run(i):
+            a, b = int(bounds[i]), int(bounds[i + 1])
+            return oracle.replay_batch(part_smp[int(part_off[a]):int(part_off[b])],
+                                       part_off[a:b + 1] - part_off[a], grid,
+                                       part_cot[a:b])[0]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=n) as pool:
+            want = np.concatenate(list(pool.map(run, range(4 * n))))
+        odt = time.perf_counter() - t0
+        bad = np.nonzero((ugot[:n_part] != want).any(axis=1))[0]
+        if len(bad):
+            raise SystemExit(f"uneven parity failure on trace {int(bad[0])}")
+        extra["uneven"]["parity"] = (f"ok: all results of the first {n_part} traces "
+                                     f"({len(part_smp)} samples) equal the oracle")
+        if cpu is not None:
+            cpu["uneven"] = {"value": len(part_smp) / odt, "unit": "samples*configs/s",
+                             "cores": n,
+                             "sample": f"the first {n_part} of the 20,000 uneven traces "
+                                       f"({len(part_smp)} samples, each with its grid "
+                                       f"config) in {odt:.2f} s",
+                             "extrapolated_full_call_s": n_total / (len(part_smp) / odt)}
+        log(f"  oracle uneven: {len(part_smp) / odt:.3e} samples/s on {n} threads")
     checks.append(check_uneven)
     ideal_ms = 4.0 * len(usmp) / (HBM_PEAK_GBS * 1e9) * 1e3
     extra["uneven"] = {
@@ -311,6 +435,90 @@ def bench_serve(magus, synth, np, ctx, grid, grid_arr, args, extra, checks):
         f"flat-out {extra['serve']['flat_out_samples_per_s']:.3e} samples/s")
 
 
+def host_leg(np, synth, samples, offsets, cfg, args):
+    """The oracle as it is, timed on the host cores.  The headline figure runs
+    every bulk trace on the host threads (one call per slice of traces; the
+    ctypes calls release the interpreter lock); beside it: one thread on a
+    sixteenth of the bulk traces, and one serving tick of 65,536 streams.
+    The sweep and uneven figures are added by their checks."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    n = host_threads()
+    out = {}
+
+    def timed(fn, min_s):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                return dt / reps, reps
+
+    # one thread on traces 0..255 (25.6 million samples)
+    one = args.traces // 16
+    s1, o1 = samples[:int(offsets[one])], offsets[:one + 1]
+    dt1, reps1 = timed(lambda: oracle.replay_batch(s1, o1, [cfg]), 1.0)
+    single = {"value": int(o1[-1]) / dt1, "unit": "samples*configs/s", "cores": 1,
+              "sample": f"the first {one} bulk traces ({int(o1[-1])} samples), "
+                        f"{reps1} passes of {dt1:.2f} s"}
+    log(f"oracle on one host thread: {single['value']:.3e} samples/s")
+
+    # all bulk traces on n threads, one slice of traces per task
+    log(f"oracle baseline on the host: {n} threads over the bulk traces ...")
+    bounds = np.linspace(0, args.traces, 4 * n + 1).astype(np.int64)
+
+    def slice_run(i):
+        a, b = int(bounds[i]), int(bounds[i + 1])
+        oracle.replay_batch(samples[int(offsets[a]):int(offsets[b])],
+                            offsets[a:b + 1] - offsets[a], [cfg])
+
+    with ThreadPoolExecutor(max_workers=n) as pool:
+        dt, reps = timed(lambda: list(pool.map(slice_run, range(4 * n))), 2.0)
+    n_samples = int(offsets[-1])
+    out.update({"value": n_samples / dt, "unit": "samples*configs/s", "cores": n,
+                "kind": "oracle",
+                "sample": f"all {args.traces} traces x {args.length} samples, 1 config, "
+                          f"{n} threads over trace slices, {reps} passes of {dt:.2f} s "
+                          f"({reps * dt * n:.0f} core-s)",
+                "host_cpus_seen": os.cpu_count(),
+                "single_thread": single})
+    log(f"  oracle {n_samples / dt:.3e} samples/s ({dt:.2f} s per pass)")
+
+    # one serving tick: 65,536 streams with grid configs, one sample each,
+    # through the oracle's per-invocation step, streams split over n threads
+    grid = synth.sweep_grid()
+    n_streams = 65536
+    rng = np.random.default_rng(5)
+    cot = rng.integers(0, len(grid), n_streams)
+    parts = np.array_split(np.arange(n_streams), n)
+    fleets = [oracle.Streams(grid, cot[p]) for p in parts]
+    ticks = 50
+    # tick k of stream i takes bulk sample k of trace i mod 4,096
+    src = samples[:int(offsets[args.traces])].reshape(args.traces, -1) \
+        if int(offsets[-1]) == args.traces * args.length else None
+    tick_x = [np.ascontiguousarray(src[np.arange(n_streams) % args.traces, k])
+              for k in range(ticks)] if src is not None else \
+        [rng.integers(1000, 200000, n_streams).astype(np.uint32) for _ in range(ticks)]
+
+    def tick_part(j, k):
+        p = parts[j]
+        fleets[j].tick(np.arange(len(p)), tick_x[k][p])
+
+    with ThreadPoolExecutor(max_workers=n) as pool:
+        t0 = time.perf_counter()
+        for k in range(ticks):
+            list(pool.map(lambda j: tick_part(j, k), range(n)))
+        tdt = (time.perf_counter() - t0) / ticks
+    out["serve_tick"] = {"value": n_streams / tdt, "unit": "decisions/s", "cores": n,
+                         "ms_per_tick": tdt * 1e3,
+                         "sample": f"{ticks} ticks of {n_streams} streams (grid configs), one "
+                                   f"sample per stream per tick, oracle step per stream"}
+    log(f"  oracle serving tick: {tdt * 1e3:.2f} ms per 65,536-stream tick on {n} threads")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +531,8 @@ def main():
     ap.add_argument("--serve-ticks", type=int, default=300)
     ap.add_argument("--chunk", type=int, default=0, help="time-chunk length (0: default)")
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the VALU issue probe at the sweep's launch size")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only run the configuration sweep and print its figures")
     ap.add_argument("--only", choices=["stepped", "proxy", "serve", "uneven"],
@@ -353,6 +563,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "bitwise_xor int32", "elements": n,
                           "read_bytes": 4 * n, "write_bytes": 4 * n, "launches": 3}))
+        return
+    if args.valu_probe:
+        ctx = magus.Context(0)
+        print(json.dumps({"valu_probe": valu_probe(magus, ctx, dev)}), flush=True)
+        ctx.close()
         return
     if args.sweep_only:
         ctx = magus.Context(0)
@@ -432,6 +647,7 @@ def main():
     # part of this script that touches the oracle); each takes the oracle
     # module and fills in its report
     checks = []
+    cpu_extra = {}      # the oracle's figures on the other workloads, filled by checks
     got = results.cpu().numpy().view(np.uint64)
     rng = np.random.default_rng(0)
     pick = sorted(set(rng.integers(0, args.traces, 8).tolist()))
@@ -521,43 +737,20 @@ def main():
         del s, o
         torch.cuda.empty_cache()
 
-        extra["sweep"], grid_arr = bench_sweep(magus, synth, ctx, dev)
+        extra["sweep"], grid_arr = bench_sweep(magus, synth, ctx, dev, checks, cpu_extra)
         grid = synth.sweep_grid()
 
-        bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks)
+        bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks, cpu_extra)
 
         bench_serve(magus, synth, np, ctx, grid, grid_arr, args, extra, checks)
         out["extra"] = extra
 
     if not args.no_cpu:
-        # the host leg: the oracle as it is, one call per slice of traces on each host thread
-        # (its ctypes calls release the interpreter lock); several passes so
-        # the sample is ~10 s of CPU work
-        from concurrent.futures import ThreadPoolExecutor
-
-        import oracle
-        threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        passes = 3
-        log(f"oracle baseline on the host: {threads} threads x {passes} passes ...")
-        bounds = np.linspace(0, args.traces, threads + 1).astype(np.int64)
-
-        def slice_run(i):
-            a, b = int(bounds[i]), int(bounds[i + 1])
-            oracle.replay_batch(samples[int(offsets[a]):int(offsets[b])],
-                                offsets[a:b + 1] - offsets[a], [cfg])
-
-        t0 = time.perf_counter()
-        with ThreadPoolExecutor(max_workers=threads) as pool:
-            for _ in range(passes):
-                list(pool.map(slice_run, range(threads)))
-        dt = (time.perf_counter() - t0) / passes
-        out["cpu_baseline"] = {"value": n_samples / dt, "unit": "samples*configs/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"all {args.traces} traces x {args.length} samples, "
-                                         f"1 config, {threads} threads over trace slices, "
-                                         f"{passes} passes of {dt:.2f} s"}
-        log(f"  oracle {n_samples / dt:.3e} samples/s ({dt:.2f} s per pass)")
+        out["cpu_baseline"] = host_leg(np, synth, samples, offsets, cfg, args)
+        cpu_extra.update(out["cpu_baseline"])
+        out["cpu_baseline"] = cpu_extra
         # then the oracle checks of the GPU results kept above
+        import oracle
         for check in checks:
             check(oracle)
 

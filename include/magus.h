@@ -178,13 +178,15 @@ int magus_autotune_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_
  * Kernel timing.  While enabled, every call records a pair of HIP events on
  * its stream right before and after its dominant kernel (MAGUS_KERNEL_REPLAY:
  * the chunk kernel of magus_replay; MAGUS_KERNEL_SWEEP: the sweep kernel;
- * MAGUS_KERNEL_SERVE: the serve-step kernel of a server on this context).
+ * MAGUS_KERNEL_SERVE: the serve-step kernel of a server on this context;
+ * MAGUS_KERNEL_PROBE: the kernel of magus_valu_probe).
  * magus_ctx_kernel_time waits for the recorded events, returns the summed
  * elapsed time and the number of launches since its last call, and resets.
  */
 #define MAGUS_KERNEL_REPLAY 0
 #define MAGUS_KERNEL_SWEEP 1
 #define MAGUS_KERNEL_SERVE 2
+#define MAGUS_KERNEL_PROBE 3   /* the VALU issue probe below */
 int magus_ctx_set_profiling(magus_ctx* ctx, int enable);
 int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t* launches);
 
@@ -231,6 +233,22 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 const uint64_t* d_offsets, uint32_t n_traces,
                 const magus_config* h_cfgs, uint32_t n_cfgs,
                 uint64_t* d_scores, uint32_t* d_argmin, hipStream_t stream);
+
+/*
+ * Measurement aid: the VALU issue ceiling of the sweep's instruction mix.
+ * Runs the sweep kernel's per-evaluation step (the Alg. 1 compares of one
+ * config per lane against a step's shared quotients, the event FIFO, Alg. 2
+ * and the decision rule of Sec. 3.2, on wave masks) `steps` times per lane
+ * with its inputs taken from registers, nothing else in the loop, in
+ * `workgroups` workgroups of 256 lanes.  evaluations = workgroups * 256 *
+ * steps; their rate is the ceiling a sweep evaluation can reach on this chip.
+ * With kernel timing on, the launch is timed as MAGUS_KERNEL_PROBE.
+ *   steps      a positive multiple of 4.
+ *   d_out      workgroups * 256 uint32 (written; values have no meaning
+ *              beyond keeping the work alive).
+ */
+int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t* d_out,
+                     hipStream_t stream);
 
 /*
  * Monitor front end (Sec. 3, Sec. 4: memory throughput is read periodically
@@ -334,7 +352,12 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
  *                         (MAGUS_ENOSLOT if none); its state is reset by the
  *                         next magus_serve_step on the server.
  *   magus_stream_close    frees the slot (the slot may be handed out again).
- *   magus_serve_step      one step for n (slot, sample) pairs: h_slots and
+ *   magus_serve_step      one step for n (slot, sample) pairs -- for each
+ *                         pair, one invocation of the controller with the
+ *                         stream's newest sample, as the runtime is invoked
+ *                         once per monitoring interval (Sec. 3.2, Sec. 4):
+ *                         Alg. 1 on the stream's FIFO, the event FIFO and
+ *                         Alg. 2, then the decision rule.  h_slots and
  *                         h_samples are host arrays (copied before return),
  *                         every slot must be open and appear at most once
  *                         (MAGUS_EINVAL otherwise).  Decision bytes for the n

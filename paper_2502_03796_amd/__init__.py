@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmagus.so")
 
 OK, EINVAL, ENOMEM, ENOSLOT, EDEVICE, EDATA = 0, -1, -2, -3, -4, -5
-KERNEL_REPLAY, KERNEL_SWEEP, KERNEL_SERVE = 0, 1, 2
+KERNEL_REPLAY, KERNEL_SWEEP, KERNEL_SERVE, KERNEL_PROBE = 0, 1, 2, 3
 MAX_TRACE_LEN = (1 << 30) - 1
 
 
@@ -118,6 +118,7 @@ SIGNATURES = {
                                     ctypes.c_uint32, _P, _P, _P, _P]),
     "magus_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
                                    ctypes.c_uint32, _P, _P, _P]),
+    "magus_valu_probe": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "magus_counters_to_mbps": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint32,
                                               ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "magus_proxy_model_check": (ctypes.c_int, [ctypes.POINTER(MagusProxyModel)]),
@@ -309,6 +310,17 @@ class Context:
                                             ctypes.byref(n)))
         return ms.value, n.value
 
+    def valu_probe(self, workgroups: int, steps: int, out=None, stream=None):
+        """The VALU issue probe: the sweep's per-evaluation step, `steps` times
+        per lane in `workgroups` workgroups of 256 lanes (see magus.h)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(workgroups * 256, dtype=torch.int32, device=f"cuda:{self.device}")
+        _check(load().magus_valu_probe(self._h, int(workgroups), int(steps),
+                                       _dev_ptr(out, "out", (torch.int32,)),
+                                       _stream_handle(stream, self.device)))
+        return out
+
     def check(self, stream=None) -> None:
         """Synchronize and raise MagusError(EDATA) on a device-side data fault."""
         _check(load().magus_ctx_check(self._h, _stream_handle(stream, self.device)))
@@ -340,11 +352,12 @@ class Context:
         return results, (levels_out if levels else None)
 
     def proxy(self, samples, offsets, cfgs, model, cfg_of_trace=None, metrics: bool = True,
-              stream=None):
+              stream=None, stats=None):
         """Proxy energy / EDP model of MAGUS vs always-max vs always-min per trace.
 
         Returns (stats int64[T, 66], metrics float64[T, 21] or None); decode rows
-        with proxy_stats_dict / proxy_metrics_dict.
+        with proxy_stats_dict / proxy_metrics_dict.  `stats` optionally gives
+        the output tensor for the statistics.
         """
         torch = _torch()
         arr = config_array(cfgs)
@@ -352,8 +365,11 @@ class Context:
         sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
         op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
         n_traces = offsets.numel() - 1
-        st = torch.empty((n_traces, 2 + 2 * PROXY_LEVELS), dtype=torch.int64,
-                         device=samples.device)
+        st = stats if stats is not None else \
+            torch.empty((n_traces, 2 + 2 * PROXY_LEVELS), dtype=torch.int64,
+                        device=samples.device)
+        if tuple(st.shape) != (n_traces, 2 + 2 * PROXY_LEVELS) or not st.is_contiguous():
+            raise ValueError("stats must be a contiguous int64 tensor [n_traces, 66]")
         me = None
         mp = None
         if metrics:

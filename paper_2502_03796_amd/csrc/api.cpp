@@ -282,7 +282,7 @@ int magus_ctx_set_profiling(magus_ctx* ctx, int enable) {
 
 int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t* launches) {
     if (!ctx || !total_ms || !launches) return fail(MAGUS_EINVAL, "NULL argument");
-    if (kernel < 0 || kernel > 2) return fail(MAGUS_EINVAL, "unknown kernel id %d", kernel);
+    if (kernel < 0 || kernel > 3) return fail(MAGUS_EINVAL, "unknown kernel id %d", kernel);
     DeviceGuard g(ctx->device);
     double sum = 0.0;
     uint64_t n = 0;
@@ -816,6 +816,19 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     HIP_TRY(launch_sweep(d_samples, n_samples, d_offsets, n_traces, ctx->plan, n_cfgs, d_scores,
                          d_argmin, ctx->keys.as<uint64_t>(), ctx->err.as<uint32_t>(), stream,
                          tp.first, tp.second));
+    tp.commit();
+    return MAGUS_OK;
+}
+
+int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t* d_out,
+                     hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (workgroups == 0 || steps == 0 || steps % 4 || !d_out)
+        return fail(MAGUS_EINVAL, "need workgroups >= 1, steps a positive multiple of 4, out");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    magus_ctx::Timing tp(ctx, MAGUS_KERNEL_PROBE);
+    HIP_TRY(launch_valu_probe(workgroups, steps, 0x5A17u, d_out, stream, tp.first, tp.second));
     tp.commit();
     return MAGUS_OK;
 }

@@ -94,7 +94,7 @@ struct magus_ctx {
     // kernel timing: event pairs recorded around the dominant kernel of a call
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> recorded[3];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> recorded[4];
 
     // A pair of events to record around one launch of `kernel` (nulls when
     // timing is off).  The pair counts for magus_ctx_kernel_time only once

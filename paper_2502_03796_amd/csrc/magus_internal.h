@@ -207,6 +207,12 @@ hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint6
                         uint64_t* scores, uint32_t* argmin, uint64_t* keys, uint32_t* err,
                         hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 
+// The sweep's per-evaluation step on register data (valu_probe.hip): `steps`
+// steps (a multiple of 4) per lane, workgroups of kSweepLanes lanes, one
+// uint32 per lane written to out.
+hipError_t launch_valu_probe(uint32_t workgroups, uint32_t steps, uint32_t seed, uint32_t* out,
+                             hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
 // Serving slot state.
 struct SlotState {
     uint32_t ring[31];   // last W-1 samples, sample k at ring[k % (W-1)]

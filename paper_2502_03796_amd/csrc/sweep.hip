@@ -14,7 +14,7 @@
 // level and counters in registers across the trace; scores and the per-trace
 // arg-min are reduced at the end.
 
-#include "magus_internal.h"
+#include "sweep_step.h"
 
 namespace magus {
 namespace {
@@ -23,16 +23,6 @@ constexpr int kTile = kSweepLanes;     // steps per LDS tile (one per thread)
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-
-// v + w + this lane's bit of the wave-uniform mask m, as one add with carry-in
-// (the mask is the carry), so a lane-mask bit needs no conversion to 0/1.
-__device__ __forceinline__ uint32_t add_bit(uint32_t v, uint32_t w, uint64_t m) {
-    uint32_t r;
-    uint64_t carry_out;
-    asm("v_addc_co_u32_e64 %0, %1, %2, %3, %4"
-        : "=v"(r), "=s"(carry_out) : "v"(v), "v"(w), "s"(m));
-    return r;
 }
 
 __device__ __forceinline__ uint64_t wave_mask(bool p) { return __ballot(p); }
@@ -158,17 +148,8 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
             // the decisions of all lanes as wave masks (every lane runs
             // every step): the logic is scalar, and each mask bit enters the
             // lane's history and counters as the carry of one add
-            const uint32_t zero = 0;
-            uint64_t lvl_m = wave_mask(lvl);
-            auto one_step = [&](const int2 v) {
-                const uint64_t up = wave_mask(inc < v.x), dn = wave_mask(dec > v.y);
-                hist = add_bit(hist, hist, up | dn) & hmask;
-                const uint64_t high = wave_mask((uint32_t)__popc(hist) >= thr);
-                const uint64_t nl = high | up | (lvl_m & ~dn);
-                trans = add_bit(trans, zero, nl ^ lvl_m);
-                cmax = add_bit(cmax, zero, nl);
-                lvl_m = nl;
-            };
+            MaskLane L{hist, trans, cmax, wave_mask(lvl)};
+            auto one_step = [&](const int2 v) { mask_step(L, v, inc, dec, hmask, thr); };
             uint32_t i = 0;
 #pragma unroll 1
             for (; i + 4 <= nt; i += 4) {
@@ -176,7 +157,10 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
                 for (int k = 0; k < 4; ++k) one_step(q[i + k]);
             }
             for (; i < nt; ++i) one_step(q[i]);
-            lvl = (lvl_m >> (threadIdx.x & 63)) & 1ull;
+            hist = L.hist;
+            trans = L.trans;
+            cmax = L.cmax;
+            lvl = (L.lvl_m >> (threadIdx.x & 63)) & 1ull;
         }
         if (tile0 + kTile < n) prepass(tile0 + kTile, buf ^ 1);
         __syncthreads();

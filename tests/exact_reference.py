@@ -123,3 +123,49 @@ def proxy(trace, cfg, model):
         m["energy_saving"] = [1 - E[p] / E[1] for p in range(3)]
         m["edp_saving"] = [1 - (E[p] * T[p]) / (E[1] * T[1]) for p in range(3)]
     return st, m
+
+
+def run_tree(alphabet, depth, cfg):
+    """Per-step decision bytes of every trace of length `depth` over
+    `alphabet`, in itertools.product order, as a uint8 array [count, depth].
+
+    The controller is causal, so the steps of a trace's prefix are the first
+    steps of the trace; the traces are walked as a tree, level by level, each
+    node one step of ``run``'s loop from its parent's state (same Fraction
+    arithmetic), so every prefix is evaluated once.
+    """
+    import numpy as np
+    inc = Fraction(cfg["inc_q16"], 65536)
+    dec = Fraction(cfg["dec_q16"], 65536)
+    hft = Fraction(cfg["hf_num"], cfg["hf_den"])
+    W, H = cfg["window"], cfg["hold"]
+    up, down = cfg.get("up_step", 0), cfg.get("down_step", 0)
+    which = cfg.get("base", 0)
+    # state: (mem_throughput_ls, uncore_tune_ls, level)
+    states = [((), (0,) * H, cfg["level_init"])]
+    out = np.zeros((len(alphabet) ** depth, depth), np.uint8)
+    for k in range(depth):
+        nxt = []
+        col = []
+        for ls, tune, level in states:
+            for x in alphabet:
+                mem = (ls + (int(x),))[-W:]
+                pred = trend_prediction(inc, dec, list(mem), W, which) if len(mem) == W else 0
+                tune2 = tune[1:] + ((1 if pred != 0 else 0),)
+                high = high_freq_detection(hft, list(tune2))
+                if high:
+                    new = cfg["level_max"]
+                elif pred == 1:
+                    new = cfg["level_max"] if up == 0 else min(level + up, cfg["level_max"])
+                elif pred == -1:
+                    new = cfg["level_min"] if down == 0 else max(level - down, cfg["level_min"])
+                else:
+                    new = level
+                nxt.append((mem, tune2, new))
+                col.append(new | (int(high) << 5) | ((pred + 1) << 6))
+        # node j of this level is the prefix j; its subtree spans
+        # len(alphabet) ** (depth - k - 1) consecutive traces
+        rep = len(alphabet) ** (depth - k - 1)
+        out[:, k] = np.repeat(np.array(col, np.uint8), rep)
+        states = nxt
+    return out

@@ -238,25 +238,29 @@ def test_bulk_workload_full_size_stepped_sampled(ctx, oracle_mod):
 @pytest.mark.parametrize("stepped", [False, True])
 def test_device_data_faults_leave_stats_zero(ctx, stepped):
     """A batch the device-side checks reject (offsets not monotone, a config
-    index out of range) is reported by check() and leaves the statistics zero,
-    on the one-pass path and on the stepped path."""
+    index out of range) is reported by check() and sets every word of the
+    statistics to zero, on the one-pass path and on the stepped path: the
+    output buffer is filled with a non-zero sentinel before each call."""
     import torch
     samples, offsets = synth.make_batch(mixed_traces(1, [100, 100]))
     s, o, _ = to_dev(samples, offsets)
     cfg = default_config(up_step=2, down_step=1) if stepped else default_config()
     model = proxy_model()
+    out = torch.empty((2, 2 + 2 * magus.PROXY_LEVELS), dtype=torch.int64, device="cuda")
     bad = torch.tensor([0, 150, 100], dtype=torch.int64, device="cuda")   # not monotone
-    st, _ = ctx.proxy(s, bad, [cfg], model, metrics=False)
+    out.fill_(0x5A5A5A5A5A5A5A5A)
+    st, _ = ctx.proxy(s, bad, [cfg], model, metrics=False, stats=out)
     with pytest.raises(magus.MagusError) as ei:
         ctx.check()
     assert ei.value.code == magus.EDATA
     assert (st.cpu().numpy() == 0).all()
     cot = torch.tensor([0, 5], dtype=torch.int32, device="cuda")      # index out of range
-    st, _ = ctx.proxy(s, o, [cfg], model, cot, metrics=False)
+    out.fill_(0x5A5A5A5A5A5A5A5A)
+    st, _ = ctx.proxy(s, o, [cfg], model, cot, metrics=False, stats=out)
     with pytest.raises(magus.MagusError):
         ctx.check()
     assert (st.cpu().numpy() == 0).all()
-    st, _ = ctx.proxy(s, o, [cfg], model)
+    out.fill_(0x5A5A5A5A5A5A5A5A)
+    st, _ = ctx.proxy(s, o, [cfg], model, stats=out)
     ctx.check()
     assert st.cpu().numpy()[:, 2:2 + magus.PROXY_LEVELS].sum() == 200
-

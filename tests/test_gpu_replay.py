@@ -65,12 +65,25 @@ def test_pin_traces(ctx, oracle_mod, cfg):
 
 
 def test_brute_force_tiny_traces(ctx, oracle_mod):
-    traces = [np.array(t, np.uint32) for n in range(0, 6)
+    """Every trace over {0..4} of length <= 7 (97,656 traces, one batch), for
+    W in {2,3,4}, H in {1,2,3,5} and 25 threshold pairs with exact-equality
+    cases: results and every decision byte against the oracle."""
+    traces = [np.array(t, np.uint32) for n in range(0, 8)
               for t in itertools.product(range(5), repeat=n)]
-    for W, H, inc, dec in itertools.product((2, 3, 4), (1, 2, 3, 5), (0, 16384, 65536),
-                                            (0, -16384, -32768)):
+    samples, offsets = synth.make_batch(traces)
+    s, o, _ = to_dev(samples, offsets)
+    for W, H, inc, dec in itertools.product((2, 3, 4), (1, 2, 3, 5),
+                                            (0, 1, 16384, 32768, 65536),
+                                            (0, -1, -16384, -32768, -65536)):
         cfg = default_config(window=W, hold=H, inc_q16=inc, dec_q16=dec)
-        run_both(ctx, oracle_mod, traces, [cfg])
+        want_res, want_b = oracle_mod.replay_batch(samples, offsets, [cfg], want_bytes=True)
+        res, lv = ctx.replay(s, o, [cfg], levels=True)
+        ctx.check()
+        got_res = results_np(res)
+        assert (got_res == want_res).all(), (cfg, describe_mismatch(got_res[:, 0],
+                                                                    want_res[:, 0]))
+        got_b = lv.cpu().numpy()
+        assert (got_b == want_b).all(), (cfg, describe_mismatch(got_b, want_b, offsets))
 
 
 def mixed_traces(seed, lengths):
@@ -186,18 +199,25 @@ def test_device_data_faults_are_reported_not_run(ctx):
     ctx.replay(s, o, [default_config()], cfg_of_trace=cot)
     with pytest.raises(magus.MagusError):
         ctx.check()
-    # a trace longer than the maximum (claimed sizes; the kernels read nothing)
+    # a trace one sample longer than the maximum, over a real allocation of
+    # its whole span (4 GiB), so that the device-side gate is the only thing
+    # that keeps the kernels from running it, and a run would stay in bounds
     lib = magus.load()
+    n_big = (1 << 30) + 1
+    big = torch.zeros(n_big, dtype=torch.int32, device="cuda")
     huge = torch.tensor([0, 1 << 30], dtype=torch.int64, device="cuda")
-    res = torch.empty((1, 4), dtype=torch.int64, device="cuda")
+    res = torch.full((1, 4), 7, dtype=torch.int64, device="cuda")
     arr = magus.config_array([default_config()])
-    rc = lib.magus_replay(ctx._h, ctypes.c_void_p(s.data_ptr()), 1 << 31,
+    rc = lib.magus_replay(ctx._h, ctypes.c_void_p(big.data_ptr()), n_big,
                           ctypes.c_void_p(huge.data_ptr()), 1, arr, 1, None,
                           ctypes.c_void_p(res.data_ptr()), None,
                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == 0
     with pytest.raises(magus.MagusError):
         ctx.check()
+    assert (res.cpu().numpy() == 7).all()      # not run: the results are untouched
+    del big
+    torch.cuda.empty_cache()
     ctx.check()                      # cleared
     r, _ = ctx.replay(s, o, [default_config()])
     ctx.check()

@@ -336,6 +336,34 @@ def test_brute_force_against_exact_rational_transliteration(oracle_mod):
     assert checked == len(traces) * 3 * 4 * len(incs) * len(decs)
 
 
+def _tree_bytes(cfg):
+    return ref.run_tree(range(5), 7, cfg)
+
+
+def test_brute_force_length_seven_every_prefix(oracle_mod):
+    """All 78,125 traces over {0..4} of length 7 -- and so, step by step,
+    every trace of length <= 7, the controller being causal -- for W in
+    {2,3,4}, H in {1,2,3,5} and threshold pairs with exact-equality cases,
+    per-step decision bytes against the Fraction transliteration walked as a
+    prefix tree (host processes in parallel)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    traces = np.array(list(itertools.product(range(5), repeat=7)), np.uint32)
+    samples = traces.ravel()
+    offsets = np.arange(0, len(samples) + 1, 7, dtype=np.uint64)
+    pairs = ((0, 0), (1, -1), (16384, -16384), (32768, -32768), (65536, -65536),
+             (0, -65536), (65536, 0), (16384, -32768))
+    cfgs = [default_config(window=W, hold=H, inc_q16=i, dec_q16=d)
+            for W, H, (i, d) in itertools.product((2, 3, 4), (1, 2, 3, 5), pairs)]
+    workers = max(1, min(8, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as pool:
+        for cfg, tree in zip(cfgs, pool.map(_tree_bytes, cfgs)):
+            _, b = oracle_mod.replay_batch(samples, offsets, [cfg], want_bytes=True)
+            b = b.reshape(-1, 7)
+            bad = np.nonzero((b != tree).any(axis=1))[0]
+            assert len(bad) == 0, (cfg, traces[bad[0]].tolist())
+
+
 def test_brute_force_hf_threshold_and_levels(oracle_mod):
     """Other high_freq_threshold fractions and ladders, against the transliteration."""
     traces = [t for t in _brute_traces() if len(t) >= 3]
