@@ -11,8 +11,9 @@ silent.
 Configs are passed as plain dicts with the keys
 ``window, hold, inc_q16, dec_q16, hf_num, hf_den, level_min, level_max,
 level_init`` and optionally ``up_step, down_step`` (steps; 0 = jump to the
-bound) and ``base`` (derivative base: 0 min of the two samples, 1 oldest,
-2 newest) -- integers; thresholds in Q16.16.
+bound), ``base`` (derivative base: 0 min of the two samples, 1 oldest,
+2 newest, 3 the fixed reference) and ``base_ref`` (B_ref in MB/s for base 3)
+-- integers; thresholds in Q16.16.
 """
 from __future__ import annotations
 
@@ -46,7 +47,8 @@ class _Cfg(ctypes.Structure):
                 ("hf_num", ctypes.c_uint32), ("hf_den", ctypes.c_uint32),
                 ("level_min", ctypes.c_uint32), ("level_max", ctypes.c_uint32),
                 ("level_init", ctypes.c_uint32), ("up_step", ctypes.c_uint32),
-                ("down_step", ctypes.c_uint32), ("base", ctypes.c_uint32)]
+                ("down_step", ctypes.c_uint32), ("base", ctypes.c_uint32),
+                ("base_ref", ctypes.c_uint32)]
 
 
 class _Res(ctypes.Structure):
@@ -85,7 +87,7 @@ def _cfg(d: dict) -> _Cfg:
     return _Cfg(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
                 int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
                 int(d["level_max"]), int(d["level_init"]), int(d.get("up_step", 0)),
-                int(d.get("down_step", 0)), int(d.get("base", 0)))
+                int(d.get("down_step", 0)), int(d.get("base", 0)), int(d.get("base_ref", 0)))
 
 
 def _cfg_array(cfgs):

@@ -45,8 +45,13 @@
  *     moves the level by that many rungs, clamped to [level_min, level_max];
  *     0 keeps the jump to the bound.  The high state still goes to the max.
  *   - The derivative's base is a reading as well; besides the default
- *     min(oldest, newest) two alternatives are kept for sensitivity studies:
- *     the oldest sample (r = (b - a) / (W a)) and the newest (W b).
+ *     min(oldest, newest) three alternatives are kept for sensitivity studies:
+ *     the oldest sample (r = (b - a) / (W a)), the newest (W b), and a fixed
+ *     reference B_ref from the config (r = (b - a) / (W B_ref)).  The last is
+ *     the listing's own absolute derivative, (newest - oldest) / direv_length
+ *     in MB/s per step, measured in units of B_ref: an absolute threshold of
+ *     theta MB/s per step is inc = theta / B_ref (B_ref = 1 is the listing's
+ *     formula unscaled).
  *   - Per step the tick is accounted after the decision:
  *       transitions += (new level != old level); level_sum += new level;
  *     score = level_sum + 1000 * transitions.
@@ -76,7 +81,8 @@ int oracle_config_valid(const oracle_config* c)
     if (c->level_min >= c->level_max || c->level_max > 31) return 0;
     if (c->level_init < c->level_min || c->level_init > c->level_max) return 0;
     if (c->up_step > 31 || c->down_step > 31) return 0;
-    if (c->base > 2) return 0;
+    if (c->base > 3) return 0;
+    if (c->base == 3 && c->base_ref < 1) return 0;
     return 1;
 }
 
@@ -86,22 +92,25 @@ int oracle_config_valid(const oracle_config* c)
  * MEM_THROUGHPUT_TREND_PREDICTION (Alg. 1) with the relative derivative and
  * Q16.16 thresholds.  ls holds direv_length samples, ls[0] oldest.
  */
-static int64_t derivative_base(int64_t first, int64_t last, uint32_t which)
+static int64_t derivative_base(int64_t first, int64_t last, uint32_t which, uint32_t ref)
 {
     if (which == 1) return first;
     if (which == 2) return last;
+    if (which == 3) return ref;
     return first < last ? first : last;
 }
 
 static int predict_exact(int32_t inc_q, int32_t dec_q,
-                         const uint32_t* ls, uint32_t direv_length, uint32_t which)
+                         const uint32_t* ls, uint32_t direv_length, uint32_t which,
+                         uint32_t ref)
 {
     int64_t first = ls[0];
     int64_t last = ls[direv_length - 1];
-    int64_t base = derivative_base(first, last, which);
+    int64_t base = derivative_base(first, last, which, ref);
     int64_t delta = last - first;
     /* derivative = delta / (direv_length * base); compare with q / 65536
-       by cross-multiplying with the positive (or zero) denominator.       */
+       by cross-multiplying with the positive (or zero) denominator
+       (|lhs| < 2^49 and |q * den| <= 2^20 * 2^5 * 2^32 = 2^57).           */
     int64_t lhs = delta * 65536;
     int64_t den = (int64_t)direv_length * base;
     if (lhs > (int64_t)inc_q * den) return 1;        /* derivative > inc */
@@ -112,11 +121,13 @@ static int predict_exact(int32_t inc_q, int32_t dec_q,
 /* ------------------------------------------------------ Alg. 1, FP64 form */
 
 static int predict_fp64(double inc_threshold, double dec_threshold,
-                        const uint32_t* ls, uint32_t direv_length, uint32_t which)
+                        const uint32_t* ls, uint32_t direv_length, uint32_t which,
+                        uint32_t ref)
 {
     double first = (double)ls[0];
     double last = (double)ls[direv_length - 1];
-    double base = which == 1 ? first : which == 2 ? last : (first < last ? first : last);
+    double base = which == 1 ? first : which == 2 ? last : which == 3 ? (double)ref
+                : (first < last ? first : last);
     double derivative = (last - first) / ((double)direv_length * base);
     if (derivative > inc_threshold) return 1;
     if (derivative < dec_threshold) return -1;
@@ -168,8 +179,9 @@ static uint8_t controller_step(oracle_state* s, const oracle_config* c, uint32_t
     int pred = 0;
     if (s->filled == W) {
         pred = use_fp64 ? predict_fp64(inc_threshold, dec_threshold, mem_throughput_ls, W,
-                                       c->base)
-                        : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W, c->base);
+                                       c->base, c->base_ref)
+                        : predict_exact(c->inc_q, c->dec_q, mem_throughput_ls, W, c->base,
+                                        c->base_ref);
     }
 
     /* 3. log whether a frequency change would be triggered */

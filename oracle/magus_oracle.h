@@ -22,7 +22,9 @@ typedef struct oracle_config {
     uint32_t up_step;       /* 0: an executed increase goes to level_max;  */
     uint32_t down_step;     /*    else the level moves by this many rungs  */
     uint32_t base;          /* derivative base: 0 min(oldest, newest),     */
-                            /* 1 oldest sample, 2 newest sample            */
+                            /* 1 oldest sample, 2 newest sample,           */
+                            /* 3 the fixed reference base_ref              */
+    uint32_t base_ref;      /* B_ref in MB/s (>= 1) for base 3, else unused */
 } oracle_config;
 
 typedef struct oracle_result {

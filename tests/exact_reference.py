@@ -14,11 +14,11 @@ INF = float("inf")
 
 
 def trend_prediction(inc_threshold, dec_threshold, mem_throughput_ls, direv_length,
-                     which_base=0):
+                     which_base=0, base_ref=0):
     """Alg. 1 with the derivative taken relative to the smaller end sample
-    (or, as alternatives, the oldest or the newest)."""
+    (or, as alternatives, the oldest, the newest, or a fixed reference)."""
     first, last = mem_throughput_ls[0], mem_throughput_ls[-1]
-    base = (min(first, last), first, last)[which_base]
+    base = (min(first, last), first, last, base_ref)[which_base]
     if base == 0:
         if last == first:
             return 0                      # 0/0: no trend
@@ -53,7 +53,8 @@ def run(trace, cfg):
         mem_throughput_ls.append(int(x))
         if len(mem_throughput_ls) > W:
             mem_throughput_ls.pop(0)
-        pred = trend_prediction(inc, dec, mem_throughput_ls, W, cfg.get("base", 0)) \
+        pred = trend_prediction(inc, dec, mem_throughput_ls, W, cfg.get("base", 0),
+                                cfg.get("base_ref", 0)) \
             if len(mem_throughput_ls) == W else 0
         uncore_tune_ls.pop(0)
         uncore_tune_ls.append(1 if pred != 0 else 0)
@@ -140,7 +141,7 @@ def run_tree(alphabet, depth, cfg):
     hft = Fraction(cfg["hf_num"], cfg["hf_den"])
     W, H = cfg["window"], cfg["hold"]
     up, down = cfg.get("up_step", 0), cfg.get("down_step", 0)
-    which = cfg.get("base", 0)
+    which, ref = cfg.get("base", 0), cfg.get("base_ref", 0)
     # state: (mem_throughput_ls, uncore_tune_ls, level)
     states = [((), (0,) * H, cfg["level_init"])]
     out = np.zeros((len(alphabet) ** depth, depth), np.uint8)
@@ -150,7 +151,8 @@ def run_tree(alphabet, depth, cfg):
         for ls, tune, level in states:
             for x in alphabet:
                 mem = (ls + (int(x),))[-W:]
-                pred = trend_prediction(inc, dec, list(mem), W, which) if len(mem) == W else 0
+                pred = trend_prediction(inc, dec, list(mem), W, which, ref) \
+                    if len(mem) == W else 0
                 tune2 = tune[1:] + ((1 if pred != 0 else 0),)
                 high = high_freq_detection(hft, list(tune2))
                 if high:

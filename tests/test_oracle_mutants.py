@@ -28,6 +28,10 @@ MUTANTS = [
      "    return first;"),
     ("base variants swapped", "    if (which == 1) return first;\n    if (which == 2) return last;",
      "    if (which == 1) return last;\n    if (which == 2) return first;"),
+    ("fixed reference replaced by the smaller sample", "    if (which == 3) return ref;",
+     "    if (which == 3) return first < last ? first : last;"),
+    ("fixed reference without the window", "    int64_t den = (int64_t)direv_length * base;",
+     "    int64_t den = which == 3 ? base : (int64_t)direv_length * base;"),
     ("front end ignores the counter wrap",
      "        if (counter_bits < 64) delta &= (((unsigned __int128)1) << counter_bits) - 1;\n"
      "        else delta &= (unsigned __int128)UINT64_MAX;",
@@ -99,6 +103,8 @@ def _checks():
         lambda: pins.test_counters_wrap_zero_interval_and_saturation(om),
         lambda: pins.test_counters_against_exact_rationals(om),
         lambda: pins.test_brute_force_base_variants(om),
+        lambda: pins.test_fixed_reference_closed_form(om),
+        lambda: pins.test_fixed_reference_is_not_scale_invariant(om),
         lambda: pins.test_brute_force_against_exact_rational_transliteration(om),
     ]
 

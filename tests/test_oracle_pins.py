@@ -503,6 +503,103 @@ def test_brute_force_base_variants(oracle_mod):
                 assert b.tobytes() == ref.encode(steps), (which, W, inc, dec, t)
 
 
+# ------------------------------------------- fixed reference base (base 3)
+
+def test_fixed_reference_closed_form(oracle_mod):
+    """Base 3: r = (b - a) / (W B_ref).  With W = 4, B_ref = 10,000 and
+    inc = dec magnitude = 6554/2^16, a step of size D fires iff
+    D 2^16 > 6554 * 4 * 10,000 = 262,160,000, i.e. iff D >= 4001
+    (4001 * 65536 = 262,209,536; 4000 * 65536 = 262,144,000), whatever the
+    level it starts from.  A clean step up at s = 40 of n = 100 then gives
+    W-1 steps of +1 from s, score 16 (n - s) + 1000 = 1960."""
+    cfg = default_config(base=3, base_ref=10000)
+    for lo in (0, 10000, 300000, 2**32 - 4002):
+        res, lv, hi, pr = run(oracle_mod, [lo] * 40 + [lo + 4001] * 60, cfg)
+        assert (pr[40:43] == 1).all() and (pr[:40] == 0).all() and (pr[43:] == 0).all(), lo
+        assert res["score"] == 1960 and res["transitions"] == 1, lo
+        res, _, _, pr = run(oracle_mod, [lo] * 40 + [lo + 4000] * 60, cfg)
+        assert res["score"] == 0 and (pr == 0).all(), lo
+        # the same step down goes to the minimum from level_init = 16
+        res, lv, _, pr = run(oracle_mod, [lo + 4001] * 40 + [lo] * 60,
+                             default_config(base=3, base_ref=10000, level_init=16))
+        assert (pr[40:43] == -1).all() and (lv[:40] == 16).all() and (lv[40:] == 0).all(), lo
+        res, lv, _, pr = run(oracle_mod, [lo + 4000] * 40 + [lo] * 60,
+                             default_config(base=3, base_ref=10000, level_init=16))
+        assert (pr == 0).all() and (lv == 16).all(), lo
+
+
+def test_fixed_reference_one_is_the_listings_absolute_derivative(oracle_mod):
+    """B_ref = 1 makes r = (newest - oldest) / direv_length, Alg. 1's own
+    formula in MB/s per step.  Against that formula evaluated directly with
+    exact rationals on random steps (thresholds q/2^16 up to the 2^20 = 16
+    MB/s per step the config allows)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(31)
+    for _ in range(300):
+        W = int(rng.integers(2, 33))
+        q = int(rng.integers(0, 2**20 + 1))
+        a = int(rng.integers(0, 2**32 - 1000))
+        d = int(rng.integers(0, 600))
+        cfg = default_config(window=W, hold=1, inc_q16=q, dec_q16=-q, base=3, base_ref=1)
+        for x in ([a] * W + [a + d] * W, [a + d] * W + [a] * W):
+            _, _, _, pr = run(oracle_mod, x, cfg)
+            for t in range(W - 1, len(x)):
+                derivative = Fraction(x[t] - x[t - W + 1], W)
+                want = 1 if derivative > Fraction(q, 65536) else \
+                    -1 if derivative < Fraction(-q, 65536) else 0
+                assert pr[t] == want, (W, q, a, d, t)
+
+
+def test_fixed_reference_is_not_scale_invariant(oracle_mod):
+    """Unlike the relative bases, scaling the samples changes base 3's
+    decisions: the 4,001 MB/s step fires at B_ref = 10,000, half of it does
+    not (while the min base gives the same bytes for both)."""
+    x = np.array([10000] * 40 + [14002] * 60, np.uint64)
+    c3 = default_config(base=3, base_ref=10000)
+    r1, _ = oracle_mod.replay_trace(x.astype(np.uint32), c3)
+    r2, _ = oracle_mod.replay_trace((x // 2).astype(np.uint32), c3)
+    assert r1["transitions"] == 1 and r2["transitions"] == 0
+    c0 = default_config(base=0)
+    _, b1 = oracle_mod.replay_trace(x.astype(np.uint32), c0)
+    _, b2 = oracle_mod.replay_trace((x // 2).astype(np.uint32), c0)
+    assert (b1 == b2).all()
+
+
+def test_fixed_reference_q16_and_fp64_disagree_at_the_boundary(oracle_mod):
+    """W = 4, B_ref = 100,000: the step 40,001 gives r = 0.1000025, above the
+    decimal 0.1 (the FP64 side-form fires) but not above 6554/2^16 =
+    0.100006103515625 (the exact form does not); 40,003 fires in both."""
+    cfg = default_config(base=3, base_ref=100000)
+    for d, exact, fp in ((40001, 0, 1), (40002, 0, 1), (40003, 1, 1)):
+        x = np.array([50000] * 10 + [50000 + d] * 10, np.uint32)
+        _, be = oracle_mod.replay_trace(x, cfg)
+        _, bf = oracle_mod.replay_trace_fp64(x, cfg, 0.1, -0.1)
+        assert int(((be >> 6) == 2).any()) == exact, d
+        assert int(((bf >> 6) == 2).any()) == fp, d
+
+
+def test_fixed_reference_validation(oracle_mod):
+    assert oracle_mod.config_valid(default_config(base=3, base_ref=1))
+    assert not oracle_mod.config_valid(default_config(base=3, base_ref=0))
+    assert not oracle_mod.config_valid(default_config(base=4, base_ref=1))
+
+
+def test_brute_force_fixed_reference(oracle_mod):
+    """Base 3 against the Fraction transliteration on every trace over {0..4}
+    of length <= 5, B_ref in {1, 2, 3}: equality cases included (W = 4,
+    B_ref = 1, a step of 1 gives r = 1/4 = 16384/2^16, no event)."""
+    traces = [t for n in range(1, 6) for t in itertools.product(range(5), repeat=n)]
+    for bref in (1, 2, 3):
+        for W, inc, dec in itertools.product((2, 3, 4), (0, 16384, 32768), (0, -16384)):
+            cfg = default_config(window=W, hold=3, inc_q16=inc, dec_q16=dec, base=3,
+                                 base_ref=bref)
+            for t in traces[::3]:
+                steps, score, *_ = ref.run(t, cfg)
+                r, b = oracle_mod.replay_trace(np.array(t, np.uint32), cfg)
+                assert b.tobytes() == ref.encode(steps), (bref, W, inc, dec, t)
+                assert r["score"] == score
+
+
 # ---------------------------------------------------------------- monitor front end
 
 def test_counters_constant_rate(oracle_mod):
