@@ -23,12 +23,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# int32 VALU issue peak: 256 CUs x 64 lanes per clock x 2.4 GHz
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# int32 VALU peak in lane-ops/s: 256 CUs x 128 lanes per clock x 2.4 GHz.
+# The chip's published fp32 vector peak, 157.3 TFLOP/s, is 2 flops per FMA
+# lane-op: 157.3e12 / 2 / (256 x 2.4e9) = 128 lanes per clock per CU, i.e.
+# two wave64 instructions per clock per CU; a full-rate 32-bit integer
+# instruction takes the same lane slot as an FMA.
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
+# algorithmic VALU lane-ops per (sample, config) evaluation of the sweep:
+# 2 compares, a select, a shift-or, an and, a popcount, a compare, 2 selects,
+# a compare, an add-with-carry and an add
+SWEEP_OPS_PER_EVAL = 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chunk_kernel_bulk_traffic.json")
 SWEEP_COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_sweep_counters.json")
-# sources of the sweep kernel and of the VALU probe (the counters are keyed to them)
-SWEEP_SOURCES = ("sweep.hip", "sweep_step.h", "valu_probe.hip", "magus_internal.h")
+# sources of the sweep kernel (its counters are keyed to them)
+SWEEP_SOURCES = ("sweep.hip", "sweep_step.h", "magus_internal.h")
 
 
 def log(*a):
@@ -75,28 +83,28 @@ def host_threads():
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
-def valu_probe(magus, ctx, dev, n_work=1024, blocks=64, steps=5000, reps=3):
-    """Times magus_valu_probe: `n_work * blocks` workgroups of 256 lanes, each
-    lane running the sweep's per-evaluation step `steps` times."""
+def valu_probe(magus, ctx, dev, workgroups=65536, steps=2000, reps=3):
+    """Times magus_valu_probe in both modes (independent v_add_u32 chains; the
+    sweep step's compare / add-with-carry / and / popcount opcodes) at the
+    sweep's launch size: lane-ops per second and wave instructions per clock
+    per compute unit at 2.4 GHz."""
     import torch
-    wg = n_work * blocks
-    out = torch.empty(wg * 256, dtype=torch.int32, device=dev)
-    ctx.valu_probe(wg, steps, out)
-    torch.cuda.synchronize()
-    ctx.set_profiling(True)
-    ctx.kernel_time(magus.KERNEL_PROBE)
-    for _ in range(reps):
-        ctx.valu_probe(wg, steps, out)
-    torch.cuda.synchronize()
-    ctx.set_profiling(False)
-    ms, n = ctx.kernel_time(magus.KERNEL_PROBE)
-    evals = float(wg) * 256 * steps
-    r = {"workgroups": wg, "steps": steps, "kernel_ms": ms / n,
-         "evals_per_s": evals / (ms / n * 1e-3)}
-    cnt = stored_sweep_counters()
-    if cnt and cnt.get("probe_valu_insts_per_launch") and cnt.get("probe_evals_per_launch"):
-        r["valu_insts_per_eval"] = cnt["probe_valu_insts_per_launch"] * 64 / \
-            cnt["probe_evals_per_launch"]
+    out = torch.empty(workgroups * 256, dtype=torch.int32, device=dev)
+    r = {"workgroups": workgroups, "steps": steps}
+    for mode, name in ((0, "v_add_u32"), (1, "sweep_opcodes")):
+        _, ops = ctx.valu_probe(workgroups, steps, mode, out)
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        ctx.kernel_time(magus.KERNEL_PROBE)
+        for _ in range(reps):
+            ctx.valu_probe(workgroups, steps, mode, out)
+        torch.cuda.synchronize()
+        ctx.set_profiling(False)
+        ms, n = ctx.kernel_time(magus.KERNEL_PROBE)
+        rate = ops / (ms / n * 1e-3)
+        r[name] = {"kernel_ms": ms / n, "lane_ops_per_s": rate,
+                   "frac_of_peak": rate / VALU_PEAK_OPS,
+                   "wave_insts_per_clk_per_cu": rate / 64 / (256 * 2.4e9)}
     del out
     return r
 
@@ -136,35 +144,34 @@ def bench_sweep(magus, synth, ctx, dev, checks=None, cpu=None):
     kern_s = kms / kn * 1e-3
     res = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
            "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3, "kernel_ms": kern_s * 1e3,
-           # lane-ops per evaluation the VALU could issue at peak in this time
-           "valu_lane_ops_per_eval_at_peak": VALU_PEAK_OPS * kern_s / evals,
            "parity": "not checked (--no-cpu)"}
+    log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
+    # ALU roofline: algorithmic int32 lane-ops per evaluation x evaluations /
+    # the kernel's time, against the chip's int32 VALU lane-op peak
+    achieved = SWEEP_OPS_PER_EVAL * evals / kern_s
+    res["roofline"] = {
+        "bound": "alu", "kernel": "sweep_kernel", "achieved": achieved,
+        "peak": VALU_PEAK_OPS, "unit": "int32 lane-ops/s", "frac": achieved / VALU_PEAK_OPS,
+        "algorithmic_ops_per_eval": SWEEP_OPS_PER_EVAL,
+        "peak_source": "256 CUs x 128 int32 lanes per clock x 2.4 GHz (the lane rate of the "
+                       "published 157.3 TFLOP/s fp32 vector peak, 2 flops per FMA)"}
     cnt = stored_sweep_counters()
     if cnt:
-        # wave instructions issued / (kernel time x 1 wave-instruction per
-        # clock per compute unit x 256 compute units x 2.4 GHz)
-        res["valu_issue_frac"] = cnt["valu_insts_per_launch"] / (kern_s * 256 * 2.4e9)
-        res["valu_lane_ops_per_eval"] = cnt["valu_insts_per_launch"] * 64 / evals
-    log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
-    # the VALU ceiling of the sweep's per-evaluation step: the same step on
-    # register data (no LDS tiles, no pre-pass, no barriers) in as many
-    # workgroups as the sweep launches, timed the same way
-    probe = valu_probe(magus, ctx, dev, n_work=len(soff) - 1, blocks=64)
-    res["roofline"] = {
-        "bound": "valu", "kernel": "sweep_kernel",
-        "achieved": evals / kern_s, "peak": probe["evals_per_s"], "unit": "evals/s",
-        "frac": evals / kern_s / probe["evals_per_s"],
-        "peak_source": "valu_probe_kernel: the sweep's per-evaluation step (mask_step) on "
-                       "register data, 65,536 workgroups of 256 lanes, timed in this run",
-        "probe": probe}
-    if cnt and probe.get("valu_insts_per_eval"):
-        # issue rates in wave instructions per clock per compute unit at 2.4 GHz
-        res["roofline"]["valu_issue_per_clk_per_cu"] = {
-            "sweep": res["valu_issue_frac"],
-            "probe": probe["valu_insts_per_eval"] / 64 * probe["evals_per_s"] /
-            (256 * 2.4e9)}
-    log(f"  VALU probe {probe['evals_per_s']:.3e} evals/s: sweep at "
-        f"{res['roofline']['frac']:.1%} of the probe's rate")
+        # the instructions the kernel really issues (rocprofv3 SQ_INSTS_VALU,
+        # wave instructions per launch, taken on the current kernel source)
+        issued = cnt["valu_insts_per_launch"] * 64 / kern_s
+        res["roofline"]["issued"] = {
+            "lane_ops_per_eval": cnt["valu_insts_per_launch"] * 64 / evals,
+            "lane_ops_per_s": issued, "frac_of_peak": issued / VALU_PEAK_OPS,
+            "wave_insts_per_clk_per_cu": issued / 64 / (256 * 2.4e9)}
+    # the issue rate the chip sustains for plain independent instruction
+    # streams of the same kind, at the sweep's launch size
+    probe = valu_probe(magus, ctx, dev, workgroups=64 * (len(soff) - 1))
+    res["roofline"]["probe"] = probe
+    log(f"  sweep at {res['roofline']['frac']:.1%} of the int32 VALU peak "
+        f"({SWEEP_OPS_PER_EVAL} lane-ops per evaluation); probe: v_add_u32 "
+        f"{probe['v_add_u32']['frac_of_peak']:.1%}, sweep opcodes "
+        f"{probe['sweep_opcodes']['frac_of_peak']:.1%} of the peak")
     traces = {t: ssmp[int(soff[t]):int(soff[t + 1])].copy() for t in pick}
 
     def check_sweep(oracle):
@@ -532,7 +539,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="time-chunk length (0: default)")
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches")
     ap.add_argument("--valu-probe", action="store_true",
-                    help="only run the VALU issue probe at the sweep's launch size")
+                    help="only run the VALU issue-rate probe at the sweep's launch size")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only run the configuration sweep and print its figures")
     ap.add_argument("--only", choices=["stepped", "proxy", "serve", "uneven"],
@@ -692,16 +699,22 @@ def main():
         extra = {}
         # FP64 side-form vs the exact Q16.16 form (an oracle-only study)
         def check_fp64(oracle):
-            dp = dl = tot = 0
-            for t in range(0, args.traces, max(1, args.traces // 32)):
-                x = samples[int(offsets[t]):int(offsets[t + 1])]
-                _, be = oracle.replay_trace(x, cfg)
-                _, bf = oracle.replay_trace_fp64(x, cfg, 0.1, -0.1)
-                dp += int(((be >> 6) != (bf >> 6)).sum())
-                dl += int(((be & 31) != (bf & 31)).sum())
-                tot += len(x)
-            extra["fp64_side_form"] = {"pred_disagreement_rate": dp / tot,
-                                       "level_disagreement_rate": dl / tot, "steps": tot}
+            def rates(c):
+                dp = dl = tot = 0
+                for t in range(0, args.traces, max(1, args.traces // 32)):
+                    x = samples[int(offsets[t]):int(offsets[t + 1])]
+                    _, be = oracle.replay_trace(x, c)
+                    _, bf = oracle.replay_trace_fp64(x, c, 0.1, -0.1)
+                    dp += int(((be >> 6) != (bf >> 6)).sum())
+                    dl += int(((be & 31) != (bf & 31)).sum())
+                    tot += len(x)
+                return {"pred_disagreement_rate": dp / tot,
+                        "level_disagreement_rate": dl / tot, "steps": tot}
+            extra["fp64_side_form"] = rates(cfg)
+            # the fixed-reference base at the bulk traces' median level:
+            # thresholds +-0.1 mean +-2,000 MB/s per step over the window
+            fixed = synth.default_config(base=3, base_ref=20000)
+            extra["fp64_side_form"]["fixed_reference_20000"] = rates(fixed)
         checks.append(check_fp64)
 
         # context for the roofline: plain torch kernels over the same bytes (a

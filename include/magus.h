@@ -76,8 +76,13 @@ extern "C" {
  *               decrease", Sec. 2).  The high state always goes to level_max.
  *   base        derivative base: 0 = min(oldest, newest) (the default reading:
  *               symmetric for rises and falls), 1 = the oldest sample, 2 = the
- *               newest sample (alternative readings of Alg. 1 kept for
- *               sensitivity sweeps).
+ *               newest sample, 3 = the fixed reference base_ref (alternative
+ *               readings of Alg. 1 kept for sensitivity sweeps).
+ *   base_ref    B_ref in MB/s, >= 1, for base 3 (ignored otherwise): the
+ *               derivative is (x[t] - x[t-W+1]) / (W * B_ref), which is
+ *               Alg. 1's own absolute derivative (newest - oldest) /
+ *               direv_length in units of B_ref MB/s per step; an absolute
+ *               threshold of theta MB/s per step is inc = theta / B_ref.
  */
 typedef struct magus_config {
     uint16_t window;
@@ -89,6 +94,7 @@ typedef struct magus_config {
     uint8_t level_init;
     uint8_t up_step, down_step;
     uint8_t base;
+    uint32_t base_ref;
 } magus_config;
 
 /* Per-trace replay result. */
@@ -235,20 +241,24 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 uint64_t* d_scores, uint32_t* d_argmin, hipStream_t stream);
 
 /*
- * Measurement aid: the VALU issue ceiling of the sweep's instruction mix.
- * Runs the sweep kernel's per-evaluation step (the Alg. 1 compares of one
- * config per lane against a step's shared quotients, the event FIFO, Alg. 2
- * and the decision rule of Sec. 3.2, on wave masks) `steps` times per lane
- * with its inputs taken from registers, nothing else in the loop, in
- * `workgroups` workgroups of 256 lanes.  evaluations = workgroups * 256 *
- * steps; their rate is the ceiling a sweep evaluation can reach on this chip.
- * With kernel timing on, the launch is timed as MAGUS_KERNEL_PROBE.
+ * Measurement aid: the issue rate of 32-bit integer VALU instructions.  Every
+ * lane of `workgroups` workgroups of 256 lanes runs `steps` rounds of 8
+ * independent dependency chains, with nothing else in the loop (no memory,
+ * no LDS, no barriers):
+ *   mode 0  one v_add_u32 per chain and round (8 lane-ops per round);
+ *   mode 1  the opcodes of the sweep's per-evaluation step, one each per
+ *           chain and round: compare into a wave mask, add with that mask as
+ *           carry-in, and, population count (32 lane-ops per round).
+ * *h_lane_ops (optional) receives the lane-ops the launch issues; divided by
+ * the kernel time it is the rate the chip sustains for that mix, the issue
+ * ceiling the sweep kernel's instruction stream is compared with.  With
+ * kernel timing on, the launch is timed as MAGUS_KERNEL_PROBE.
  *   steps      a positive multiple of 4.
  *   d_out      workgroups * 256 uint32 (written; values have no meaning
  *              beyond keeping the work alive).
  */
-int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t* d_out,
-                     hipStream_t stream);
+int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t mode,
+                     uint32_t* d_out, uint64_t* h_lane_ops, hipStream_t stream);
 
 /*
  * Monitor front end (Sec. 3, Sec. 4: memory throughput is read periodically

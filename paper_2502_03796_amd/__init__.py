@@ -8,7 +8,7 @@ built, every entry point raises.
 
 Configs are dicts with the keys ``window, hold, inc_q16, dec_q16, hf_num,
 hf_den, level_min, level_max, level_init`` and optionally ``up_step,
-down_step, base`` (see ``include/magus.h`` for meaning and ranges).
+down_step, base, base_ref`` (see ``include/magus.h`` for meaning and ranges).
 """
 from __future__ import annotations
 
@@ -37,7 +37,8 @@ class MagusConfig(ctypes.Structure):
                 ("hf_num", ctypes.c_uint8), ("hf_den", ctypes.c_uint8),
                 ("level_min", ctypes.c_uint8), ("level_max", ctypes.c_uint8),
                 ("level_init", ctypes.c_uint8), ("up_step", ctypes.c_uint8),
-                ("down_step", ctypes.c_uint8), ("base", ctypes.c_uint8)]
+                ("down_step", ctypes.c_uint8), ("base", ctypes.c_uint8),
+                ("base_ref", ctypes.c_uint32)]
 
 
 class MagusResult(ctypes.Structure):
@@ -87,7 +88,7 @@ EV_SAMPLE, EV_JOIN, EV_LEAVE = 0, 1, 2
 EVENT_DTYPE = np.dtype([("t_ns", "<u8"), ("kind", "<u4"), ("stream", "<u4"),
                         ("value", "<u4"), ("reserved", "<u4")])
 
-assert ctypes.sizeof(MagusConfig) == 20 and ctypes.sizeof(MagusResult) == 32
+assert ctypes.sizeof(MagusConfig) == 24 and ctypes.sizeof(MagusResult) == 32
 assert ctypes.sizeof(MagusProxyModel) == 272 and ctypes.sizeof(MagusProxyStats) == 528
 assert ctypes.sizeof(MagusProxyMetrics) == 168
 assert EVENT_DTYPE.itemsize == 24
@@ -118,7 +119,8 @@ SIGNATURES = {
                                     ctypes.c_uint32, _P, _P, _P, _P]),
     "magus_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
                                    ctypes.c_uint32, _P, _P, _P]),
-    "magus_valu_probe": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
+    "magus_valu_probe": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                        _P, ctypes.POINTER(ctypes.c_uint64), _P]),
     "magus_counters_to_mbps": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint32,
                                               ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "magus_proxy_model_check": (ctypes.c_int, [ctypes.POINTER(MagusProxyModel)]),
@@ -166,7 +168,8 @@ def make_config(d: dict) -> MagusConfig:
     return MagusConfig(int(d["window"]), int(d["hold"]), int(d["inc_q16"]), int(d["dec_q16"]),
                        int(d["hf_num"]), int(d["hf_den"]), int(d["level_min"]),
                        int(d["level_max"]), int(d["level_init"]), int(d.get("up_step", 0)),
-                       int(d.get("down_step", 0)), int(d.get("base", 0)))
+                       int(d.get("down_step", 0)), int(d.get("base", 0)),
+                       int(d.get("base_ref", 0)))
 
 
 def config_array(cfgs) -> ctypes.Array:
@@ -310,16 +313,18 @@ class Context:
                                             ctypes.byref(n)))
         return ms.value, n.value
 
-    def valu_probe(self, workgroups: int, steps: int, out=None, stream=None):
-        """The VALU issue probe: the sweep's per-evaluation step, `steps` times
-        per lane in `workgroups` workgroups of 256 lanes (see magus.h)."""
+    def valu_probe(self, workgroups: int, steps: int, mode: int = 1, out=None, stream=None):
+        """The VALU issue-rate probe (see magus.h): `steps` rounds of 8
+        independent instruction chains per lane in `workgroups` workgroups of
+        256 lanes.  Returns (out, lane-ops issued by the launch)."""
         torch = _torch()
         if out is None:
             out = torch.empty(workgroups * 256, dtype=torch.int32, device=f"cuda:{self.device}")
-        _check(load().magus_valu_probe(self._h, int(workgroups), int(steps),
-                                       _dev_ptr(out, "out", (torch.int32,)),
+        ops = ctypes.c_uint64()
+        _check(load().magus_valu_probe(self._h, int(workgroups), int(steps), int(mode),
+                                       _dev_ptr(out, "out", (torch.int32,)), ctypes.byref(ops),
                                        _stream_handle(stream, self.device)))
-        return out
+        return out, ops.value
 
     def check(self, stream=None) -> None:
         """Synchronize and raise MagusError(EDATA) on a device-side data fault."""

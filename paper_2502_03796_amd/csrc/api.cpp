@@ -49,13 +49,15 @@ int derive(const magus_config* c, DevCfg* d) {
     if (c->up_step > 31 || c->down_step > 31)
         return fail(MAGUS_EINVAL, "step sizes must be 0..31 (got %u, %u)",
                     (unsigned)c->up_step, (unsigned)c->down_step);
-    if (c->base > 2) return fail(MAGUS_EINVAL, "base %u is not 0, 1 or 2", (unsigned)c->base);
+    if (c->base > 3) return fail(MAGUS_EINVAL, "base %u is not 0..3", (unsigned)c->base);
+    if (c->base == 3 && c->base_ref == 0)
+        return fail(MAGUS_EINVAL, "base 3 (fixed reference) needs base_ref >= 1");
     d->W = c->window;
     d->H = c->hold;
     d->mu = (uint32_t)c->window * (uint32_t)c->inc_q16;
     d->md = (uint32_t)c->window * (uint32_t)(-c->dec_q16);
-    d->inc_q = c->inc_q16;
-    d->dec_q = c->dec_q16;
+    d->ref = c->base == 3 ? c->base_ref : 0u;
+    d->pad = 0;
     d->thr = (uint16_t)(((uint32_t)c->hf_num * c->hold + c->hf_den - 1) / c->hf_den);
     d->up = c->up_step;
     d->down = c->down_step;
@@ -739,22 +741,26 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         // Group configs by window into blocks of kSweepLanes lanes.
         std::vector<uint32_t> order(n_cfgs);
         for (uint32_t i = 0; i < n_cfgs; ++i) order[i] = i;
-        auto wkey = [&](uint32_t i) { return tab[i].W | ((uint32_t)tab[i].base << 8); };
+        // blocks share the window, the base and (base 3) the reference
+        auto wkey = [&](uint32_t i) {
+            return (uint64_t)tab[i].ref << 32 | tab[i].W | ((uint32_t)tab[i].base << 8);
+        };
         std::stable_sort(order.begin(), order.end(),
                          [&](uint32_t a, uint32_t b) { return wkey(a) < wkey(b); });
-        std::vector<uint32_t> bw;
+        std::vector<uint32_t> bw, bref;
         std::vector<int32_t> inc, dec;
         std::vector<uint32_t> hmask, thr, lv, orig, steps, bstep;
         size_t i = 0;
         while (i < order.size()) {
-            const uint32_t W = wkey(order[i]);
-            bw.push_back(W);
+            const uint64_t W = wkey(order[i]);
+            bw.push_back((uint32_t)W);
+            bref.push_back((uint32_t)(W >> 32));
             uint32_t any_step = 0;
             for (int l = 0; l < kSweepLanes; ++l) {
                 if (i < order.size() && wkey(order[i]) == W) {
                     const DevCfg& d = tab[order[i]];
-                    inc.push_back(d.inc_q);
-                    dec.push_back(d.dec_q);
+                    inc.push_back(h_cfgs[order[i]].inc_q16);
+                    dec.push_back(h_cfgs[order[i]].dec_q16);
                     hmask.push_back(d.H >= 32 ? 0xFFFFFFFFu : ((1u << d.H) - 1u));
                     thr.push_back(d.thr);
                     lv.push_back(d.lmin | (d.lmax << 8) | (d.linit << 16));
@@ -778,7 +784,7 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         if ((uint64_t)nb * n_traces >= (1ull << 31))
             return fail(MAGUS_EINVAL, "traces x config blocks too large for one call");
         const size_t nl = (size_t)nb * kSweepLanes;
-        const size_t bytes = nb * 4 * 2 + nl * 4 * 7 + 9 * 256;
+        const size_t bytes = nb * 4 * 3 + nl * 4 * 7 + 10 * 256;
         int rc;
         if ((rc = ctx->sweep_tab.ensure(bytes))) return rc;
         std::vector<uint8_t> host(bytes, 0);
@@ -789,7 +795,7 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
             off += (n + 255) & ~(size_t)255;
             return at;
         };
-        size_t o_bw = put(bw.data(), nb * 4), o_inc = put(inc.data(), nl * 4),
+        size_t o_bw = put(bw.data(), nb * 4), o_bref = put(bref.data(), nb * 4), o_inc = put(inc.data(), nl * 4),
                o_dec = put(dec.data(), nl * 4), o_hm = put(hmask.data(), nl * 4),
                o_thr = put(thr.data(), nl * 4), o_lv = put(lv.data(), nl * 4),
                o_orig = put(orig.data(), nl * 4), o_steps = put(steps.data(), nl * 4),
@@ -798,6 +804,7 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         char* base = ctx->sweep_tab.as<char>();
         ctx->plan.n_blocks = nb;
         ctx->plan.block_w = reinterpret_cast<const uint32_t*>(base + o_bw);
+        ctx->plan.block_ref = reinterpret_cast<const uint32_t*>(base + o_bref);
         ctx->plan.lane_inc = reinterpret_cast<const int32_t*>(base + o_inc);
         ctx->plan.lane_dec = reinterpret_cast<const int32_t*>(base + o_dec);
         ctx->plan.lane_hmask = reinterpret_cast<const uint32_t*>(base + o_hm);
@@ -820,15 +827,19 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     return MAGUS_OK;
 }
 
-int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t* d_out,
-                     hipStream_t stream) {
+int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t mode,
+                     uint32_t* d_out, uint64_t* h_lane_ops, hipStream_t stream) {
     if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
-    if (workgroups == 0 || steps == 0 || steps % 4 || !d_out)
-        return fail(MAGUS_EINVAL, "need workgroups >= 1, steps a positive multiple of 4, out");
+    if (workgroups == 0 || steps == 0 || steps % 4 || mode > 1 || !d_out)
+        return fail(MAGUS_EINVAL,
+                    "need workgroups >= 1, steps a positive multiple of 4, mode 0 or 1, out");
+    if (h_lane_ops)
+        *h_lane_ops = (uint64_t)workgroups * kSweepLanes * steps * valu_probe_ops_per_step(mode);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
     magus_ctx::Timing tp(ctx, MAGUS_KERNEL_PROBE);
-    HIP_TRY(launch_valu_probe(workgroups, steps, 0x5A17u, d_out, stream, tp.first, tp.second));
+    HIP_TRY(launch_valu_probe(workgroups, steps, mode, 0x5A17u, d_out, stream, tp.first,
+                              tp.second));
     tp.commit();
     return MAGUS_OK;
 }

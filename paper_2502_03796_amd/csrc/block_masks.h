@@ -80,7 +80,7 @@ __device__ __forceinline__ BlockMasks block_masks(uint32_t a, uint32_t b, uint32
     } else {
         const bool rising = b > a;
         const uint32_t d = max(a, b) - min(a, b);
-        const uint32_t lov = derivative_base(a, b, c.base);
+        const uint32_t lov = derivative_base(a, b, c.base, c.ref);
         const uint32_t m = rising ? c.mu : c.md;
         // r = d / (W base) beyond q / 2^16  <=>  d 2^16 > base (W q)
         r.E = lane_ballot(((uint64_t)d << 16) > (uint64_t)lov * m) & vm;

@@ -19,22 +19,26 @@ struct DevCfg {
     uint32_t H;          // event FIFO length
     uint32_t mu;         // W * inc_q16    (E1': (hi-lo) * 2^16 > lo * mu -> +1)
     uint32_t md;         // W * |dec_q16|  (E1': (hi-lo) * 2^16 > lo * md -> -1)
-    int32_t inc_q;       // inc_q16 (sweep quotient form)
-    int32_t dec_q;       // dec_q16
+    uint32_t ref;        // B_ref of the fixed-reference base (base 3), else 0
+    uint32_t pad;
     uint16_t thr;        // ceil(hf_num * H / hf_den): high iff events >= thr
     uint8_t up, down;    // step sizes of an executed +1 / -1 (0 = to the bound)
     uint8_t lmin, lmax, linit;
-    uint8_t base;        // derivative base: 0 min(oldest, newest), 1 oldest, 2 newest
+    uint8_t base;        // derivative base: 0 min(oldest, newest), 1 oldest, 2 newest,
+                         // 3 the fixed reference `ref`
 };
 static_assert(sizeof(DevCfg) == 32, "DevCfg layout");
 
-// Base of the relative derivative of Alg. 1 for one step: the smaller of the
-// two samples, or (alternative readings) the oldest or the newest.
-__device__ __forceinline__ uint32_t derivative_base(uint32_t a, uint32_t b, uint32_t base) {
+// Base of the derivative of Alg. 1 for one step: the smaller of the two
+// samples, or (alternative readings) the oldest, the newest, or the fixed
+// reference `ref` (base 3).
+__device__ __forceinline__ uint32_t derivative_base(uint32_t a, uint32_t b, uint32_t base,
+                                                    uint32_t ref) {
     // masking the excluded sample to all-ones turns min() into a selection
-    const uint32_t mo = base == 2 ? 0xFFFFFFFFu : 0u;
-    const uint32_t mn = base == 1 ? 0xFFFFFFFFu : 0u;
-    return min(a | mo, b | mn);
+    const uint32_t mo = base >= 2 ? 0xFFFFFFFFu : 0u;
+    const uint32_t mn = base == 1 || base == 3 ? 0xFFFFFFFFu : 0u;
+    const uint32_t m = min(a | mo, b | mn);
+    return base == 3 ? ref : m;
 }
 
 // Trace of chunk g: the last t with chunk_base[t] <= g, for a non-decreasing
@@ -191,6 +195,7 @@ hipError_t launch_counters(const uint64_t* counts, const uint64_t* ts, const uin
 struct SweepPlan {
     uint32_t n_blocks;        // config blocks of kSweepLanes lanes, one window each
     const uint32_t* block_w;  // [n_blocks] window | base << 8
+    const uint32_t* block_ref;// [n_blocks] B_ref of base-3 blocks (else 0)
     const int32_t* lane_inc;  // [n_blocks * kSweepLanes]
     const int32_t* lane_dec;
     const uint32_t* lane_hmask;
@@ -207,11 +212,14 @@ hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint6
                         uint64_t* scores, uint32_t* argmin, uint64_t* keys, uint32_t* err,
                         hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 
-// The sweep's per-evaluation step on register data (valu_probe.hip): `steps`
-// steps (a multiple of 4) per lane, workgroups of kSweepLanes lanes, one
-// uint32 per lane written to out.
-hipError_t launch_valu_probe(uint32_t workgroups, uint32_t steps, uint32_t seed, uint32_t* out,
-                             hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+// VALU issue-rate probe (valu_probe.hip): `steps` rounds per lane of
+// independent 32-bit instructions (mode 0: v_add_u32; mode 1: the sweep
+// step's compare / add-with-carry / and / bcnt), workgroups of kSweepLanes
+// lanes, one uint32 per lane written to out.
+hipError_t launch_valu_probe(uint32_t workgroups, uint32_t steps, uint32_t mode, uint32_t seed,
+                             uint32_t* out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+// VALU instructions per lane and round of a probe mode.
+uint32_t valu_probe_ops_per_step(uint32_t mode);
 
 // Serving slot state.
 struct SlotState {

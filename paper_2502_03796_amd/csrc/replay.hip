@@ -129,7 +129,7 @@ __device__ __forceinline__ void replay_chunk(
     auto events = [&](uint32_t a, uint32_t b, uint64_t& EU, uint64_t& ED) {
         if constexpr (kAnyBase) {
             const bool rising = b > a;
-            const uint32_t lov = derivative_base(a, b, c.base);
+            const uint32_t lov = derivative_base(a, b, c.base, c.ref);
             const uint32_t d = max(a, b) - min(a, b);
             const uint32_t m = rising ? mu : md;
             // r = d / (W base) beyond q / 2^16  <=>  d 2^16 > base (W q)

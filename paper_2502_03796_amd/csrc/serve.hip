@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void serve_step_kernel(
     if (k >= w1) {
         const uint32_t a = st[slot].ring[pos];                  // sample k-W+1
         const uint32_t d = max(a, b) - min(a, b);
-        const uint32_t lov = derivative_base(a, b, c.base);
+        const uint32_t lov = derivative_base(a, b, c.base, c.ref);
         const bool rising = b > a;
         const uint32_t m = rising ? c.mu : c.md;
         if (((uint64_t)d << 16) > (uint64_t)lov * m) pred = rising ? 1 : -1;

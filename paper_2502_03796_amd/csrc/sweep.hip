@@ -29,12 +29,13 @@ __device__ __forceinline__ uint64_t wave_mask(bool p) { return __ballot(p); }
 
 // Quotients of step t (t >= W-1) of trace x.  The derivative's base is the
 // smaller sample by default (a for a rise, b for a fall), or always the
-// oldest (base 1) or always the newest (base 2) sample.
+// oldest (base 1), always the newest (base 2) sample, or the fixed reference
+// `ref` (base 3).
 __device__ __forceinline__ int2 step_quotients(uint32_t a, uint32_t b, uint32_t W,
-                                               uint32_t base) {
+                                               uint32_t base, uint32_t ref) {
     int2 r = make_int2(0, 0);
     if (b > a) {
-        const uint32_t bu = base == 2 ? b : a;
+        const uint32_t bu = base == 3 ? ref : base == 2 ? b : a;
         if (bu == 0) {
             r.x = INT32_MAX;
         } else {
@@ -44,7 +45,7 @@ __device__ __forceinline__ int2 step_quotients(uint32_t a, uint32_t b, uint32_t 
             r.x = q > (uint64_t)INT32_MAX ? INT32_MAX : (int32_t)q;
         }
     } else if (b < a) {
-        const uint32_t bd = base == 1 ? a : b;
+        const uint32_t bd = base == 3 ? ref : base == 1 ? a : b;
         if (bd == 0) {
             r.y = INT32_MIN;
         } else {
@@ -60,7 +61,8 @@ __device__ __forceinline__ int2 step_quotients(uint32_t a, uint32_t b, uint32_t 
 __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, uint32_t n_blocks, const uint32_t* __restrict__ chunk_status,
-    const uint32_t* __restrict__ block_w, const int32_t* __restrict__ lane_inc,
+    const uint32_t* __restrict__ block_w, const uint32_t* __restrict__ block_ref,
+    const int32_t* __restrict__ lane_inc,
     const int32_t* __restrict__ lane_dec, const uint32_t* __restrict__ lane_hmask,
     const uint32_t* __restrict__ lane_thr, const uint32_t* __restrict__ lane_lv,
     const uint32_t* __restrict__ lane_orig, const uint32_t* __restrict__ lane_steps,
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     const uint32_t t = work / n_blocks, blk = work % n_blocks;
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t W = block_w[blk] & 255u, base = block_w[blk] >> 8;
+    const uint32_t W = block_w[blk] & 255u, base = block_w[blk] >> 8, ref = block_ref[blk];
     const uint32_t li = blk * kSweepLanes + tid;
     const int32_t inc = lane_inc[li], dec = lane_dec[li];
     const uint32_t hmask = lane_hmask[li], thr = lane_thr[li];
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     auto prepass = [&](uint32_t tile0, int buf) {
         const uint32_t step = tile0 + tid;
         int2 q = make_int2(0, 0);
-        if (step < n && step + 1 >= W) q = step_quotients(x[step + 1 - W], x[step], W, base);
+        if (step < n && step + 1 >= W) q = step_quotients(x[step + 1 - W], x[step], W, base, ref);
         ud[buf][tid] = q;
     };
 
@@ -239,7 +241,8 @@ hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint6
     const uint32_t grid = (uint32_t)((n_work + 7) / 8 * 8);
     if (ev0) (void)hipEventRecord(ev0, stream);
     sweep_kernel<<<grid, kSweepLanes, 0, stream>>>(
-        samples, offsets, n_traces, plan.n_blocks, status, plan.block_w, plan.lane_inc,
+        samples, offsets, n_traces, plan.n_blocks, status, plan.block_w, plan.block_ref,
+        plan.lane_inc,
         plan.lane_dec, plan.lane_hmask, plan.lane_thr, plan.lane_lv, plan.lane_orig,
         plan.lane_steps, plan.block_stepped, n_cfgs, scores, keys);
     if (ev1) (void)hipEventRecord(ev1, stream);

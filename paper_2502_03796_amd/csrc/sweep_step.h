@@ -2,9 +2,8 @@
 // lane) whose configs jump to the bounds and whose level is at a bound: the
 // decisions of all lanes are wave masks, so the decision logic is scalar and
 // each mask bit enters the lane's event history and counters as the carry-in
-// of one add.  Shared by the sweep kernel and the VALU issue probe, which
-// runs this exact step on register data to measure the issue ceiling of its
-// instruction mix.
+// of one add.  The add with a mask as carry-in is shared with the VALU
+// issue-rate probe.
 #pragma once
 
 #include "magus_internal.h"

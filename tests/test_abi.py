@@ -35,7 +35,7 @@ def test_struct_layouts_match_header():
     fields = re.findall(r"(u?int\d+_t)\s+([\w, ]+);", cfg)
     names = [n.strip() for _, group in fields for n in group.split(",")]
     assert names == [f[0] for f in magus.MagusConfig._fields_]
-    assert ctypes.sizeof(magus.MagusConfig) == 20
+    assert ctypes.sizeof(magus.MagusConfig) == 24
     res = re.search(r"typedef struct magus_result \{(.*?)\} magus_result;", text, re.S).group(1)
     assert re.findall(r"uint64_t\s+(\w+);", res) == [f[0] for f in magus.MagusResult._fields_]
 

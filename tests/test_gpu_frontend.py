@@ -69,13 +69,22 @@ def test_counters_reject_empty_traces(ctx):
         ctx.check()
 
 
-@pytest.mark.parametrize("base", [1, 2])
+# B_ref values of the fixed-reference base (base 3): the listing's unscaled
+# derivative (1), levels inside the traces' range, and the largest reference
+REFS = (1, 5000, 20000, 100000, 2**32 - 1)
+
+
+@pytest.mark.parametrize("base", [1, 2, 3])
 def test_base_variants_replay_sweep_serve(ctx, oracle_mod, base):
     traces = mixed_traces(50 + base, LENGTHS)
     grid = synth.sweep_grid()
     rng = np.random.default_rng(base)
     cfgs = [dict(grid[int(i)], base=base) for i in rng.integers(0, len(grid), 20)]
     cfgs += [dict(default_config(up_step=2, down_step=1), base=base), default_config()]
+    if base == 3:
+        # several references in one call (the sweep groups configs by them)
+        for k, cf in enumerate(cfgs[:-1]):
+            cf["base_ref"] = REFS[k % len(REFS)]
     cot = (np.arange(len(traces)) % len(cfgs)).astype(np.uint32)
     samples, offsets = synth.make_batch(traces)
     want_res, want_b = oracle_mod.replay_batch(samples, offsets, cfgs, cot, want_bytes=True)

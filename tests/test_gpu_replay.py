@@ -86,6 +86,26 @@ def test_brute_force_tiny_traces(ctx, oracle_mod):
         assert (got_b == want_b).all(), (cfg, describe_mismatch(got_b, want_b, offsets))
 
 
+def test_brute_force_tiny_traces_other_bases(ctx, oracle_mod):
+    """The same tiny traces under the oldest, newest and fixed-reference
+    derivative bases (B_ref 1 and 2: r = 1/4 at W = 4 is an equality case)."""
+    traces = [np.array(t, np.uint32) for n in range(0, 8)
+              for t in itertools.product(range(5), repeat=n)]
+    samples, offsets = synth.make_batch(traces)
+    s, o, _ = to_dev(samples, offsets)
+    for (base, bref), W, H, (inc, dec) in itertools.product(
+            ((1, 0), (2, 0), (3, 1), (3, 2)), (2, 4), (1, 3),
+            ((0, 0), (16384, -16384), (32768, -1))):
+        cfg = default_config(window=W, hold=H, inc_q16=inc, dec_q16=dec, base=base,
+                             base_ref=bref)
+        want_res, want_b = oracle_mod.replay_batch(samples, offsets, [cfg], want_bytes=True)
+        res, lv = ctx.replay(s, o, [cfg], levels=True)
+        ctx.check()
+        assert (results_np(res) == want_res).all(), cfg
+        got_b = lv.cpu().numpy()
+        assert (got_b == want_b).all(), (cfg, describe_mismatch(got_b, want_b, offsets))
+
+
 def mixed_traces(seed, lengths):
     out = []
     for i, n in enumerate(lengths):
@@ -146,6 +166,13 @@ def test_extreme_sample_values(ctx, oracle_mod):
     for W, q in ((2, 2**20), (32, 2**20), (7, 1), (3, 12345), (16, 0)):
         run_both(ctx, oracle_mod, traces, [default_config(window=W, hold=3, inc_q16=q,
                                                           dec_q16=-q)], chunk=128)
+    # every derivative base at the extremes of the products (the fixed
+    # reference up to 2^32-1 against thresholds up to 2^20 at W = 32)
+    for base, bref in ((1, 0), (2, 0), (3, 1), (3, 2**32 - 1), (3, 77777)):
+        for W, q in ((2, 2**20), (32, 2**20), (7, 1), (16, 0)):
+            run_both(ctx, oracle_mod, traces,
+                     [default_config(window=W, hold=3, inc_q16=q, dec_q16=-q, base=base,
+                                     base_ref=bref)], chunk=128)
 
 
 def test_small_workload(ctx, oracle_mod):
