@@ -121,6 +121,11 @@ def bench_sweep(magus, synth, ctx, dev, checks=None, cpu=None):
     so = torch.from_numpy(soff.view(np.int64)).to(dev)
     grid = synth.sweep_grid()
     grid_arr = magus.config_array(grid)      # marshalled once
+    # the launch shape (configs per workgroup, steps per tile) from the
+    # autotuner, which checks that every shape finds the same arg-min
+    tuned = ctx.autotune_sweep(ss, so, grid_arr, reps=1)
+    log(f"  sweep autotuner: shape {tuned['shape']} ({tuned['lanes']} configs x "
+        f"{tuned['tile']} steps), {tuned['best_ms']:.1f} ms vs {tuned['default_ms']:.1f} ms")
     ctx.sweep(ss, so, grid_arr)
     torch.cuda.synchronize()
     ctx.set_profiling(True)
@@ -144,6 +149,9 @@ def bench_sweep(magus, synth, ctx, dev, checks=None, cpu=None):
     kern_s = kms / kn * 1e-3
     res = {"workload": "1,024 traces x 50,000 samples x 16,384 configs",
            "evals_per_s": evals / dt, "ms_per_sweep": dt * 1e3, "kernel_ms": kern_s * 1e3,
+           "autotuned": {"shape": tuned["shape"], "configs_per_workgroup": tuned["lanes"],
+                         "steps_per_tile": tuned["tile"], "best_ms": tuned["best_ms"],
+                         "default_ms": tuned["default_ms"]},
            "parity": "not checked (--no-cpu)"}
     log(f"  sweep {evals / dt:.3e} evals/s ({dt * 1e3:.1f} ms)")
     # ALU roofline: algorithmic int32 lane-ops per evaluation x evaluations /

@@ -241,6 +241,38 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                 uint64_t* d_scores, uint32_t* d_argmin, hipStream_t stream);
 
 /*
+ * Launch shape of magus_sweep: configs per workgroup and steps per tile of
+ * shared quotients.  Shapes 0..MAGUS_SWEEP_SHAPES-1 are, as (configs, steps):
+ * (256, 256) (the default), (256, 512), (256, 1024), (128, 256), (128, 512),
+ * (64, 256); magus_sweep_shape_info returns them.  Results never depend on
+ * the shape.
+ */
+#define MAGUS_SWEEP_SHAPES 6
+int magus_ctx_set_sweep_shape(magus_ctx* ctx, uint32_t shape);
+uint32_t magus_ctx_get_sweep_shape(const magus_ctx* ctx);
+int magus_sweep_shape_info(uint32_t shape, uint32_t* lanes, uint32_t* tile);
+
+/*
+ * Autotuner for magus_sweep: times every launch shape on the given batch and
+ * configs (`reps` timed calls each, after one untimed call), checks that every
+ * shape finds the same minimal score and config for every trace as shape 0
+ * (else MAGUS_EDEVICE and the context is left unchanged), and sets the
+ * fastest on the context.  d_argmin receives the arg-min of the calls; a
+ * batch that fails the data checks is MAGUS_EDATA.  Synchronizes `stream`.
+ */
+typedef struct magus_sweep_tune_result {
+    uint32_t shape;              /* chosen shape                             */
+    uint32_t lanes, tile;        /* its configs per workgroup, steps per tile */
+    uint32_t candidates;         /* shapes timed                             */
+    double best_ms;              /* time per call of the chosen shape        */
+    double default_ms;           /* time per call of shape 0                 */
+} magus_sweep_tune_result;
+int magus_autotune_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                         const uint64_t* d_offsets, uint32_t n_traces,
+                         const magus_config* h_cfgs, uint32_t n_cfgs, uint32_t* d_argmin,
+                         uint32_t reps, hipStream_t stream, magus_sweep_tune_result* h_out);
+
+/*
  * Measurement aid: the issue rate of 32-bit integer VALU instructions.  Every
  * lane of `workgroups` workgroups of 256 lanes runs `steps` rounds of 8
  * independent dependency chains, with nothing else in the loop (no memory,
@@ -393,7 +425,11 @@ int magus_stream_result(magus_server* srv, uint32_t slot, magus_result* h_out);
  * Events are sorted by t_ns (nanoseconds from the start of the run):
  *   MAGUS_EV_JOIN    node `stream` asks to be served with config
  *                    h_cfgs[value]; it is admitted into a free slot at once,
- *                    or waits (oldest first) until a leave frees one.
+ *                    or waits (oldest first) until a leave frees one.  A
+ *                    join of a node that left but whose slot still serves
+ *                    its earlier samples waits for that slot to close, then
+ *                    waits like any other join (a leave withdraws it).  A
+ *                    join of a node that is live or waiting is ignored.
  *   MAGUS_EV_SAMPLE  one throughput sample `value` of node `stream`; dropped
  *                    unless the node is admitted.
  *   MAGUS_EV_LEAVE   the node stops; its slot is freed once its pending

@@ -54,6 +54,15 @@ class MagusRunStats(ctypes.Structure):
                 ("joins_refused", ctypes.c_uint64), ("wall_s", ctypes.c_double)]
 
 
+class MagusSweepTuneResult(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
+                ("tile", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+
+SWEEP_SHAPES = 6
+
+
 class MagusTuneResult(ctypes.Structure):
     _fields_ = [("chunk_steps", ctypes.c_uint32), ("persistent_blocks", ctypes.c_uint32),
                 ("candidates", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
@@ -119,6 +128,13 @@ SIGNATURES = {
                                     ctypes.c_uint32, _P, _P, _P, _P]),
     "magus_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
                                    ctypes.c_uint32, _P, _P, _P]),
+    "magus_ctx_set_sweep_shape": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "magus_ctx_get_sweep_shape": (ctypes.c_uint32, [_P]),
+    "magus_sweep_shape_info": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                              ctypes.POINTER(ctypes.c_uint32)]),
+    "magus_autotune_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
+                                            ctypes.c_uint32, _P, ctypes.c_uint32, _P,
+                                            ctypes.POINTER(MagusSweepTuneResult)]),
     "magus_valu_probe": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                         _P, ctypes.POINTER(ctypes.c_uint64), _P]),
     "magus_counters_to_mbps": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint32,
@@ -182,6 +198,13 @@ def config_array(cfgs) -> ctypes.Array:
     for i, d in enumerate(cfgs):
         arr[i] = make_config(d)
     return arr
+
+
+def sweep_shape_info(shape: int):
+    """(configs per workgroup, steps per tile) of a sweep launch shape."""
+    lanes, tile = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().magus_sweep_shape_info(int(shape), ctypes.byref(lanes), ctypes.byref(tile)))
+    return lanes.value, tile.value
 
 
 def config_check(cfg: dict) -> None:
@@ -301,6 +324,28 @@ class Context:
             cp, _dev_ptr(results, "results", (torch.int64,)), int(reps),
             _stream_handle(stream, self.device), ctypes.byref(r)))
         return {f: getattr(r, f) for f, _ in MagusTuneResult._fields_ if f != "reserved"}
+
+    @property
+    def sweep_shape(self) -> int:
+        return int(load().magus_ctx_get_sweep_shape(self._h))
+
+    def set_sweep_shape(self, shape: int) -> None:
+        _check(load().magus_ctx_set_sweep_shape(self._h, int(shape)))
+
+    def autotune_sweep(self, samples, offsets, cfgs, reps: int = 2, stream=None) -> dict:
+        """Time every sweep launch shape on this batch (the arg-min must agree),
+        keep the fastest on the context and return what was chosen."""
+        torch = _torch()
+        arr = config_array(cfgs)
+        n_traces = offsets.numel() - 1
+        argmin = torch.empty(n_traces, dtype=torch.int32, device=samples.device)
+        r = MagusSweepTuneResult()
+        _check(load().magus_autotune_sweep(
+            self._h, _dev_ptr(samples, "samples", (torch.int32, torch.uint32)), samples.numel(),
+            _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64)), n_traces, arr, len(arr),
+            _dev_ptr(argmin, "argmin", (torch.int32,)), int(reps),
+            _stream_handle(stream, self.device), ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in MagusSweepTuneResult._fields_}
 
     def set_profiling(self, enable: bool) -> None:
         _check(load().magus_ctx_set_profiling(self._h, int(bool(enable))))

@@ -563,7 +563,11 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         ctx->proxy_model_set = true;
     }
     if (!stepped) {
-        // one pass over the samples: plan, fused chunk pass, fold, metrics
+        // one pass over the samples: plan, fused chunk pass, fold, metrics;
+        // a config that starts between the bounds needs the pass's third
+        // prefix total
+        bool mid_init = false;
+        for (const DevCfg& d : ctx->cfg_host) mid_init |= d.linit != d.lmin && d.linit != d.lmax;
         const void* before = ctx->chunk_base.p;
         if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
             (rc = ctx->proxy_sums.ensure((size_t)max_chunks * sizeof(ProxySum))))
@@ -576,7 +580,7 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                    max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
                                    ctx->proxy_model.as<magus_proxy_model>(),
                                    ctx->proxy_sums.as<ProxySum>(), d_stats, d_metrics, any_base,
-                                   stream));
+                                   mid_init, stream));
         return MAGUS_OK;
     }
     // stepped actuation: pass 1 of the stepped replay (plan, step masks, the
@@ -815,15 +819,109 @@ int magus_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         ctx->plan.block_stepped = reinterpret_cast<const uint32_t*>(base + o_bstep);
         ctx->sweep_cfg_host.assign(h_cfgs, h_cfgs + n_cfgs);
     }
-    if ((uint64_t)ctx->plan.n_blocks * n_traces >= (1ull << 31))
+    const uint32_t parts = kSweepLanes / kSweepShapes[ctx->sweep_shape].lanes;
+    if ((uint64_t)ctx->plan.n_blocks * n_traces * parts >= (1ull << 31))
         return fail(MAGUS_EINVAL, "traces x config blocks too large for one call");
     int rc;
     if ((rc = ctx->keys.ensure(((size_t)n_traces + 1) * 8))) return rc;
     magus_ctx::Timing tp(ctx, MAGUS_KERNEL_SWEEP);
     HIP_TRY(launch_sweep(d_samples, n_samples, d_offsets, n_traces, ctx->plan, n_cfgs, d_scores,
-                         d_argmin, ctx->keys.as<uint64_t>(), ctx->err.as<uint32_t>(), stream,
-                         tp.first, tp.second));
+                         d_argmin, ctx->keys.as<uint64_t>(), ctx->err.as<uint32_t>(),
+                         ctx->sweep_shape, stream, tp.first, tp.second));
     tp.commit();
+    return MAGUS_OK;
+}
+
+int magus_ctx_set_sweep_shape(magus_ctx* ctx, uint32_t shape) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (shape >= kSweepShapeCount)
+        return fail(MAGUS_EINVAL, "sweep shape %u outside 0..%u", shape, kSweepShapeCount - 1);
+    ctx->sweep_shape = shape;
+    return MAGUS_OK;
+}
+
+uint32_t magus_ctx_get_sweep_shape(const magus_ctx* ctx) { return ctx ? ctx->sweep_shape : 0; }
+
+int magus_sweep_shape_info(uint32_t shape, uint32_t* lanes, uint32_t* tile) {
+    if (shape >= kSweepShapeCount)
+        return fail(MAGUS_EINVAL, "sweep shape %u outside 0..%u", shape, kSweepShapeCount - 1);
+    if (lanes) *lanes = kSweepShapes[shape].lanes;
+    if (tile) *tile = kSweepShapes[shape].tile;
+    return MAGUS_OK;
+}
+
+int magus_autotune_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                         const uint64_t* d_offsets, uint32_t n_traces,
+                         const magus_config* h_cfgs, uint32_t n_cfgs, uint32_t* d_argmin,
+                         uint32_t reps, hipStream_t stream, magus_sweep_tune_result* h_out) {
+    if (!ctx || !h_out) return fail(MAGUS_EINVAL, "ctx and out are required");
+    if (n_traces == 0 || reps == 0) return fail(MAGUS_EINVAL, "need traces and reps >= 1");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    const uint32_t saved = ctx->sweep_shape;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<uint64_t> first(n_traces), keys(n_traces);
+    magus_sweep_tune_result r{};
+    double best = 0.0;
+    int rc = MAGUS_OK;
+    for (auto& e : ev)
+        if (rc == MAGUS_OK && hipEventCreate(&e) != hipSuccess)
+            rc = fail(MAGUS_EDEVICE, "hipEventCreate failed");
+    for (uint32_t shape = 0; rc == MAGUS_OK && shape < kSweepShapeCount; ++shape) {
+        ctx->sweep_shape = shape;
+        // one untimed call (it also builds the lane tables on the first shape)
+        if ((rc = magus_sweep(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
+                              nullptr, d_argmin, stream)))
+            break;
+        if (hipEventRecord(ev[0], stream) != hipSuccess) {
+            rc = fail(MAGUS_EDEVICE, "hipEventRecord failed");
+            break;
+        }
+        for (uint32_t k = 0; rc == MAGUS_OK && k < reps; ++k)
+            rc = magus_sweep(ctx, d_samples, n_samples, d_offsets, n_traces, h_cfgs, n_cfgs,
+                             nullptr, d_argmin, stream);
+        float ms = 0.f;
+        uint32_t status = 0;
+        if (rc == MAGUS_OK &&
+            (hipEventRecord(ev[1], stream) != hipSuccess ||
+             hipEventSynchronize(ev[1]) != hipSuccess ||
+             hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess ||
+             hipMemcpy(keys.data(), ctx->keys.p, (size_t)n_traces * 8,
+                       hipMemcpyDeviceToHost) != hipSuccess ||
+             hipMemcpy(&status, ctx->keys.as<uint64_t>() + n_traces, 4,
+                       hipMemcpyDeviceToHost) != hipSuccess))
+            rc = fail(MAGUS_EDEVICE, "timing sweep shape %u failed", shape);
+        if (rc != MAGUS_OK) break;
+        if (status != 0) {
+            rc = fail(MAGUS_EDATA, "the batch failed its data checks");
+            break;
+        }
+        // every shape must find the same minimal score and config per trace
+        if (shape == 0) {
+            first = keys;
+        } else if (keys != first) {
+            rc = fail(MAGUS_EDEVICE, "sweep shape %u gives results unlike shape 0", shape);
+            break;
+        }
+        const double per = (double)ms / reps;
+        if (shape == 0) r.default_ms = per;
+        if (shape == 0 || per < best) {
+            best = per;
+            r.shape = shape;
+        }
+        ++r.candidates;
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != MAGUS_OK) {
+        ctx->sweep_shape = saved;
+        return rc;
+    }
+    ctx->sweep_shape = r.shape;
+    r.lanes = kSweepShapes[r.shape].lanes;
+    r.tile = kSweepShapes[r.shape].tile;
+    r.best_ms = best;
+    *h_out = r;
     return MAGUS_OK;
 }
 

@@ -73,6 +73,7 @@ struct magus_ctx {
     magus::DevBuf sweep_tab;    // sweep: lane tables
     std::vector<magus_config> sweep_cfg_host;   // configs of the last sweep plan
     magus::SweepPlan plan{};
+    uint32_t sweep_shape = 0;   // sweep launch shape (index into kSweepShapes)
     magus::DevBuf proxy_model;    // proxy: the model in device memory
     magus::DevBuf proxy_sums;     // proxy: per-chunk summaries of the fused pass
     magus_proxy_model proxy_model_host{};   // ... as last uploaded

@@ -207,10 +207,20 @@ struct SweepPlan {
 };
 constexpr int kSweepLanes = 256;
 
+// Launch shapes of the sweep kernel: configs per workgroup (a block of
+// kSweepLanes configs, or an equal part of one) and steps per LDS tile.
+// Every shape gives the same scores.
+struct SweepShape {
+    uint32_t lanes, tile;
+};
+constexpr SweepShape kSweepShapes[] = {{256, 256}, {256, 512}, {256, 1024},
+                                       {128, 256}, {128, 512}, {64, 256}};
+constexpr uint32_t kSweepShapeCount = sizeof(kSweepShapes) / sizeof(kSweepShapes[0]);
+
 hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
                         uint32_t n_traces, const SweepPlan& plan, uint32_t n_cfgs,
                         uint64_t* scores, uint32_t* argmin, uint64_t* keys, uint32_t* err,
-                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+                        uint32_t shape, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 
 // VALU issue-rate probe (valu_probe.hip): `steps` rounds per lane of
 // independent 32-bit instructions (mode 0: v_add_u32; mode 1: the sweep

@@ -388,7 +388,15 @@ __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
 
 // Fused pass, one wave per chunk (blocks loaded four at a time: the per-lane
 // sums leave fewer registers for loads in flight than the plain replay has).
-template <bool kAnyBase>
+// Per lane, running totals of the excess at level_max and level_min over the
+// chunk so far are the only per-step sums: a run of blocks at one level is
+// credited at its end from the difference of its level's total at its two
+// ends, and the steps up to the chunk's first decisive step from the totals
+// at that point (summed over the wave there, once), so a block without a
+// decisive step costs two saturating subtractions and two 64-bit adds.
+// kMidInit: some config starts between the bounds, so a chunk can also be
+// entered at level_init and its prefix needs a third total.
+template <bool kAnyBase, bool kMidInit>
 __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -402,27 +410,24 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
                                    chunk, g);
     const uint32_t c_lo = model->cap_mbps[v.c.lmin], c_hi = model->cap_mbps[v.c.lmax];
     const uint32_t c_in = model->cap_mbps[v.c.linit];
-    uint64_t a_pre0 = 0, a_pre1 = 0, a_pre2 = 0, a_lo = 0, a_hi = 0, a_max = 0, a_min = 0;
+    uint64_t a_max = 0, a_min = 0;   // totals of the chunk so far (per lane)
+    uint64_t mark = 0;               // the current run's level total where it began
+    uint64_t a_in = 0;               // total at level_init before the first decisive step
+    uint64_t a_lo = 0, a_hi = 0;     // steps after the prefix, by level
+    uint64_t pre0 = 0, pre1 = 0, pre2 = 0;   // prefix at min, max, init (wave sums)
     uint32_t n_lo = 0, n_hi = 0;
-    bool seen = false;        // a decisive step earlier in this chunk
+    bool seen = false;          // a decisive step earlier in this chunk
     uint32_t ppre = v.e - v.s;  // steps up to and including the first decisive step
-    uint32_t lvl = 0;         // level bit after the last step (once seen)
-    uint64_t lvl_mask = 0;    // lvl as a lane mask (all or none)
-    // The run since the last decisive block is summed at its level without
-    // per-lane masks and moved to a_hi or a_lo at the next decisive block or
-    // the end (before the chunk's first decisive step it is discarded: those
-    // steps are summed after the walk).
-    uint64_t a_run = 0;
-    uint32_t n_run = 0;
+    uint32_t lvl = 0;           // level bit after the last step (once seen)
+    uint32_t run0 = v.s;        // first step of the current run
     for_each_block<4, kAnyBase>(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid,
                                              uint32_t x) {
         const uint32_t e_hi = sat_sub(x, c_hi), e_lo = sat_sub(x, c_lo);
-        a_max += e_hi;                                   // lanes past the end read 0
-        a_min += e_lo;
         if ((m.E | m.HM) == 0) {
             // no decisive step: the block runs at the level it was entered at
-            a_run += lane_pick(lvl_mask, e_hi, e_lo);
-            n_run += (uint32_t)__builtin_popcountll(valid);
+            a_max += e_hi;                               // lanes past the end read 0
+            a_min += e_lo;
+            if (kMidInit && !seen) a_in += sat_sub(x, c_in);
             return;
         }
         const uint64_t UP = m.HM | (m.E & m.R);          // high or +1 -> max
@@ -430,23 +435,29 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
         const uint64_t D = UP | DN;
         uint64_t det = valid;
         if (seen) {
+            // the run since the last decisive block, at level lvl
             if (lvl) {
-                a_hi += a_run;
-                n_hi += n_run;
+                a_hi += a_max - mark;
+                n_hi += tb - run0;
             } else {
-                a_lo += a_run;
-                n_lo += n_run;
+                a_lo += a_min - mark;
+                n_lo += tb - run0;
             }
         } else {
-            // steps up to and including the first decisive one are summed
-            // after the walk at each possible entering level
+            // steps up to and including the first decisive one run at the
+            // level entering the chunk: the totals so far plus this block's
+            // lanes up to it, at each level the chunk can be entered at
             const uint32_t p = (uint32_t)__builtin_ctzll(D);
+            const uint64_t in = mask_below(p + 1);
             ppre = tb + p + 1 - v.s;
-            det &= ~mask_below(p + 1);
+            pre0 = dpp_wave_sum64(a_min + lane_sel(in, e_lo));
+            pre1 = dpp_wave_sum64(a_max + lane_sel(in, e_hi));
+            if (kMidInit) pre2 = dpp_wave_sum64(a_in + lane_sel(in, sat_sub(x, c_in)));
+            det &= ~in;
             seen = true;
         }
-        a_run = 0;
-        n_run = 0;
+        a_max += e_hi;
+        a_min += e_lo;
         // level bit before each step: the carries into the bits of
         // ~DN + UP + lvl (UP generates, DN kills)
         uint32_t cout;
@@ -457,37 +468,29 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
         a_hi += lane_sel(hi_m, e_hi);
         a_lo += lane_sel(lo_m, e_lo);
         lvl = cout;                                      // level after the block's last step
-        lvl_mask = cout ? ~0ull : 0ull;
+        mark = lvl ? a_max : a_min;
+        run0 = tb + 64;
     });
     if (seen) {
         if (lvl) {
-            a_hi += a_run;
-            n_hi += n_run;
+            a_hi += a_max - mark;
+            n_hi += v.e > run0 ? v.e - run0 : 0u;
         } else {
-            a_lo += a_run;
-            n_lo += n_run;
+            a_lo += a_min - mark;
+            n_lo += v.e > run0 ? v.e - run0 : 0u;
         }
     }
-    // the steps up to and including the first decisive step, at each of the
-    // three levels the chunk can be entered at (usually a block or two)
-    {
-        const uint32_t first_real = v.s >= 64 ? 1u : 0u;
-        for (uint32_t b = 0; b * 64 < ppre; ++b) {
-            const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(
-                v.rsrc, (int)(((first_real + b) * 64 + lane) * 4), 0, 0);
-            const uint64_t in = mask_below(min(ppre - b * 64, 64u));
-            a_pre0 += lane_sel(in, sat_sub(x, c_lo));
-            a_pre1 += lane_sel(in, sat_sub(x, c_hi));
-            a_pre2 += lane_sel(in, sat_sub(x, c_in));
-        }
-    }
-    a_pre0 = dpp_wave_sum64(a_pre0);
-    a_pre1 = dpp_wave_sum64(a_pre1);
-    a_pre2 = dpp_wave_sum64(a_pre2);
     a_lo = dpp_wave_sum64(a_lo);
     a_hi = dpp_wave_sum64(a_hi);
     a_max = dpp_wave_sum64(a_max);
     a_min = dpp_wave_sum64(a_min);
+    if (!seen) {
+        // no decisive step: the whole chunk runs at the entering level
+        pre0 = a_min;
+        pre1 = a_max;
+        if (kMidInit) pre2 = dpp_wave_sum64(a_in);
+    }
+    if (!kMidInit) pre2 = v.c.linit == v.c.lmax ? pre1 : pre0;
     if (lane == 0) {
         ProxySum r;
         r.len = v.e - v.s;
@@ -496,9 +499,9 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
         r.end_up = (uint32_t)lvl;
         r.n_lo = n_lo;
         r.n_hi = n_hi;
-        r.pre_x[0] = a_pre0;
-        r.pre_x[1] = a_pre1;
-        r.pre_x[2] = a_pre2;
+        r.pre_x[0] = pre0;
+        r.pre_x[1] = pre1;
+        r.pre_x[2] = pre2;
         r.x_lo = a_lo;
         r.x_hi = a_hi;
         r.ex_max = a_max;
@@ -621,14 +624,18 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                               const magus_proxy_model* model, ProxySum* psums,
                               magus_proxy_stats* stats, magus_proxy_metrics* metrics,
-                              bool any_base, hipStream_t stream)
+                              bool any_base, bool mid_init, hipStream_t stream)
 {
     if (n_traces == 0) return hipSuccess;
     const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
-    if (blocks)
-        (any_base ? proxy_chunk_kernel<true> : proxy_chunk_kernel<false>)
-            <<<blocks, kStatsWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base,
-                                                         cfgs, cfg_of_trace, chunk, model, psums);
+    if (blocks) {
+        auto k = any_base ? (mid_init ? proxy_chunk_kernel<true, true>
+                                      : proxy_chunk_kernel<true, false>)
+                          : (mid_init ? proxy_chunk_kernel<false, true>
+                                      : proxy_chunk_kernel<false, false>);
+        k<<<blocks, kStatsWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base,
+                                                      cfgs, cfg_of_trace, chunk, model, psums);
+    }
     proxy_fold_kernel<<<(n_traces + kStatsWaves - 1) / kStatsWaves, kStatsWaves * kWave, 0,
                         stream>>>(n_traces, chunk_base, psums, cfgs, cfg_of_trace, stats);
     if (metrics)

@@ -34,7 +34,7 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                               const magus_proxy_model* model, ProxySum* psums,
                               magus_proxy_stats* stats, magus_proxy_metrics* metrics,
-                              bool any_base, hipStream_t stream);
+                              bool any_base, bool mid_init, hipStream_t stream);
 
 // Stepped configs: runs after launch_stepped_prepare of the same batch
 // (chunk plan in chunk_base, the level entering every chunk in `entering`,

@@ -10,7 +10,9 @@
 // arrival order (a stream's state update of step k+1 needs the one of step
 // k).  Joins are admitted while slots (the
 // memory budget) allow, otherwise they wait for a leave; a leave closes the
-// slot once the stream's pending samples are served.
+// slot once the stream's pending samples are served.  A join for a node whose
+// old slot is still draining is held until that slot closes, then queues like
+// any join that waits.
 
 #include <chrono>
 #include <deque>
@@ -32,6 +34,8 @@ struct StreamRec {
     uint32_t in_flight = 0;          // dispatched samples not yet retired
     std::deque<uint64_t> fifo;       // pending sample events (indices)
     bool ready = false;              // listed in the ready list
+    bool rejoin = false;             // a join arrived while leaving (kLeaving)
+    uint32_t rejoin_cfg = 0;         // ... with this config
 };
 
 struct Batch {
@@ -111,6 +115,12 @@ extern "C" int magus_server_run(magus_server* srv, const magus_event* ev, uint64
         StreamRec& r = rec[sid];
         if (int rc = magus_stream_close(srv, r.slot)) return rc;
         r.state = kIdle;
+        if (r.rejoin) {                          // the node joined again meanwhile
+            r.rejoin = false;
+            r.cfg = r.rejoin_cfg;
+            r.state = kWaiting;
+            waiting.push_back(sid);
+        }
         while (!waiting.empty()) {               // admit waiting joins, oldest first
             const uint32_t w = waiting.front();
             if (rec[w].state != kWaiting) {
@@ -133,6 +143,11 @@ extern "C" int magus_server_run(magus_server* srv, const magus_event* ev, uint64
         StreamRec& r = rec[e.stream];
         switch (e.kind) {
         case MAGUS_EV_JOIN:
+            if (r.state == kLeaving) {           // its old slot is still draining
+                r.rejoin = true;
+                r.rejoin_cfg = e.value;
+                break;
+            }
             if (r.state != kIdle) break;         // already live or waiting
             r.cfg = e.value;
             if (try_admit(e.stream)) {
@@ -145,6 +160,9 @@ extern "C" int magus_server_run(magus_server* srv, const magus_event* ev, uint64
         case MAGUS_EV_LEAVE:
             if (r.state == kWaiting) {
                 r.state = kIdle;                 // never admitted
+                ++st.joins_refused;
+            } else if (r.state == kLeaving && r.rejoin) {
+                r.rejoin = false;                // the held join is withdrawn
                 ++st.joins_refused;
             } else if (r.state == kLive) {
                 r.state = kLeaving;
@@ -268,7 +286,8 @@ extern "C" int magus_server_run(magus_server* srv, const magus_event* ev, uint64
     if (rc == MAGUS_OK) rc = retire(true);
     // the run owns the streams it admitted: close those still open
     for (uint32_t sid = 0; sid < n_streams; ++sid) {
-        if (rec[sid].state == kWaiting) ++st.joins_refused;
+        if (rec[sid].state == kWaiting || (rec[sid].state == kLeaving && rec[sid].rejoin))
+            ++st.joins_refused;
         if (rec[sid].state == kLive || rec[sid].state == kLeaving) {
             (void)magus_stream_close(srv, rec[sid].slot);
             rec[sid].state = kIdle;

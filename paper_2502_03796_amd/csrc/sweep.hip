@@ -1,7 +1,9 @@
 // Parameter sweep of the MAGUS controller on gfx950: one lane per config.
 //
-// A workgroup takes one trace and one block of kSweepLanes configs that share
-// the derivative window W.  For each tile of steps the workgroup first
+// Configs are grouped into blocks of kSweepLanes that share the derivative
+// window W (and base).  A workgroup takes one trace and kLanes configs of one
+// block (the whole block, or a part of it; the launch shape is tunable).  For
+// each tile of kTile steps the workgroup first
 // computes, once per step, the two integer quotients that decide Alg. 1 for
 // every threshold at once:
 //   U(t) = ceil((b-a) 2^16 / (W a))  if b > a (a = 0: INT32_MAX), else 0
@@ -18,8 +20,6 @@
 
 namespace magus {
 namespace {
-
-constexpr int kTile = kSweepLanes;     // steps per LDS tile (one per thread)
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -58,7 +58,10 @@ __device__ __forceinline__ int2 step_quotients(uint32_t a, uint32_t b, uint32_t 
     return r;
 }
 
-__global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
+// One workgroup per (trace, part of a config block): kLanes configs, tiles of
+// kTile steps (kTile / kLanes quotient pairs per thread per tile).
+template <int kLanes, int kTile>
+__global__ __launch_bounds__(kLanes) void sweep_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, uint32_t n_blocks, const uint32_t* __restrict__ chunk_status,
     const uint32_t* __restrict__ block_w, const uint32_t* __restrict__ block_ref,
@@ -69,21 +72,27 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     const uint32_t* __restrict__ block_stepped, uint32_t n_cfgs,
     uint64_t* __restrict__ scores, uint64_t* __restrict__ keys)
 {
+    static_assert(kSweepLanes % kLanes == 0 && kTile % kLanes == 0, "sweep launch shape");
+    constexpr uint32_t kParts = kSweepLanes / kLanes;
     __shared__ int2 ud[2][kTile];
-    __shared__ uint64_t wave_min[kSweepLanes / kWave];
+    __shared__ uint64_t wave_min[kLanes / kWave];
     if (chunk_status[0] != 0) return;
 
     // Work index, grouped so that the config blocks of one trace run on the
     // same XCD (workgroups are dealt round-robin to the 8 XCDs).
-    const uint32_t n_work = n_traces * n_blocks;
+    const uint32_t n_work = n_traces * n_blocks * kParts;
     const uint32_t per_xcd = (gridDim.x + 7) / 8;
     const uint32_t work = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (work >= n_work) return;
-    const uint32_t t = work / n_blocks, blk = work % n_blocks;
+    const uint32_t t = work / (n_blocks * kParts), bp = work % (n_blocks * kParts);
+    const uint32_t blk = bp / kParts, part = bp % kParts;
+    // a part of a block holding only padding lanes (they sit at the block's
+    // end) has nothing to report
+    if (kParts > 1 && lane_orig[blk * kSweepLanes + part * kLanes] == 0xFFFFFFFFu) return;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t W = block_w[blk] & 255u, base = block_w[blk] >> 8, ref = block_ref[blk];
-    const uint32_t li = blk * kSweepLanes + tid;
+    const uint32_t li = blk * kSweepLanes + part * kLanes + tid;
     const int32_t inc = lane_inc[li], dec = lane_dec[li];
     const uint32_t hmask = lane_hmask[li], thr = lane_thr[li];
     const uint32_t lv = lane_lv[li];
@@ -105,10 +114,14 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     uint64_t isum = 0;
 
     auto prepass = [&](uint32_t tile0, int buf) {
-        const uint32_t step = tile0 + tid;
-        int2 q = make_int2(0, 0);
-        if (step < n && step + 1 >= W) q = step_quotients(x[step + 1 - W], x[step], W, base, ref);
-        ud[buf][tid] = q;
+#pragma unroll
+        for (uint32_t j = 0; j < (uint32_t)kTile; j += kLanes) {
+            const uint32_t step = tile0 + j + tid;
+            int2 q = make_int2(0, 0);
+            if (step < n && step + 1 >= W)
+                q = step_quotients(x[step + 1 - W], x[step], W, base, ref);
+            ud[buf][j + tid] = q;
+        }
     };
 
     prepass(0, 0);
@@ -187,7 +200,7 @@ __global__ __launch_bounds__(kSweepLanes) void sweep_kernel(
     __syncthreads();
     if (tid == 0) {
         uint64_t m = wave_min[0];
-        for (int w = 1; w < kSweepLanes / kWave; ++w) m = wave_min[w] < m ? wave_min[w] : m;
+        for (int w = 1; w < kLanes / kWave; ++w) m = wave_min[w] < m ? wave_min[w] : m;
         atomicMin((unsigned long long*)&keys[t], (unsigned long long)m);
     }
 }
@@ -231,20 +244,32 @@ __global__ __launch_bounds__(1024) void sweep_check_kernel(
 hipError_t launch_sweep(const uint32_t* samples, uint64_t n_samples, const uint64_t* offsets,
                         uint32_t n_traces, const SweepPlan& plan, uint32_t n_cfgs,
                         uint64_t* scores, uint32_t* argmin, uint64_t* keys, uint32_t* err,
-                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
+                        uint32_t shape, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (n_traces == 0) return hipSuccess;
+    if (shape >= kSweepShapeCount) return hipErrorInvalidValue;
     uint32_t* status = reinterpret_cast<uint32_t*>(keys + n_traces);
     sweep_check_kernel<<<1, 1024, 0, stream>>>(offsets, n_traces, n_samples, status, err);
     keys_init_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(keys, n_traces);
-    const uint64_t n_work = (uint64_t)n_traces * plan.n_blocks;
+    const uint32_t lanes = kSweepShapes[shape].lanes;
+    const uint64_t n_work = (uint64_t)n_traces * plan.n_blocks * (kSweepLanes / lanes);
     const uint32_t grid = (uint32_t)((n_work + 7) / 8 * 8);
     if (ev0) (void)hipEventRecord(ev0, stream);
-    sweep_kernel<<<grid, kSweepLanes, 0, stream>>>(
-        samples, offsets, n_traces, plan.n_blocks, status, plan.block_w, plan.block_ref,
-        plan.lane_inc,
-        plan.lane_dec, plan.lane_hmask, plan.lane_thr, plan.lane_lv, plan.lane_orig,
-        plan.lane_steps, plan.block_stepped, n_cfgs, scores, keys);
+    auto go = [&](auto kernel, uint32_t threads) {
+        kernel<<<grid, threads, 0, stream>>>(
+            samples, offsets, n_traces, plan.n_blocks, status, plan.block_w, plan.block_ref,
+            plan.lane_inc, plan.lane_dec, plan.lane_hmask, plan.lane_thr, plan.lane_lv,
+            plan.lane_orig, plan.lane_steps, plan.block_stepped, n_cfgs, scores, keys);
+    };
+    static_assert(kSweepShapeCount == 6, "one launch per shape");
+    switch (shape) {
+    case 0: go(sweep_kernel<256, 256>, 256); break;
+    case 1: go(sweep_kernel<256, 512>, 256); break;
+    case 2: go(sweep_kernel<256, 1024>, 256); break;
+    case 3: go(sweep_kernel<128, 256>, 128); break;
+    case 4: go(sweep_kernel<128, 512>, 128); break;
+    default: go(sweep_kernel<64, 256>, 64); break;
+    }
     if (ev1) (void)hipEventRecord(ev1, stream);
     argmin_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(keys, n_traces, status, argmin);
     return hipGetLastError();

@@ -66,6 +66,18 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.magus_server_slot_bytes() == 192
 
 
+def test_sweep_shapes_on_the_host():
+    lib = magus.load()
+    shapes = [magus.sweep_shape_info(i) for i in range(magus.SWEEP_SHAPES)]
+    assert shapes[0] == (256, 256)
+    for lanes, tile in shapes:
+        assert 256 % lanes == 0 and tile % lanes == 0 and lanes % 64 == 0
+    with pytest.raises(magus.MagusError):
+        magus.sweep_shape_info(magus.SWEEP_SHAPES)
+    assert lib.magus_ctx_set_sweep_shape(None, 0) == magus.EINVAL
+    assert lib.magus_ctx_get_sweep_shape(None) == 0
+
+
 def test_proxy_struct_layouts_match_header():
     text = open(HEADER).read()
     for cname, pyt, size in (("magus_proxy_model", magus.MagusProxyModel, 272),

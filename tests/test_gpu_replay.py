@@ -250,6 +250,45 @@ def test_device_data_faults_are_reported_not_run(ctx):
     ctx.check()
 
 
+def test_a_data_fault_stays_with_its_call(ctx, oracle_mod):
+    """A faulty batch (offsets that go backwards in the middle) writes no
+    result; the next good replay on the context, before the check, is run
+    and correct (the plan's status is per call); the check still reports the
+    earlier fault; after it, good batches (with and without decision bytes,
+    one wave per chunk and the persistent grid) match the oracle."""
+    import torch
+    traces = mixed_traces(41, [9000, 5000, 12000, 300, 20000, 7000])
+    samples, offsets = synth.make_batch(traces)
+    want, want_b = oracle_mod.replay_batch(samples, offsets, [default_config()],
+                                           want_bytes=True)
+    s, o, _ = to_dev(samples, offsets)
+    bad_off = offsets.copy()
+    bad_off[3] = offsets[1]                         # trace 2 runs backwards
+    bo = torch.from_numpy(bad_off.view(np.int64)).cuda()
+    sentinel = torch.full((len(traces), 4), 7, dtype=torch.int64, device="cuda")
+    ctx.replay(s, bo, [default_config()], levels=True, results=sentinel)
+    torch.cuda.synchronize()
+    assert (sentinel.cpu().numpy() == 7).all()      # no result written
+    res, _ = ctx.replay(s, o, [default_config()])
+    torch.cuda.synchronize()
+    assert (results_np(res) == want).all()
+    with pytest.raises(magus.MagusError) as ei:
+        ctx.check()
+    assert ei.value.code == magus.EDATA
+    for persistent in (0, 3):
+        ctx.set_persistent(persistent)
+        try:
+            for levels in (False, True):
+                res, lv = ctx.replay(s, o, [default_config()], levels=levels)
+                ctx.check()
+                assert (results_np(res) == want).all(), (persistent, levels)
+                if levels:
+                    got = lv.cpu().numpy()
+                    assert (got == want_b).all(), describe_mismatch(got, want_b, offsets)
+        finally:
+            ctx.set_persistent(0)
+
+
 @pytest.fixture(scope="module")
 def bulk():
     return synth.workload_bulk()

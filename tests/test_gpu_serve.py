@@ -181,6 +181,53 @@ def test_fleet_flat_out_with_churn_matches_oracle(ctx, oracle_mod):
     srv.close()
 
 
+def test_leave_then_rejoin_same_stream(ctx, oracle_mod):
+    """A node leaves and joins again (another config) while its first
+    session's samples are still queued: the join is held until the old slot
+    closes, then admitted as a waiting join, and the new session starts from a
+    fresh state; a held join withdrawn by a leave counts as refused."""
+    grid = synth.sweep_grid()
+    ca, cb = 5, 9001
+    x1 = synth.serve_stream_samples(3, 400)
+    x2 = synth.serve_stream_samples(4, 300)
+
+    def events(t_leave, t_join, t2, withdraw=False):
+        rows = [(0, synth.EV_JOIN, 0, ca, 0)]
+        rows += [(1000 + 1000 * i, synth.EV_SAMPLE, 0, int(v), 0) for i, v in enumerate(x1)]
+        rows += [(t_leave, synth.EV_LEAVE, 0, 0, 0), (t_join, synth.EV_JOIN, 0, cb, 0)]
+        if withdraw:
+            rows += [(t_join + 1, synth.EV_LEAVE, 0, 0, 0)]
+        rows += [(t2 + 1000 * i, synth.EV_SAMPLE, 0, int(v), 0) for i, v in enumerate(x2)]
+        return np.array(rows, dtype=magus.EVENT_DTYPE)
+
+    _, want1 = oracle_mod.replay_trace(x1, grid[ca])
+    _, want2 = oracle_mod.replay_trace(x2, grid[cb])
+    srv = magus.Server(ctx, 4 * magus.Server.slot_bytes())
+    s1 = np.arange(1, 401)
+    # flat out: every event is ingested before the first batch retires, so
+    # the join meets the draining slot; the new session's samples arrive
+    # before it is admitted and are dropped
+    ev = events(401_000, 401_500, 402_000)
+    dec, _, st = srv.run(ev, 1, grid, realtime=False, depth=2)
+    assert (dec[s1] == want1).all()
+    assert st["joins_admitted"] == 1 and st["joins_waited"] == 1 and st["joins_refused"] == 0
+    assert st["samples_served"] == 400 and st["samples_dropped"] == 300
+    # the held join withdrawn by a leave before the slot closes
+    ev = events(401_000, 401_500, 402_000, withdraw=True)
+    dec, _, st = srv.run(ev, 1, grid, realtime=False, depth=2)
+    assert (dec[s1] == want1).all()
+    assert st["joins_admitted"] == 1 and st["joins_waited"] == 0 and st["joins_refused"] == 1
+    # real time, the new session's samples 20 ms later: both sessions are
+    # served whole, each from a fresh state
+    ev = events(401_000, 401_500, 20_000_000)
+    dec, _, st = srv.run(ev, 1, grid, realtime=True, depth=2)
+    assert (dec[s1] == want1).all()
+    assert (dec[len(ev) - 300:] == want2).all()
+    assert st["joins_admitted"] + st["joins_waited"] == 2 and st["samples_served"] == 700
+    assert srv.open_count == 0
+    srv.close()
+
+
 def test_fleet_stream_alone_equals_in_mix(ctx, oracle_mod):
     grid = synth.sweep_grid()
     ev, n_streams, cfg_of_stream = synth.serve_fleet_events(64, 60, join_rate=0.0,

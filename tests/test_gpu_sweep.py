@@ -64,6 +64,47 @@ def test_unsorted_windows_and_padding(ctx, oracle_mod):
     sweep_both(ctx, oracle_mod, traces, cfgs)
 
 
+@pytest.mark.parametrize("shape", range(magus.SWEEP_SHAPES))
+def test_every_launch_shape_matches_the_oracle(ctx, oracle_mod, shape):
+    """Each launch shape (configs per workgroup, steps per tile): traces of
+    lengths around the tile sizes (255..1025, and 2 tiles + 1), a grid
+    sample, stepped and base-variant configs, and blocks with padding parts
+    (700 configs: the last block of each window holds fewer than 256)."""
+    grid = synth.sweep_grid()
+    rng = np.random.default_rng(50 + shape)
+    cfgs = [grid[int(i)] for i in rng.integers(0, len(grid), 640)]
+    cfgs += [dict(default_config(up_step=2, down_step=1)), dict(default_config(base=1)),
+             dict(default_config(base=3, base_ref=20000)), default_config(level_init=7)]
+    cfgs += [grid[int(i)] for i in rng.integers(0, len(grid), 56)]
+    traces = mixed_traces(404 + shape, [0, 1, 63, 255, 256, 257, 511, 512, 513, 1023, 1024,
+                                        1025, 2049, 4000])
+    ctx.set_sweep_shape(shape)
+    try:
+        assert ctx.sweep_shape == shape
+        sweep_both(ctx, oracle_mod, traces, cfgs)
+    finally:
+        ctx.set_sweep_shape(0)
+
+
+def test_sweep_autotune_keeps_results(ctx, oracle_mod):
+    """The autotuner times every shape, requires identical arg-min keys, and
+    keeps the fastest; the sweep with the chosen shape matches the oracle."""
+    grid = synth.sweep_grid()
+    cfgs = [grid[i] for i in range(0, 16384, 5)]
+    traces = mixed_traces(505, [3000] * 8 + [777, 1])
+    samples, offsets = synth.make_batch(traces)
+    s, o, _ = to_dev(samples, offsets)
+    r = ctx.autotune_sweep(s, o, cfgs, reps=1)
+    try:
+        assert r["candidates"] == magus.SWEEP_SHAPES
+        assert ctx.sweep_shape == r["shape"]
+        assert (r["lanes"], r["tile"]) == magus.sweep_shape_info(r["shape"])
+        assert r["best_ms"] <= r["default_ms"]
+        sweep_both(ctx, oracle_mod, traces, cfgs)
+    finally:
+        ctx.set_sweep_shape(0)
+
+
 def test_ties_take_the_lowest_index(ctx, oracle_mod):
     """A constant trace scores 0 under every config: arg-min is config 0; with a
     duplicated best config the lower index wins."""
