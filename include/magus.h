@@ -225,6 +225,56 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                  uint8_t* d_levels, hipStream_t stream);
 
 /*
+ * Bits of a device-side data-check status word: the checks behind
+ * MAGUS_EDATA (magus_ctx_check), as magus_replay_noalloc reports them.
+ */
+#define MAGUS_DATA_OFFSETS 1u    /* offsets not non-decreasing, or beyond n_samples */
+#define MAGUS_DATA_TOO_LONG 2u   /* a trace longer than MAGUS_MAX_TRACE_LEN         */
+#define MAGUS_DATA_CFG_INDEX 4u  /* a d_cfg_of_trace index >= n_cfgs                */
+
+/*
+ * Allocation-free replay, for callers that cannot allocate device memory at
+ * call time (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid allocation).  The same computation as magus_replay for configs
+ * that jump to the bound (up_step = down_step = 0; stepped configs are
+ * MAGUS_EINVAL), with the same argument rules and results, on the calling
+ * thread's current HIP device, with no context.
+ *   - Its scratch (config table, chunk prefix and status, chunk summaries,
+ *     fix-up records for decision bytes) is one fixed array of
+ *     MAGUS_NOALLOC_SCRATCH_BYTES in device memory, one per device, held from
+ *     the library's load until the process ends.  Its address is resolved on
+ *     the first call on each device.  The call itself allocates nothing: no
+ *     hipMalloc, no hipFree, no pinned host memory.
+ *   - A batch needs 32 B per config (at most MAGUS_NOALLOC_MAX_CFGS),
+ *     4 B per trace, and 32 B per time chunk of 4,096 steps (an upper bound
+ *     of n_samples / 4096 + n_traces + 1 chunks), + 16 B per chunk with
+ *     d_levels; each part rounded up to 256 B.  A batch that needs more is
+ *     MAGUS_EINVAL with the sizes in magus_last_error() and nothing runs.
+ *     8 MiB holds the 4,096 x 100,000 batch with decision bytes, or 20,000
+ *     traces of 6.6e8 samples in all with 16,384 configs without them.
+ *   - d_status: NULL, or one uint32 of device memory that receives the
+ *     call's data-check bits (MAGUS_DATA_*, 0 = the batch was run).  A batch
+ *     whose bits are not 0 leaves d_results and d_levels unwritten; with
+ *     d_status NULL nothing reports it.  The status is the call's own (no
+ *     fault of an earlier call carries over).
+ *   - Every call on a device shares that device's array, which keeps the last
+ *     call's contents (each call rewrites every part it reads).  Calls that
+ *     overlap in time on one device, from any stream or thread, race on it:
+ *     the caller orders them (one stream, or events).  Host-side, calls are
+ *     serialised by a lock while they validate and enqueue.
+ *   - The configs are validated and derived into a fixed host array, which
+ *     the copy to the device has read before the call returns (h_cfgs may be
+ *     reused at once).
+ */
+#define MAGUS_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+#define MAGUS_NOALLOC_MAX_CFGS 16384u
+int magus_replay_noalloc(const uint32_t* d_samples, uint64_t n_samples,
+                         const uint64_t* d_offsets, uint32_t n_traces,
+                         const magus_config* h_cfgs, uint32_t n_cfgs,
+                         const uint32_t* d_cfg_of_trace, magus_result* d_results,
+                         uint8_t* d_levels, uint32_t* d_status, hipStream_t stream);
+
+/*
  * Parameter sweep: every trace against every config (the same controller as
  * magus_replay for every pair; Alg. 1's window and thresholds and Alg. 2's
  * FIFO length are the swept parameters).

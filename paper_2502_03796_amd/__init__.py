@@ -23,6 +23,9 @@ LIB_PATH = os.path.join(_HERE, "libmagus.so")
 OK, EINVAL, ENOMEM, ENOSLOT, EDEVICE, EDATA = 0, -1, -2, -3, -4, -5
 KERNEL_REPLAY, KERNEL_SWEEP, KERNEL_SERVE, KERNEL_PROBE = 0, 1, 2, 3
 MAX_TRACE_LEN = (1 << 30) - 1
+DATA_OFFSETS, DATA_TOO_LONG, DATA_CFG_INDEX = 1, 2, 4   # data-check status bits
+NOALLOC_SCRATCH_BYTES = 8 << 20
+NOALLOC_MAX_CFGS = 16384
 
 
 class MagusError(RuntimeError):
@@ -126,6 +129,8 @@ SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_uint64)]),
     "magus_replay": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
                                     ctypes.c_uint32, _P, _P, _P, _P]),
+    "magus_replay_noalloc": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
+                                            ctypes.c_uint32, _P, _P, _P, _P, _P]),
     "magus_sweep": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.c_uint32, _P,
                                    ctypes.c_uint32, _P, _P, _P]),
     "magus_ctx_set_sweep_shape": (ctypes.c_int, [_P, ctypes.c_uint32]),
@@ -266,6 +271,38 @@ def proxy_metrics_dict(row) -> dict:
     """One row of the float64[T, 21] metrics tensor returned by Context.proxy."""
     v = [float(x) for x in row]
     return {k: v[3 * i:3 * i + 3] for i, k in enumerate(PROXY_METRIC_KEYS)}
+
+
+def replay_noalloc(samples, offsets, cfgs, cfg_of_trace=None, levels: bool = False,
+                   results=None, levels_out=None, status=None, stream=None):
+    """magus_replay_noalloc on the tensors' device (made current for the call):
+    the jump-to-bound replay without a context, with the library's fixed
+    scratch array.  Returns (results int64[T, 4], levels uint8 or None,
+    status int32[1]: the data-check bits, 0 = run)."""
+    torch = _torch()
+    arr = config_array(cfgs)
+    sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
+    op = _dev_ptr(offsets, "offsets", (torch.int64, torch.uint64))
+    n_traces = offsets.numel() - 1
+    dev = samples.device
+    if results is None:
+        results = torch.empty((n_traces, 4), dtype=torch.int64, device=dev)
+    rp = _dev_ptr(results, "results", (torch.int64,))
+    cp = None
+    if cfg_of_trace is not None:
+        cp = _dev_ptr(cfg_of_trace, "cfg_of_trace", (torch.int32, torch.uint32))
+    lp = None
+    if levels:
+        if levels_out is None:
+            levels_out = torch.zeros(samples.numel(), dtype=torch.uint8, device=dev)
+        lp = _dev_ptr(levels_out, "levels", (torch.uint8,))
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+    stp = _dev_ptr(status, "status", (torch.int32,))
+    with torch.cuda.device(dev):
+        _check(load().magus_replay_noalloc(sp, samples.numel(), op, n_traces, arr, len(arr),
+                                           cp, rp, lp, stp, _stream_handle(stream, dev)))
+    return results, (levels_out if levels else None), status
 
 
 class Context:

@@ -132,16 +132,17 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
                          magus_result* results, uint8_t* levels, uint32_t* err,
                          uint32_t persistent_blocks, bool any_base, hipStream_t stream,
-                         hipEvent_t ev0, hipEvent_t ev1);
+                         hipEvent_t ev0, hipEvent_t ev1, uint32_t* status_out = nullptr);
 
 // Around the chunk kernel (replay_fold.hip): the plan (chunk prefix per trace,
-// data checks, status word chunk_base[n_traces + 1]), the fold of the chunk summaries of every trace
+// data checks, status word chunk_base[n_traces + 1], ORed into *err and copied
+// to *status_out where those are not null), the fold of the chunk summaries of every trace
 // (fix: optional, receives the level entering each chunk) and the fix-up of the
 // decision bytes of the steps before each chunk's first decisive step.
 hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,
                        const uint32_t* cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
                        uint32_t max_chunks, uint32_t* chunk_base, uint32_t* err,
-                       hipStream_t stream);
+                       hipStream_t stream, uint32_t* status_out = nullptr);
 hipError_t launch_fold(const uint64_t* offsets, uint32_t n_traces, const uint32_t* chunk_base,
                        const ChunkSum* sums, const DevCfg* cfgs, const uint32_t* cfg_of_trace,
                        magus_result* results, ChunkFix* fix, hipStream_t stream);

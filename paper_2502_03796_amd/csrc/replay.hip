@@ -386,11 +386,11 @@ hipError_t launch_replay(const uint32_t* samples, uint64_t n_samples, const uint
                          ChunkSum* sums, uint32_t max_chunks, ChunkFix* fix,
                          magus_result* results, uint8_t* levels, uint32_t* err,
                          uint32_t persistent_blocks, bool any_base, hipStream_t stream,
-                         hipEvent_t ev0, hipEvent_t ev1)
+                         hipEvent_t ev0, hipEvent_t ev1, uint32_t* status_out)
 {
     if (n_traces == 0) return hipSuccess;
     (void)launch_plan(offsets, n_traces, n_samples, cfg_of_trace, n_cfgs, chunk, max_chunks,
-                      chunk_base, err, stream);
+                      chunk_base, err, stream, status_out);
     uint32_t blocks = (max_chunks + kChunkWavesPerBlock - 1) / kChunkWavesPerBlock;
     if (hipError_t e = record_timing_event(ev0, stream); e != hipSuccess) return e;
     auto go = [&](auto levels_tag, auto base_tag) {

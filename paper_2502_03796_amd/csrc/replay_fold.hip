@@ -41,7 +41,8 @@ __device__ __forceinline__ uint64_t low_mask(uint32_t n) {   // n in [0, 64]
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
     const uint64_t* __restrict__ offsets, uint32_t n_traces, uint64_t n_samples,
     const uint32_t* __restrict__ cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
-    uint32_t max_chunks, uint32_t* __restrict__ chunk_base, uint32_t* __restrict__ err)
+    uint32_t max_chunks, uint32_t* __restrict__ chunk_base, uint32_t* __restrict__ err,
+    uint32_t* __restrict__ status_out)
 {
     // Rows of 1,024 consecutive traces; thread i takes trace i of every row,
     // so each load and store of a row is coalesced.  Up to kRows rows (a
@@ -136,7 +137,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(
         if (carry > max_chunks) ee |= kErrOffsets;
         chunk_base[n_traces] = ee ? 0u : carry;
         chunk_base[n_traces + 1] = ee;           // status of this call
-        if (ee) atomicOr(err, ee);
+        if (ee && err) atomicOr(err, ee);        // sticky word of a context
+        if (status_out) *status_out = ee;        // the caller's copy of the status
     }
 }
 
@@ -234,10 +236,11 @@ __global__ __launch_bounds__(256) void fixup_kernel(
 hipError_t launch_plan(const uint64_t* offsets, uint32_t n_traces, uint64_t n_samples,
                        const uint32_t* cfg_of_trace, uint32_t n_cfgs, uint32_t chunk,
                        uint32_t max_chunks, uint32_t* chunk_base, uint32_t* err,
-                       hipStream_t stream)
+                       hipStream_t stream, uint32_t* status_out)
 {
     plan_kernel<<<1, kPlanThreads, 0, stream>>>(offsets, n_traces, n_samples, cfg_of_trace,
-                                                n_cfgs, chunk, max_chunks, chunk_base, err);
+                                                n_cfgs, chunk, max_chunks, chunk_base, err,
+                                                status_out);
     return hipGetLastError();
 }
 

@@ -78,6 +78,39 @@ def test_sweep_shapes_on_the_host():
     assert lib.magus_ctx_get_sweep_shape(None) == 0
 
 
+def test_noalloc_host_limits_without_a_device():
+    """The allocation-free replay checks its arguments and its fixed scratch
+    size on the host, before it touches a device."""
+    lib = magus.load()
+    one = magus.config_array([default_config()])
+    fake = ctypes.c_void_p(256)          # never dereferenced: rejected first
+    # no configs, too many configs, missing buffers
+    assert lib.magus_replay_noalloc(fake, 10, fake, 1, None, 0, None, fake, None, None,
+                                    None) == magus.EINVAL
+    many = magus.config_array([default_config()] * (magus.NOALLOC_MAX_CFGS + 1))
+    assert lib.magus_replay_noalloc(fake, 10, fake, 1, many, len(many), None, fake, None,
+                                    None, None) == magus.EINVAL
+    assert b"at most 16384" in lib.magus_last_error()
+    assert lib.magus_replay_noalloc(fake, 10, None, 1, one, 1, None, fake, None, None,
+                                    None) == magus.EINVAL
+    # a batch whose chunk summaries exceed the 8 MiB array: 2^31 samples in
+    # one trace need 2^19 chunks x 32 B = 16 MiB
+    assert lib.magus_replay_noalloc(fake, 1 << 31, fake, 1, one, 1, None, fake, None, None,
+                                    None) == magus.EINVAL
+    assert b"bytes of scratch" in lib.magus_last_error()
+    # decision bytes need 16 B more per chunk: 3 x 2^28 samples are 196,610
+    # chunks, 6 MiB of summaries (they fit) + 3 MiB of fix-up records (too many)
+    assert lib.magus_replay_noalloc(fake, 3 << 28, fake, 1, one, 1, None, fake, fake, None,
+                                    None) == magus.EINVAL
+    assert b"bytes of scratch" in lib.magus_last_error()
+    # no traces and no status word: only the configs are checked
+    assert lib.magus_replay_noalloc(None, 0, None, 0, one, 1, None, None, None, None,
+                                    None) == magus.OK
+    bad = magus.config_array([default_config(window=1)])
+    assert lib.magus_replay_noalloc(None, 0, None, 0, bad, 1, None, None, None, None,
+                                    None) == magus.EINVAL
+
+
 def test_proxy_struct_layouts_match_header():
     text = open(HEADER).read()
     for cname, pyt, size in (("magus_proxy_model", magus.MagusProxyModel, 272),
