@@ -164,9 +164,12 @@ def bench_sweep(magus, synth, ctx, dev, checks=None, cpu=None):
         "peak_source": "256 CUs x 128 int32 lanes per clock x 2.4 GHz (the lane rate of the "
                        "published 157.3 TFLOP/s fp32 vector peak, 2 flops per FMA)"}
     cnt = stored_sweep_counters()
+    shape_key = f"{tuned['lanes']}x{tuned['tile']}"
+    cnt = cnt.get("shapes", {}).get(shape_key) if cnt else None
     if cnt:
         # the instructions the kernel really issues (rocprofv3 SQ_INSTS_VALU,
-        # wave instructions per launch, taken on the current kernel source)
+        # wave instructions per launch of this launch shape, taken on the
+        # current kernel source)
         issued = cnt["valu_insts_per_launch"] * 64 / kern_s
         res["roofline"]["issued"] = {
             "lane_ops_per_eval": cnt["valu_insts_per_launch"] * 64 / evals,

@@ -159,7 +159,8 @@ __device__ __forceinline__ void for_each_block(const ChunkView& v, uint32_t lane
     const uint32_t first_real = v.s >= 64 ? 1u : 0u;
     const uint32_t nblk = (v.e - v.wbeg + 63) >> 6;
     auto load = [&](uint32_t blk) -> uint32_t {
-        return __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)((blk * 64 + lane) * 4), 0, 0);
+        return __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)((blk * 64 + lane) * 4), 0,
+                                                    kStreamLoad);
     };
     uint64_t fps = 0;
     uint32_t xprev = 0;                 // the last block of the group before

@@ -223,7 +223,8 @@ void proxy_stepped_kernel(
     // group is summed (loads past the chunk's end read 0), the next span's
     // masks while a span is summed
     auto load = [&](uint32_t b) -> uint32_t {
-        return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((b * 64 + lane) * 4), 0, 0);
+        return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((b * 64 + lane) * 4), 0,
+                                                    kStreamLoad);
     };
     // a group of kStepGroup blocks starting at block b, lanes kb.. of the
     // span's masks; a block without a move adds to the run

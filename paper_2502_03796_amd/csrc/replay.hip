@@ -123,7 +123,8 @@ __device__ __forceinline__ void replay_chunk(
     asm volatile("s_mov_b32 %0, 0x10000" : "=s"(k16));
 
     auto load_block = [&](uint32_t desc_blk) -> uint32_t {
-        return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((desc_blk * 64 + lane) * 4), 0, 0);
+        return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)((desc_blk * 64 + lane) * 4), 0,
+                                                    kStreamLoad);
     };
     // Alg. 1 for the 64 steps of a block: masks of the +1 and -1 predictions.
     auto events = [&](uint32_t a, uint32_t b, uint64_t& EU, uint64_t& ED) {
