@@ -152,9 +152,11 @@ uint32_t magus_ctx_get_persistent(const magus_ctx* ctx);
  * graph the first time it sees a given set of arguments (pointers, sizes,
  * config count, chunk and launch shape) and relaunches that graph on later
  * calls with the same set; the config table is uploaded outside the graph.
- * Up to 8 graphs are kept per context.  Kernel timing (below) works inside
- * the graph: two event-record nodes bracket the chunk kernel and each launch
- * points them at that launch's events.
+ * Up to 8 graphs are kept per context, each instantiated 8 times; launches
+ * take the instances in turn.  Kernel timing (below) works inside the
+ * graph: two event-record nodes bracket the chunk kernel, and each instance
+ * records into a pair of events of its own, read when the instance is next
+ * launched or by magus_ctx_kernel_time.
  */
 int magus_ctx_set_graphs(magus_ctx* ctx, int enable);
 

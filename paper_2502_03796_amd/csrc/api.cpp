@@ -147,11 +147,32 @@ magus_ctx::Timing::~Timing() {
     }
 }
 
-void magus_ctx::drop_graphs() {
-    for (auto& e : graphs) {
-        if (e.exec) (void)hipGraphExecDestroy(e.exec);
-        if (e.graph) (void)hipGraphDestroy(e.graph);
+void magus_ctx::harvest(GraphEntry& e, int i) {
+    if (!e.pending[i]) return;
+    e.pending[i] = false;
+    float ms = 0.f;
+    hipError_t err = hipEventSynchronize(e.ev[i][1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e.ev[i][0], e.ev[i][1]);
+    if (err != hipSuccess) {
+        graph_timing_error = err;
+        return;
     }
+    graph_ms += ms;
+    ++graph_launches;
+}
+
+void magus_ctx::destroy_graph(GraphEntry& e) {
+    for (int i = 0; i < kGraphRing; ++i) {
+        harvest(e, i);
+        if (e.exec[i]) (void)hipGraphExecDestroy(e.exec[i]);
+        for (auto ev : e.ev[i])
+            if (ev) (void)hipEventDestroy(ev);
+    }
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+}
+
+void magus_ctx::drop_graphs() {
+    for (auto& e : graphs) destroy_graph(e);
     graphs.clear();
 }
 
@@ -303,6 +324,19 @@ int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t
         ctx->ev_pool.push_back(pr.second);
     }
     ctx->recorded[kernel].clear();
+    if (kernel == MAGUS_KERNEL_REPLAY) {
+        // the graph launches: their instances' own event pairs
+        for (auto& e : ctx->graphs)
+            for (int i = 0; i < magus_ctx::kGraphRing; ++i) ctx->harvest(e, i);
+        sum += ctx->graph_ms;
+        n += ctx->graph_launches;
+        ctx->graph_ms = 0.0;
+        ctx->graph_launches = 0;
+        if (ctx->graph_timing_error != hipSuccess && rc == MAGUS_OK)
+            rc = fail(MAGUS_EDEVICE, "graph event timing: %s",
+                      hipGetErrorString(ctx->graph_timing_error));
+        ctx->graph_timing_error = hipSuccess;
+    }
     *total_ms = sum;
     *launches = n;
     return rc;
@@ -431,8 +465,8 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                              ctx->err.as<uint32_t>(), ctx->persistent_blocks, any_base, q, e0,
                              e1);
     };
-    magus_ctx::Timing tp(ctx, MAGUS_KERNEL_REPLAY);
     if (!ctx->use_graphs) {
+        magus_ctx::Timing tp(ctx, MAGUS_KERNEL_REPLAY);
         HIP_TRY(launch(stream, tp.first, tp.second));
         tp.commit();
         return MAGUS_OK;
@@ -446,21 +480,20 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         (uint64_t)ctx->sums.p, (uint64_t)ctx->fix.p, (uint64_t)stepped, (uint64_t)any_base,
         (uint64_t)ctx->step_funcs.p, (uint64_t)ctx->step_enter.p, (uint64_t)ctx->step_sums.p,
         (uint64_t)ctx->step_masks.p};
-    hipGraphExec_t exec = nullptr;
+    magus_ctx::GraphEntry* entry = nullptr;
     for (size_t i = 0; i < ctx->graphs.size(); ++i)
         if (ctx->graphs[i].key == key) {
-            exec = ctx->graphs[i].exec;
             std::rotate(ctx->graphs.begin() + i, ctx->graphs.begin() + i + 1, ctx->graphs.end());
+            entry = &ctx->graphs.back();       // the hit was rotated to the back
             break;
         }
-    magus_ctx::GraphEntry* entry = nullptr;
-    if (!exec) {
+    if (!entry) {
         if (!ctx->cap_stream)
             HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         for (auto& ev : ctx->graph_ev)
             if (!ev) HIP_TRY(hipEventCreate(&ev));
-        // the chunk kernel is bracketed by two event-record nodes; each
-        // launch points them at the events of that launch
+        // the chunk kernel is bracketed by two event-record nodes; every
+        // instance points them at a pair of events of its own
         std::vector<hipGraphNode_t> marks;
         HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
         magus::capture_marks = &marks;
@@ -482,33 +515,35 @@ int magus_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         magus_ctx::GraphEntry fresh;
         fresh.key = key;
         fresh.graph = graph;
-        fresh.rec[0] = marks[0];
-        fresh.rec[1] = marks[1];
-        const hipError_t ge = hipGraphInstantiate(&fresh.exec, graph, nullptr, nullptr, 0);
+        hipError_t ge = hipSuccess;
+        for (int i = 0; i < magus_ctx::kGraphRing && ge == hipSuccess; ++i) {
+            ge = hipGraphInstantiate(&fresh.exec[i], graph, nullptr, nullptr, 0);
+            for (int k = 0; k < 2 && ge == hipSuccess; ++k) {
+                ge = hipEventCreate(&fresh.ev[i][k]);
+                if (ge == hipSuccess)
+                    ge = hipGraphExecEventRecordNodeSetEvent(fresh.exec[i], marks[k],
+                                                             fresh.ev[i][k]);
+            }
+        }
         if (ge != hipSuccess) {
-            (void)hipGraphDestroy(graph);
+            ctx->destroy_graph(fresh);
             return fail(MAGUS_EDEVICE, "graph instantiate: %s", hipGetErrorString(ge));
         }
         if (ctx->graphs.size() >= 8) {
-            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
-            (void)hipGraphDestroy(ctx->graphs.front().graph);
+            ctx->destroy_graph(ctx->graphs.front());
             ctx->graphs.erase(ctx->graphs.begin());
         }
         ctx->graphs.push_back(fresh);
         entry = &ctx->graphs.back();
-        exec = entry->exec;
-    } else {
-        entry = &ctx->graphs.back();       // the hit was rotated to the back
     }
-    for (int k = 0; k < 2; ++k) {
-        hipEvent_t ev = k == 0 ? tp.first : tp.second;
-        const hipError_t se = hipGraphExecEventRecordNodeSetEvent(exec, entry->rec[k],
-                                                                  ev ? ev : ctx->graph_ev[k]);
-        if (se != hipSuccess)
-            return fail(MAGUS_EDEVICE, "graph timing node %d: %s", k, hipGetErrorString(se));
-    }
-    HIP_TRY(hipGraphLaunch(exec, stream));
-    tp.commit();
+    // the next instance; its previous launch's events are read first if that
+    // launch was timed (by then it has long finished unless the host is a
+    // whole ring of launches ahead)
+    const int i = entry->next;
+    entry->next = (i + 1) % magus_ctx::kGraphRing;
+    ctx->harvest(*entry, i);
+    HIP_TRY(hipGraphLaunch(entry->exec[i], stream));
+    entry->pending[i] = ctx->prof;
     return MAGUS_OK;
 }
 

@@ -83,14 +83,28 @@ struct magus_ctx {
     // hipGraph cache of replay calls
     bool use_graphs = false;
     hipStream_t cap_stream = nullptr;
+    // A captured call is instantiated kGraphRing times; instance i's two
+    // event-record nodes (around the chunk kernel) record into its own pair
+    // of events, set once, and launches take the instances in turn, so no
+    // node is re-pointed per launch.  A launch made while timing is on leaves
+    // its instance `pending` until its pair is read (when the instance is
+    // next launched, or by magus_ctx_kernel_time).
+    static constexpr int kGraphRing = 8;
     struct GraphEntry {
         std::vector<uint64_t> key;
-        hipGraph_t graph = nullptr;             // kept: its record nodes are retargeted
-        hipGraphExec_t exec = nullptr;
-        hipGraphNode_t rec[2] = {nullptr, nullptr};   // event records around the chunk kernel
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec[kGraphRing] = {};
+        hipEvent_t ev[kGraphRing][2] = {};
+        bool pending[kGraphRing] = {};
+        int next = 0;
     };
-    hipEvent_t graph_ev[2] = {nullptr, nullptr};      // record targets while not timing
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};      // record targets during capture
     std::vector<GraphEntry> graphs;          // most recent last
+    double graph_ms = 0.0;                   // timed graph launches read so far
+    uint64_t graph_launches = 0;
+    hipError_t graph_timing_error = hipSuccess;
+    void harvest(GraphEntry& e, int i);      // reads instance i's pair if pending
+    void destroy_graph(GraphEntry& e);
     void drop_graphs();
     // kernel timing: event pairs recorded around the dominant kernel of a call
     bool prof = false;
