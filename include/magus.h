@@ -419,7 +419,9 @@ int magus_proxy_model_check(const magus_proxy_model* model);
 /*
  * Evaluates the proxy for every trace under the controller of magus_replay
  * (same sample, offset and config rules), without materialising per-step
- * levels: configs that jump to the bound take one pass over the samples;
+ * levels: configs that jump to the bound take one pass over the samples (in
+ * time chunks of twice the context's chunk length while that is at most
+ * 8,192 steps, else of the context's length);
  * stepped configs take the stepped replay's first pass (context-owned step
  * masks, 28 B per 64 steps) and one statistics pass over samples and masks.
  *   h_model    the proxy model (host memory, read before return); an invalid

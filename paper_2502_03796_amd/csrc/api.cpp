@@ -14,6 +14,7 @@ namespace magus {
 namespace {
 thread_local std::string g_last_error;
 constexpr uint32_t kDefaultChunk = 4096;
+constexpr uint32_t kProxyChunkMax = 16384;   // longest chunk the fused proxy pass doubles to
 }  // namespace
 
 int fail(int code, const char* fmt, ...) {
@@ -603,16 +604,21 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         // prefix total
         bool mid_init = false;
         for (const DevCfg& d : ctx->cfg_host) mid_init |= d.linit != d.lmin && d.linit != d.lmax;
+        // the fused pass ends each chunk with more per-chunk work than the
+        // replay (seven wave sums): it takes chunks of twice the context's
+        // length up to 16,384 steps
+        const uint32_t pchunk = ctx->chunk <= kProxyChunkMax / 2 ? 2 * ctx->chunk : ctx->chunk;
+        const uint32_t pmax_chunks = (uint32_t)(n_samples / pchunk + n_traces + 1);
         const void* before = ctx->chunk_base.p;
         if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
             (rc = ctx->proxy_sums.ensure((size_t)max_chunks * sizeof(ProxySum))))
             return rc;
         if (ctx->chunk_base.p != before) ctx->drop_graphs();
-        HIP_TRY(launch_plan(d_offsets, n_traces, n_samples, d_cfg_of_trace, n_cfgs, ctx->chunk,
-                            max_chunks, ctx->chunk_base.as<uint32_t>(), ctx->err.as<uint32_t>(),
+        HIP_TRY(launch_plan(d_offsets, n_traces, n_samples, d_cfg_of_trace, n_cfgs, pchunk,
+                            pmax_chunks, ctx->chunk_base.as<uint32_t>(), ctx->err.as<uint32_t>(),
                             stream));
         HIP_TRY(launch_proxy_fused(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
-                                   max_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
+                                   pmax_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, pchunk,
                                    ctx->proxy_model.as<magus_proxy_model>(),
                                    ctx->proxy_sums.as<ProxySum>(), d_stats, d_metrics, any_base,
                                    mid_init, stream));

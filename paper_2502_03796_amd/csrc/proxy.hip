@@ -21,8 +21,8 @@
 //   fused chunk one wave per chunk: Alg. 1 / Alg. 2 per 64-step block, the
 //               block's level bits from the carries of ~DN + UP + level, the
 //               excess sums per level -> ProxySum
-//   fused fold  one wave per trace -> magus_proxy_stats
-//   metrics     as below
+//   fused fold  one wave per trace -> magus_proxy_stats, and the trace's
+//               metrics from the same sums (one lane, as the metrics kernel)
 // Stepped configs take the path over the stepped replay's pass 1 (its step
 // masks and the level entering every chunk, stepped.hip):
 //   zero     clears the statistics (no memset node, so the sequence can be
@@ -309,31 +309,35 @@ __device__ __forceinline__ double stretched(uint64_t steps, uint64_t excess, uin
     return (double)steps + (double)excess / (double)cap;
 }
 
-__global__ __launch_bounds__(256) void proxy_metrics_kernel(
-    const uint64_t* __restrict__ offsets, uint32_t n_traces,
-    const uint32_t* __restrict__ chunk_base, const DevCfg* __restrict__ cfgs,
-    const uint32_t* __restrict__ cfg_of_trace, const magus_proxy_model* __restrict__ model,
-    const magus_proxy_stats* __restrict__ stats, magus_proxy_metrics* __restrict__ out)
+// The seven figures of each policy for one trace from its statistics:
+// level_stats(l, steps, excess) gives level l's intervals and excess sum, in
+// increasing level order (FP64, the same operations in the same order
+// wherever it runs).
+template <class LevelStats>
+__device__ __forceinline__ magus_proxy_metrics metrics_of(const magus_proxy_model* model,
+                                                         const DevCfg& c, uint64_t n,
+                                                         uint64_t excess_max, uint64_t excess_min,
+                                                         LevelStats&& level_stats)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
-    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
-    const magus_proxy_stats& st = stats[t];
-    const uint64_t n = offsets[t + 1] - offsets[t];
     const double dt = (double)model->interval_us * 1e-6;
     const double core = (double)model->core_mw, gpu = (double)model->gpu_mw * 1e-3;
     double T[3], P[3];                       // intervals (stretched), package energy
     T[0] = 0.0;
     P[0] = 0.0;
-    for (uint32_t l = 0; l < model->n_levels; ++l) {
-        if (!st.steps[l]) continue;
-        const double len = stretched(st.steps[l], st.excess[l], model->cap_mbps[l]);
+    const uint32_t n_levels = model->n_levels;
+#pragma unroll
+    for (uint32_t l = 0; l < MAGUS_PROXY_LEVELS; ++l) {
+        if (l >= n_levels) break;
+        uint64_t steps, excess;
+        level_stats(l, steps, excess);
+        if (!steps) continue;
+        const double len = stretched(steps, excess, model->cap_mbps[l]);
         T[0] += len;
         P[0] += len * (core + (double)model->uncore_mw[l]);
     }
-    T[1] = stretched(n, st.excess_max, model->cap_mbps[c.lmax]);
+    T[1] = stretched(n, excess_max, model->cap_mbps[c.lmax]);
     P[1] = T[1] * (core + (double)model->uncore_mw[c.lmax]);
-    T[2] = stretched(n, st.excess_min, model->cap_mbps[c.lmin]);
+    T[2] = stretched(n, excess_min, model->cap_mbps[c.lmin]);
     P[2] = T[2] * (core + (double)model->uncore_mw[c.lmin]);
     magus_proxy_metrics r;
     for (int p = 0; p < 3; ++p) {
@@ -352,7 +356,37 @@ __global__ __launch_bounds__(256) void proxy_metrics_kernel(
         r.energy_saving[p] = 1.0 - r.energy_j[p] / r.energy_j[1];
         r.edp_saving[p] = 1.0 - (r.energy_j[p] * r.time_s[p]) / (r.energy_j[1] * r.time_s[1]);
     }
-    out[t] = r;
+    return r;
+}
+
+// The model copied into LDS by the workgroup (the metrics read it in a
+// dependent chain, each global load of which would be a full memory latency).
+__device__ __forceinline__ const magus_proxy_model* model_to_lds(const magus_proxy_model* model,
+                                                                 magus_proxy_model* s_model) {
+    constexpr uint32_t kWords = sizeof(magus_proxy_model) / 4;
+    for (uint32_t w = threadIdx.x; w < kWords; w += blockDim.x)
+        reinterpret_cast<uint32_t*>(s_model)[w] = reinterpret_cast<const uint32_t*>(model)[w];
+    __syncthreads();
+    return s_model;
+}
+
+__global__ __launch_bounds__(kWave) void proxy_metrics_kernel(
+    const uint64_t* __restrict__ offsets, uint32_t n_traces,
+    const uint32_t* __restrict__ chunk_base, const DevCfg* __restrict__ cfgs,
+    const uint32_t* __restrict__ cfg_of_trace, const magus_proxy_model* __restrict__ model,
+    const magus_proxy_stats* __restrict__ stats, magus_proxy_metrics* __restrict__ out)
+{
+    __shared__ magus_proxy_model s_model;
+    model = model_to_lds(model, &s_model);
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
+    const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
+    const magus_proxy_stats& st = stats[t];
+    out[t] = metrics_of(model, c, offsets[t + 1] - offsets[t], st.excess_max, st.excess_min,
+                        [&](uint32_t l, uint64_t& steps, uint64_t& excess) {
+                            steps = st.steps[l];
+                            excess = st.excess[l];
+                        });
 }
 
 __device__ __forceinline__ uint32_t sat_sub(uint32_t x, uint32_t cap) {
@@ -387,16 +421,333 @@ __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
     return r;
 }
 
-// Fused pass, one wave per chunk (blocks loaded four at a time: the per-lane
-// sums leave fewer registers for loads in flight than the plain replay has).
-// Per lane, running totals of the excess at level_max and level_min over the
-// chunk so far are the only per-step sums: a run of blocks at one level is
-// credited at its end from the difference of its level's total at its two
-// ends, and the steps up to the chunk's first decisive step from the totals
-// at that point (summed over the wave there, once), so a block without a
-// decisive step costs two saturating subtractions and two 64-bit adds.
+// Fused pass, one wave per chunk, in the replay chunk kernel's form: blocks of
+// 64 steps, kProxyIter blocks per unrolled iteration with the next
+// iteration's loads in flight, Alg. 1 as exact compares and Alg. 2 as mbcnt
+// chains on wave masks.  Per lane, running totals of the excess at level_max
+// and level_min (and level_init, kMidInit) over the chunk so far are the only
+// per-step sums.  Everything a decisive block changes lives in LDS, one slot
+// per lane, so a block without a decisive step touches no other register than
+// the totals and the flag history:
+//   level      the level after the last decisive step (kUnseen before the
+//              first)
+//   hacc/lacc  during a run at level_max the excess credited to it is hacc +
+//              (total at level_max), at level_min lacc + (total at
+//              level_min): a run is opened by subtracting its level's total
+//              after the decisive block and closed by adding the total before
+//              the next one (modular arithmetic)
+//   nhi        the count of steps after the prefix at level_max, kept the
+//              same way with step indices (the others are at level_min)
+//   pre        the totals at the first decisive step (lanes up to it
+//              included): the steps whose interval runs at the level entering
+//              the chunk, summed at each level it can be; ppre counts them
 // kMidInit: some config starts between the bounds, so a chunk can also be
 // entered at level_init and its prefix needs a third total.
+//
+// Two widths.  A chunk whose samples are all below 2^24 (every real
+// throughput trace) takes the narrow pass: per-lane sums in 32 bits (at most
+// 256 blocks of excesses below 2^24 per lane, so the true per-lane values fit
+// and modular intermediates are harmless) and, with the default base, the
+// Alg. 1 compares in fp32 (below).  64-bit integer operations issue at half
+// the rate of 32-bit ones on this chip, and the pass is bound by VALU issue.
+// The narrow pass tracks the largest sample it read; a chunk that had one of
+// 2^24 or more is run again by the exact 64-bit pass, which is also taken
+// when the thresholds or the chunk length rule the narrow pass out.
+#ifndef MAGUS_PROXY_ITER
+#define MAGUS_PROXY_ITER 8
+#endif
+constexpr uint32_t kProxyIter = MAGUS_PROXY_ITER;
+constexpr uint32_t kUnseen = 2;
+constexpr uint32_t kNarrowBound = 1u << 24;      // samples and thresholds below: narrow pass
+constexpr uint32_t kNarrowChunk = 256 * 64;      // steps per chunk the narrow sums allow
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+constexpr uint32_t kSlots = kStatsWaves * kWave;
+
+// The decisive-block state of the waves of a workgroup (one slot per lane).
+struct ProxyLds {
+    uint64_t hacc[kSlots], lacc[kSlots], pre[3][kSlots];
+    uint32_t level[kSlots], nhi[kSlots], ppre[kSlots];
+};
+
+// Alg. 1 with the default base in fp32: a rise is an event iff
+// b 2^16 - a (2^16 + W q_inc) > 0, evaluated as fma(a, -ku, b 2^16).  With a,
+// b and ku below 2^24 every operand is an exact float (b 2^16 too), the fma
+// forms the product and the sum exactly and rounds once, and rounding keeps
+// the sign of an integer: the compare is exact.  The same for a fall with the
+// roles of a and b swapped.
+__device__ __forceinline__ bool rise_f32(float a, float b16, float nku) {
+    return __builtin_fmaf(a, nku, b16) > 0.0f;
+}
+
+template <bool kAnyBase, bool kMidInit, bool kNarrow>
+__device__ __forceinline__ bool proxy_pass(const ChunkView& v, uint32_t lane, uint32_t slot,
+                                           uint32_t g, const magus_proxy_model* __restrict__ model,
+                                           ProxySum* __restrict__ psums, ProxyLds& L)
+{
+    using acc_t = std::conditional_t<kNarrow, uint32_t, uint64_t>;
+    using lds_acc = std::conditional_t<kNarrow, lds_u32, lds_u64>;
+    constexpr bool kF32 = kNarrow && !kAnyBase;
+    // (volatile LDS pointers: the compiler must not forward these through
+    // registers, which would put the state back into the loop's merge points,
+    // nor move the narrow pass's 32-bit accesses past the exact pass's 64-bit
+    // ones to the same bytes)
+    // A lane's 64-bit slot holds its narrow sums in its low word (the same
+    // bytes for both widths: the waves of a workgroup never overlap).
+    volatile lds_acc* s_hacc = (volatile lds_acc*)(L.hacc + slot);
+    volatile lds_acc* s_lacc = (volatile lds_acc*)(L.lacc + slot);
+    volatile lds_acc* s_pre0 = (volatile lds_acc*)(L.pre[0] + slot);
+    volatile lds_acc* s_pre1 = (volatile lds_acc*)(L.pre[1] + slot);
+    volatile lds_acc* s_pre2 = (volatile lds_acc*)(L.pre[2] + slot);
+    volatile lds_u32* s_level = (volatile lds_u32*)(L.level + slot);
+    volatile lds_u32* s_nhi = (volatile lds_u32*)(L.nhi + slot);
+    volatile lds_u32* s_ppre = (volatile lds_u32*)(L.ppre + slot);
+
+    const DevCfg& c = v.c;
+    const uint32_t W = c.W, H = c.H;
+    const uint32_t c_lo = model->cap_mbps[c.lmin], c_hi = model->cap_mbps[c.lmax];
+    const uint32_t c_in = model->cap_mbps[c.linit];
+    const uint32_t s = v.s, e = v.e;
+    const uint32_t first_real = s >= 64 ? 1u : 0u;
+    const uint32_t nreal = (e - s + 63) >> 6;            // real blocks, last may be partial
+    const uint32_t nfull = (e - s) >> 6;                 // real blocks with 64 valid steps
+    const uint32_t n_iter = (nreal + kProxyIter - 1) / kProxyIter;
+
+    // per-lane constants (as in the replay chunk kernel)
+    const int bperm_addr = (int)(((lane - (W - 1)) & 63u) << 2);  // lane of x[t-W+1]
+    const bool from_cur = lane >= W - 1;
+    const uint32_t bias_lane = 0x80000000u - (c.thr + lane);
+    const uint64_t loud = c.thr == 0 ? 1ull : 0ull;
+    uint32_t mu;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(mu) : "s"(c.mu));
+    const uint32_t md = c.md;
+    const uint32_t ku = 65536u + c.mu, kd = 65536u + c.md;
+    const uint32_t k16 = v.k16;
+    const float nku = -(float)ku, nkd = -(float)kd;
+
+    auto load_block = [&](uint32_t desc_blk) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(v.rsrc, (int)((desc_blk * 64 + lane) * 4), 0,
+                                                    kStreamLoad);
+    };
+    // the value exchanged for x[t-W+1]: the sample, or its float in the fp32 form
+    auto xchg = [&](uint32_t x) -> uint32_t {
+        if constexpr (kF32) return __float_as_uint((float)x);
+        else return x;
+    };
+    // Alg. 1 for the 64 steps of a block: masks of the +1 and -1 predictions
+    // (a: x[t-W+1] as exchanged, b: x[t])
+    auto events = [&](uint32_t a, uint32_t b, uint64_t& EU, uint64_t& ED) {
+        if constexpr (kAnyBase) {
+            const bool rising = b > a;
+            const uint32_t lov = derivative_base(a, b, c.base, c.ref);
+            const uint32_t d = max(a, b) - min(a, b);
+            const uint32_t m = rising ? mu : md;
+            const uint64_t E = lane_ballot(((uint64_t)d << 16) > (uint64_t)lov * m);
+            const uint64_t R = lane_ballot(rising);
+            EU = E & R;
+            ED = E & ~R;
+        } else if constexpr (kF32) {
+            const float af = __uint_as_float(a), bf = (float)b;
+            EU = lane_ballot(rise_f32(af, bf * 65536.0f, nku));
+            ED = lane_ballot(rise_f32(bf, af * 65536.0f, nkd));
+        } else {
+            EU = lane_ballot((uint64_t)b * k16 > (uint64_t)a * ku);
+            ED = lane_ballot((uint64_t)a * k16 > (uint64_t)b * kd);
+        }
+    };
+
+    *s_hacc = 0;
+    *s_lacc = 0;
+    *s_level = kUnseen;
+    *s_nhi = 0;
+
+    uint32_t xp = 0;             // exchanged values of the block before the current one
+    uint64_t fps = 0;            // (flags of the block before) >> 1
+    uint32_t vmax = 0;           // largest sample read (narrow pass)
+    if (first_real) {
+        const uint32_t x0 = load_block(0);
+        if constexpr (kNarrow) vmax = x0;
+        const uint32_t x0x = xchg(x0);
+        const uint32_t ac = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)x0x);
+        uint64_t EU, ED;
+        events(from_cur ? ac : xchg(0u), x0, EU, ED);
+        uint64_t E = EU | ED;
+        const uint32_t tb = s - 64;
+        if (tb < W - 1) E &= ~mask_below(W - 1 - tb);     // FIFO not yet full
+        fps = E >> 1;
+        xp = x0x;
+    }
+
+    acc_t a_max = 0, a_min = 0, a_in = 0;       // totals of the chunk so far (per lane)
+
+    // A block with a decisive step (UP: high or +1 executed, level_max after
+    // the step; DN: -1 executed, level_min after; D = UP | DN): the totals
+    // do not yet hold this block.
+    auto decisive = [&](uint32_t tb, uint64_t valid, uint64_t UP, uint64_t DN, uint64_t D,
+                        uint32_t e_hi, uint32_t e_lo, uint32_t x) {
+        const uint32_t lvl = uniform(*s_level);
+        acc_t ha = *s_hacc, la = *s_lacc;
+        uint32_t nh = *s_nhi;
+        uint64_t det = valid;                            // steps summed by their own level
+        if (lvl == kUnseen) {
+            // the chunk's first decisive step p: the steps up to it run at the
+            // level entering the chunk
+            const uint32_t p = (uint32_t)__builtin_ctzll(D);
+            const uint64_t in = mask_below(p + 1);
+            *s_ppre = tb + p + 1 - s;
+            *s_pre0 = a_min + lane_sel(in, e_lo);
+            *s_pre1 = a_max + lane_sel(in, e_hi);
+            if constexpr (kMidInit) *s_pre2 = a_in + lane_sel(in, sat_sub(x, c_in));
+            det &= ~in;
+        } else if (lvl) {                                // close the run at level_max
+            ha += a_max;
+            nh += tb;
+        } else {                                         // ... at level_min
+            la += a_min;
+        }
+        // level bit before each step: the carries into the bits of
+        // ~DN + UP + level (UP generates, DN kills; past the first decisive
+        // step they do not depend on the level entering the block)
+        uint32_t cout;
+        const uint64_t C = carries_into(~DN, UP, lvl & 1u, cout);
+        const uint64_t hi_m = C & det;
+        ha += lane_sel(hi_m, e_hi);
+        la += lane_sel(det & ~C, e_lo);
+        nh += (uint32_t)__builtin_popcountll(hi_m);
+        // open the run after the block at the level its last decisive step set
+        if (cout) {
+            ha -= a_max + e_hi;
+            nh -= min(tb + 64, e);
+        } else {
+            la -= a_min + e_lo;
+        }
+        *s_level = cout;
+        *s_hacc = ha;
+        *s_lacc = la;
+        *s_nhi = nh;
+    };
+
+    auto iteration = [&](uint32_t it, uint32_t (&cur)[kProxyIter], uint32_t (&nxt)[kProxyIter],
+                         auto generic_tag) {
+        constexpr bool generic = decltype(generic_tag)::value;
+        if (it + 1 < n_iter) {
+#pragma unroll
+            for (uint32_t j = 0; j < kProxyIter; ++j)
+                nxt[j] = load_block(first_real + (it + 1) * kProxyIter + j);
+        }
+        uint32_t xx[kProxyIter], ac[kProxyIter], ap[kProxyIter];
+#pragma unroll
+        for (uint32_t j = 0; j < kProxyIter; ++j) xx[j] = xchg(cur[j]);
+#pragma unroll
+        for (uint32_t j = 0; j < kProxyIter; ++j) {
+            ac[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)xx[j]);
+            ap[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(bperm_addr, (int)(j ? xx[j - 1] : xp));
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kProxyIter; ++j) {
+            const uint32_t x = cur[j];
+            const uint32_t tb = s + (it * kProxyIter + j) * 64;     // trace step of lane 0
+            if constexpr (kNarrow) vmax = max(vmax, x);
+            uint64_t PU, PD;
+            events(from_cur ? ac[j] : ap[j], x, PU, PD);
+            uint64_t valid = ~0ull;
+            if constexpr (generic) {
+                valid = mask_below(tb < e ? min(64u, e - tb) : 0u);
+                uint64_t vm = valid;
+                if (tb < W - 1) vm &= ~mask_below(W - 1 - tb);
+                PU &= vm;
+                PD &= vm;
+            }
+            const uint64_t E = PU | PD;
+            const uint64_t B = fps >> (64 - H);           // last H-1 flags of the block before
+            // lanes past the chunk's end read 0: no excess
+            const uint32_t e_hi = sat_sub(x, c_hi), e_lo = sat_sub(x, c_lo);
+            // a quiet block (no event in it nor in the H-1 steps before it,
+            // and a non-zero count threshold) is never high and has no
+            // decisive step
+            if ((E | B | loud) != 0) {
+                const uint64_t nG = ~((E << (H - 1)) | B);    // ~(flag H-1 steps back)
+                const uint32_t acc0 = (uint32_t)__popcll(B) + (uint32_t)(E & 1ull);
+                const uint32_t cnt = bits_below_lane(nG, bits_below_lane(E >> 1, bias_lane));
+                const uint64_t HM = lane_ballot(cnt >= 0x80000000u - acc0) & valid;
+                const uint64_t UP = HM | PU;                  // high or +1 -> max
+                const uint64_t DN = PD & ~HM;                 // -1 executed -> min
+                const uint64_t D = UP | DN;
+                if (D != 0) decisive(tb, valid, UP, DN, D, e_hi, e_lo, x);
+            }
+            fps = E >> 1;
+            a_max += e_hi;
+            a_min += e_lo;
+            if constexpr (kMidInit) a_in += sat_sub(x, c_in);
+        }
+        xp = xx[kProxyIter - 1];
+    };
+
+    // the first iteration of a trace and the iterations reaching past the
+    // last full block need per-step masks; all others take the unmasked path
+    auto run = [&](uint32_t it, uint32_t (&cur)[kProxyIter], uint32_t (&nxt)[kProxyIter]) {
+        if ((it == 0 && first_real == 0) || (it + 1) * kProxyIter > nfull)
+            iteration(it, cur, nxt, std::true_type{});
+        else
+            iteration(it, cur, nxt, std::false_type{});
+    };
+    uint32_t bufA[kProxyIter], bufB[kProxyIter];
+#pragma unroll
+    for (uint32_t j = 0; j < kProxyIter; ++j) bufA[j] = load_block(first_real + j);
+    for (uint32_t it = 0; it < n_iter; it += 2) {
+        run(it, bufA, bufB);
+        if (it + 1 < n_iter) run(it + 1, bufB, bufA);
+    }
+    if constexpr (kNarrow) {
+        if (lane_ballot(vmax >= kNarrowBound)) return false;   // the exact pass takes it
+    }
+
+    const uint32_t lvl = uniform(*s_level);
+    uint64_t ha = (acc_t)*s_hacc, la = (acc_t)*s_lacc;
+    uint32_t nh = *s_nhi, ppre = e - s;
+    uint64_t pre0, pre1, pre2 = 0;
+    if (lvl == kUnseen) {
+        // no decisive step: the whole chunk runs at the entering level
+        pre0 = dpp_wave_sum64(a_min);
+        pre1 = dpp_wave_sum64(a_max);
+        if constexpr (kMidInit) pre2 = dpp_wave_sum64(a_in);
+    } else {
+        ppre = *s_ppre;
+        pre0 = dpp_wave_sum64((acc_t)*s_pre0);
+        pre1 = dpp_wave_sum64((acc_t)*s_pre1);
+        if constexpr (kMidInit) pre2 = dpp_wave_sum64((acc_t)*s_pre2);
+        if (lvl) {                                       // close the last run
+            ha = (acc_t)(ha + a_max);
+            nh += e;
+        } else {
+            la = (acc_t)(la + a_min);
+        }
+    }
+    if constexpr (!kMidInit) pre2 = c.linit == c.lmax ? pre1 : pre0;
+    ha = dpp_wave_sum64(ha);
+    la = dpp_wave_sum64(la);
+    const uint64_t ex_max = dpp_wave_sum64(a_max);
+    const uint64_t ex_min = dpp_wave_sum64(a_min);
+    if (lane == 0) {
+        ProxySum r;
+        r.len = e - s;
+        r.ppre = ppre;
+        r.has_dec = lvl == kUnseen ? 0u : 1u;
+        r.end_up = lvl == 1u ? 1u : 0u;
+        r.n_lo = e - s - ppre - nh;
+        r.n_hi = nh;
+        r.pre_x[0] = pre0;
+        r.pre_x[1] = pre1;
+        r.pre_x[2] = pre2;
+        r.x_lo = la;
+        r.x_hi = ha;
+        r.ex_max = ex_max;
+        r.ex_min = ex_min;
+        psums[g] = r;
+    }
+    return true;
+}
+
 template <bool kAnyBase, bool kMidInit>
 __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
@@ -404,121 +755,32 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
     uint32_t chunk, const magus_proxy_model* __restrict__ model, ProxySum* __restrict__ psums)
 {
+    __shared__ ProxyLds L;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t g = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
     if (chunk_base[n_traces + 1] != 0 || g >= chunk_base[n_traces]) return;
     const ChunkView v = chunk_view(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
                                    chunk, g);
-    const uint32_t c_lo = model->cap_mbps[v.c.lmin], c_hi = model->cap_mbps[v.c.lmax];
-    const uint32_t c_in = model->cap_mbps[v.c.linit];
-    uint64_t a_max = 0, a_min = 0;   // totals of the chunk so far (per lane)
-    uint64_t mark = 0;               // the current run's level total where it began
-    uint64_t a_in = 0;               // total at level_init before the first decisive step
-    uint64_t a_lo = 0, a_hi = 0;     // steps after the prefix, by level
-    uint64_t pre0 = 0, pre1 = 0, pre2 = 0;   // prefix at min, max, init (wave sums)
-    uint32_t n_lo = 0, n_hi = 0;
-    bool seen = false;          // a decisive step earlier in this chunk
-    uint32_t ppre = v.e - v.s;  // steps up to and including the first decisive step
-    uint32_t lvl = 0;           // level bit after the last step (once seen)
-    uint32_t run0 = v.s;        // first step of the current run
-    for_each_block<4, kAnyBase>(v, lane, [&](const BlockMasks& m, uint32_t tb, uint64_t valid,
-                                             uint32_t x) {
-        const uint32_t e_hi = sat_sub(x, c_hi), e_lo = sat_sub(x, c_lo);
-        if ((m.E | m.HM) == 0) {
-            // no decisive step: the block runs at the level it was entered at
-            a_max += e_hi;                               // lanes past the end read 0
-            a_min += e_lo;
-            if (kMidInit && !seen) a_in += sat_sub(x, c_in);
-            return;
-        }
-        const uint64_t UP = m.HM | (m.E & m.R);          // high or +1 -> max
-        const uint64_t DN = m.E & ~(m.R | m.HM);         // -1 executed -> min
-        const uint64_t D = UP | DN;
-        uint64_t det = valid;
-        if (seen) {
-            // the run since the last decisive block, at level lvl
-            if (lvl) {
-                a_hi += a_max - mark;
-                n_hi += tb - run0;
-            } else {
-                a_lo += a_min - mark;
-                n_lo += tb - run0;
-            }
-        } else {
-            // steps up to and including the first decisive one run at the
-            // level entering the chunk: the totals so far plus this block's
-            // lanes up to it, at each level the chunk can be entered at
-            const uint32_t p = (uint32_t)__builtin_ctzll(D);
-            const uint64_t in = mask_below(p + 1);
-            ppre = tb + p + 1 - v.s;
-            pre0 = dpp_wave_sum64(a_min + lane_sel(in, e_lo));
-            pre1 = dpp_wave_sum64(a_max + lane_sel(in, e_hi));
-            if (kMidInit) pre2 = dpp_wave_sum64(a_in + lane_sel(in, sat_sub(x, c_in)));
-            det &= ~in;
-            seen = true;
-        }
-        a_max += e_hi;
-        a_min += e_lo;
-        // level bit before each step: the carries into the bits of
-        // ~DN + UP + lvl (UP generates, DN kills)
-        uint32_t cout;
-        const uint64_t C = carries_into(~DN, UP, lvl, cout);
-        const uint64_t hi_m = C & det, lo_m = det & ~C;
-        n_hi += (uint32_t)__builtin_popcountll(hi_m);
-        n_lo += (uint32_t)__builtin_popcountll(lo_m);
-        a_hi += lane_sel(hi_m, e_hi);
-        a_lo += lane_sel(lo_m, e_lo);
-        lvl = cout;                                      // level after the block's last step
-        mark = lvl ? a_max : a_min;
-        run0 = tb + 64;
-    });
-    if (seen) {
-        if (lvl) {
-            a_hi += a_max - mark;
-            n_hi += v.e > run0 ? v.e - run0 : 0u;
-        } else {
-            a_lo += a_min - mark;
-            n_lo += v.e > run0 ? v.e - run0 : 0u;
-        }
-    }
-    a_lo = dpp_wave_sum64(a_lo);
-    a_hi = dpp_wave_sum64(a_hi);
-    a_max = dpp_wave_sum64(a_max);
-    a_min = dpp_wave_sum64(a_min);
-    if (!seen) {
-        // no decisive step: the whole chunk runs at the entering level
-        pre0 = a_min;
-        pre1 = a_max;
-        if (kMidInit) pre2 = dpp_wave_sum64(a_in);
-    }
-    if (!kMidInit) pre2 = v.c.linit == v.c.lmax ? pre1 : pre0;
-    if (lane == 0) {
-        ProxySum r;
-        r.len = v.e - v.s;
-        r.ppre = ppre;
-        r.has_dec = seen ? 1u : 0u;
-        r.end_up = (uint32_t)lvl;
-        r.n_lo = n_lo;
-        r.n_hi = n_hi;
-        r.pre_x[0] = pre0;
-        r.pre_x[1] = pre1;
-        r.pre_x[2] = pre2;
-        r.x_lo = a_lo;
-        r.x_hi = a_hi;
-        r.ex_max = a_max;
-        r.ex_min = a_min;
-        psums[g] = r;
-    }
+    const bool narrow = chunk <= kNarrowChunk &&
+                        (kAnyBase || (65536u + v.c.mu <= kNarrowBound &&
+                                      65536u + v.c.md <= kNarrowBound));
+    if (narrow &&
+        proxy_pass<kAnyBase, kMidInit, true>(v, lane, threadIdx.x, g, model, psums, L))
+        return;
+    proxy_pass<kAnyBase, kMidInit, false>(v, lane, threadIdx.x, g, model, psums, L);
 }
 
 // Fused fold, one wave per trace; lane j takes chunk j of each group of 64.
 // The level entering chunk j is the end level of the last earlier chunk with
 // a decisive step (else the group's entering level, level_init at the start).
 __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
-    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    uint32_t n_traces, const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ chunk_base,
     const ProxySum* __restrict__ psums, const DevCfg* __restrict__ cfgs,
-    const uint32_t* __restrict__ cfg_of_trace, magus_proxy_stats* __restrict__ stats)
+    const uint32_t* __restrict__ cfg_of_trace, const magus_proxy_model* __restrict__ model,
+    magus_proxy_stats* __restrict__ stats, magus_proxy_metrics* __restrict__ metrics)
 {
+    __shared__ magus_proxy_model s_model;
+    if (metrics) model = model_to_lds(model, &s_model);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
     if (t >= n_traces) return;
@@ -575,6 +837,23 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
     x2 = dpp_wave_sum64(x2);
     emax = dpp_wave_sum64(emax);
     emin = dpp_wave_sum64(emin);
+    // level l's intervals and excess: the bins of level_min, level_max and a
+    // level_init between them
+    auto level_stats = [&](uint32_t l, uint64_t& steps, uint64_t& excess) {
+        steps = excess = 0;
+        if (l == lmin) {
+            steps += n0;
+            excess += x0;
+        }
+        if (l == lmax) {
+            steps += n1;
+            excess += x1;
+        }
+        if (l == linit && linit != lmin && linit != lmax) {
+            steps += n2;
+            excess += x2;
+        }
+    };
     // every word of the trace's stats: 0 excess_max, 1 excess_min,
     // 2 + l steps[l], 2 + 32 + l excess[l]
     for (uint32_t w = lane; w < kWords; w += 64) {
@@ -585,14 +864,15 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
             val = emin;
         } else {
             const bool is_n = w < 2 + MAGUS_PROXY_LEVELS;
-            const uint32_t l = is_n ? w - 2 : w - 2 - MAGUS_PROXY_LEVELS;
-            val = 0;
-            if (l == lmin) val += is_n ? n0 : x0;
-            if (l == lmax) val += is_n ? n1 : x1;
-            if (l == linit && linit != lmin && linit != lmax) val += is_n ? n2 : x2;
+            uint64_t steps, excess;
+            level_stats(is_n ? w - 2 : w - 2 - MAGUS_PROXY_LEVELS, steps, excess);
+            val = is_n ? steps : excess;
         }
         out[w] = val;
     }
+    // the metrics from the same sums, by one lane
+    if (metrics && lane == 0)
+        metrics[t] = metrics_of(model, c, offsets[t + 1] - offsets[t], emax, emin, level_stats);
 }
 
 }  // namespace
@@ -615,7 +895,7 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
             samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, masks,
             stepped_mask_blocks(n_samples, n_traces), model, stats);
     if (metrics)
-        proxy_metrics_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
+        proxy_metrics_kernel<<<(n_traces + kWave - 1) / kWave, kWave, 0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);
     return hipGetLastError();
 }
@@ -638,10 +918,8 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
                                                       cfgs, cfg_of_trace, chunk, model, psums);
     }
     proxy_fold_kernel<<<(n_traces + kStatsWaves - 1) / kStatsWaves, kStatsWaves * kWave, 0,
-                        stream>>>(n_traces, chunk_base, psums, cfgs, cfg_of_trace, stats);
-    if (metrics)
-        proxy_metrics_kernel<<<(n_traces + 255) / 256, 256, 0, stream>>>(
-            offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);
+                        stream>>>(n_traces, offsets, chunk_base, psums, cfgs, cfg_of_trace, model,
+                                  stats, metrics);
     return hipGetLastError();
 }
 

@@ -27,8 +27,9 @@ static_assert(sizeof(ProxySum) == 80, "ProxySum layout");
 // Fused proxy pass for batches whose configs all jump to the bound: one read
 // of the samples per step after the plan (chunk_base from launch_plan),
 // per-chunk summaries into psums (max_chunks), one wave per trace folds them
-// into stats, and metrics (optional) follow.  For a batch the plan rejected
-// the fold writes zero statistics and metrics are not written.
+// into stats and derives the metrics (optional) from the same sums.  For a
+// batch the plan rejected the fold writes zero statistics and metrics are not
+// written.
 hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
                               const uint32_t* chunk_base, uint32_t max_chunks,
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,

@@ -194,6 +194,71 @@ def test_full_range_samples(ctx, oracle_mod):
     check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
 
 
+def _alg1_boundary_trace(seed, ku, kd, n_pairs=3000):
+    """Pairs (a, b) on both sides of the Alg. 1 thresholds with window 2:
+    b 2^16 - a ku within a few 2^16 of 0 (and exactly 0 for a quarter of them)
+    for rises, a 2^16 - b kd likewise for falls; every sample below 2^24 but
+    large enough that a float product of either side would be off by far
+    more than one."""
+    rng = np.random.default_rng(seed)
+    lim = 1 << 24
+    out = []
+    for _ in range(n_pairs):
+        lo = int(rng.integers(1 << 22, (lim * 65536) // max(ku, kd) - 4))
+        if rng.integers(0, 4) == 0:
+            lo -= lo % 65536                              # a product that is a multiple of 2^16
+        delta = int(rng.integers(-2, 3))
+        if rng.integers(0, 2):
+            a = lo                                        # rise: b near a ku / 2^16
+            b = (a * ku) // 65536 + (delta if (a * ku) % 65536 else 0)
+        else:
+            b = lo                                        # fall: a near b kd / 2^16
+            a = (b * kd) // 65536 + (delta if (b * kd) % 65536 else 0)
+        out += [min(max(a, 0), lim - 1), min(max(b, 0), lim - 1)]
+    return np.array(out, np.uint32)
+
+
+@pytest.mark.parametrize("chunk", [256, 4096, 16384, 32768])
+def test_narrow_pass_boundaries(ctx, oracle_mod, chunk):
+    """The fused pass on samples just below 2^24, where it takes its 32-bit
+    form with the fp32 Alg. 1 compares: exact-boundary pairs for rises and
+    falls; a chunk that holds one sample of 2^24 (run again by the exact
+    pass) between chunks that do not; all samples at 2^24 - 1 with a cap of
+    1 (the largest 32-bit per-lane sums, 256 blocks a lane at chunk 16,384);
+    thresholds whose 2^16 + W q is 2^24 (still narrow) and above it (exact
+    only); and chunk lengths past the narrow pass's limit."""
+    lim = 1 << 24
+    cfg_a = default_config(window=2, hold=4)
+    cfg_b = default_config(window=16, hold=3, inc_q16=(lim - 65536) // 16,
+                           dec_q16=-((lim - 65536) // 16))       # 2^16 + W q = 2^24
+    cfg_c = default_config(window=16, hold=3, inc_q16=(lim - 65536) // 16 + 1,
+                           dec_q16=-3000)                        # above: exact pass only
+    cfg_d = default_config(window=4, hold=10, level_init=5)
+    cfgs = [cfg_a, cfg_b, cfg_c, cfg_d]
+    ku = 65536 + 2 * cfg_a["inc_q16"]
+    kd = 65536 - 2 * cfg_a["dec_q16"]
+    one_big = np.full(3 * chunk + 77, lim - 2, np.uint32)
+    one_big[chunk + chunk // 2] = lim                            # middle chunk only
+    one_big[::7] = 1000
+    traces = [_alg1_boundary_trace(chunk, ku, kd),
+              _alg1_boundary_trace(chunk + 1, ku, kd, 500),
+              one_big,
+              np.full(2 * chunk + 64, lim - 1, np.uint32),
+              np.array([lim - 1, 0] * (chunk // 2 + 40), np.uint32),
+              mixed_traces(chunk, [5000])[0]]
+    cot = np.array([0, 1, 0, 3, 2, 3], np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    model = dict(proxy_model(), cap_mbps=[1] + proxy_model()["cap_mbps"][1:])
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, cfgs, model, c)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
+
+
 def test_rejects_levels_the_model_does_not_describe(ctx):
     samples, offsets = synth.make_batch([np.ones(10, np.uint32)])
     s, o, _ = to_dev(samples, offsets)
