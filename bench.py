@@ -745,14 +745,37 @@ def main():
         amax_ms = torch_ms(lambda: torch.amax(s))
         copy_ms = torch_ms(lambda: dst.copy_(s))
         del dst
+        # the chunk kernel's own access pattern with no arithmetic
+        # (magus_read_probe), timed by the library's events
+        probe_out = ctx.read_probe(s, ctx.chunk)
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        ctx.kernel_time(magus.KERNEL_PROBE)
+        for _ in range(10):
+            ctx.read_probe(s, ctx.chunk, out=probe_out)
+        torch.cuda.synchronize()
+        ctx.set_profiling(False)
+        pms, pn = ctx.kernel_time(magus.KERNEL_PROBE)
+        probe_ms = pms / pn
+        del probe_out
         extra["read_reference"] = {
             "amax": {"kernel": "torch.amax over the bulk samples", "ms": amax_ms,
                      "read_gb_per_s": bytes_per_launch / amax_ms / 1e6},
             "copy": {"kernel": "device copy of the bulk samples", "ms": copy_ms,
-                     "read_plus_write_gb_per_s": 2 * bytes_per_launch / copy_ms / 1e6}}
+                     "read_plus_write_gb_per_s": 2 * bytes_per_launch / copy_ms / 1e6},
+            "read_probe": {"kernel": "magus_read_probe: the chunk kernel's loads (one wave per "
+                                     f"{ctx.chunk}-step chunk, 8 blocks in flight, non-temporal) "
+                                     "with no other work",
+                           "ms": probe_ms, "read_gb_per_s": bytes_per_launch / probe_ms / 1e6,
+                           "frac_of_peak": bytes_per_launch / probe_ms / 1e6 / HBM_PEAK_GBS,
+                           "chunk_kernel_frac_of_probe": probe_ms / avg_kernel_ms
+                           if avg_kernel_ms else None}}
         log(f"  torch.amax over the same bytes: {amax_ms:.4f} ms "
             f"({bytes_per_launch / amax_ms / 1e6:.0f} GB/s); device copy {copy_ms:.4f} ms "
             f"({2 * bytes_per_launch / copy_ms / 1e6:.0f} GB/s read + write)")
+        log(f"  read probe (the chunk kernel's loads alone): {probe_ms:.4f} ms "
+            f"({bytes_per_launch / probe_ms / 1e6:.0f} GB/s); the chunk kernel runs at "
+            f"{probe_ms / avg_kernel_ms:.1%} of it" if avg_kernel_ms else "")
 
         bench_stepped(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, pick, args,
                       dev, extra, checks)

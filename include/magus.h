@@ -187,14 +187,14 @@ int magus_autotune_replay(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_
  * its stream right before and after its dominant kernel (MAGUS_KERNEL_REPLAY:
  * the chunk kernel of magus_replay; MAGUS_KERNEL_SWEEP: the sweep kernel;
  * MAGUS_KERNEL_SERVE: the serve-step kernel of a server on this context;
- * MAGUS_KERNEL_PROBE: the kernel of magus_valu_probe).
+ * MAGUS_KERNEL_PROBE: the kernel of magus_valu_probe or magus_read_probe).
  * magus_ctx_kernel_time waits for the recorded events, returns the summed
  * elapsed time and the number of launches since its last call, and resets.
  */
 #define MAGUS_KERNEL_REPLAY 0
 #define MAGUS_KERNEL_SWEEP 1
 #define MAGUS_KERNEL_SERVE 2
-#define MAGUS_KERNEL_PROBE 3   /* the VALU issue probe below */
+#define MAGUS_KERNEL_PROBE 3   /* the VALU issue and read probes below */
 int magus_ctx_set_profiling(magus_ctx* ctx, int enable);
 int magus_ctx_kernel_time(magus_ctx* ctx, int kernel, double* total_ms, uint64_t* launches);
 
@@ -343,6 +343,23 @@ int magus_autotune_sweep(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_s
  */
 int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32_t mode,
                      uint32_t* d_out, uint64_t* h_lane_ops, hipStream_t stream);
+
+/*
+ * Measurement aid: the streaming-read rate of the replay chunk kernel's
+ * access pattern with no other work.  One wavefront per chunk of
+ * `chunk_steps` samples of d_samples (device memory, n_samples uint32) loads
+ * one dword per lane per 64-sample block, eight blocks at a time with the
+ * next eight in flight (non-temporal loads), and folds them into one word.
+ * n_samples / time is the practical read ceiling the chunk kernel's HBM rate
+ * is compared with.  With kernel timing on, the launch is timed as
+ * MAGUS_KERNEL_PROBE.
+ *   chunk_steps  a multiple of 64 in 64..2^24.
+ *   d_out        ceil(n_samples / chunk_steps) uint32 (written; values have no
+ *                meaning beyond keeping the loads alive).
+ * MAGUS_EINVAL on a NULL buffer with n_samples > 0 or a chunk out of range.
+ */
+int magus_read_probe(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                     uint32_t chunk_steps, uint32_t* d_out, hipStream_t stream);
 
 /*
  * Monitor front end (Sec. 3, Sec. 4: memory throughput is read periodically

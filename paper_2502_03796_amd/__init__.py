@@ -142,6 +142,7 @@ SIGNATURES = {
                                             ctypes.POINTER(MagusSweepTuneResult)]),
     "magus_valu_probe": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                         _P, ctypes.POINTER(ctypes.c_uint64), _P]),
+    "magus_read_probe": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P]),
     "magus_counters_to_mbps": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P, ctypes.c_uint32,
                                               ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "magus_proxy_model_check": (ctypes.c_int, [ctypes.POINTER(MagusProxyModel)]),
@@ -407,6 +408,24 @@ class Context:
                                        _dev_ptr(out, "out", (torch.int32,)), ctypes.byref(ops),
                                        _stream_handle(stream, self.device)))
         return out, ops.value
+
+    def read_probe(self, samples, chunk: int = 4096, out=None, stream=None):
+        """The streaming-read probe (see magus.h) over `samples` (int32/uint32,
+        device): one wave per chunk of `chunk` samples.  Returns out (one word
+        per chunk)."""
+        torch = _torch()
+        sp = _dev_ptr(samples, "samples", (torch.int32, torch.uint32))
+        n = samples.numel()
+        n_chunks = (n + chunk - 1) // chunk if chunk > 0 else 0
+        if out is None:
+            out = torch.empty(max(n_chunks, 1), dtype=torch.int32,
+                              device=f"cuda:{self.device}")
+        if out.numel() < n_chunks:
+            raise ValueError(f"out holds {out.numel()} words, the probe writes {n_chunks}")
+        _check(load().magus_read_probe(self._h, sp, n, int(chunk),
+                                       _dev_ptr(out, "out", (torch.int32,)),
+                                       _stream_handle(stream, self.device)))
+        return out
 
     def check(self, stream=None) -> None:
         """Synchronize and raise MagusError(EDATA) on a device-side data fault."""

@@ -238,6 +238,12 @@ hipError_t launch_valu_probe(uint32_t workgroups, uint32_t steps, uint32_t mode,
 // VALU instructions per lane and round of a probe mode.
 uint32_t valu_probe_ops_per_step(uint32_t mode);
 
+// Streaming-read probe (read_probe.hip): one wave per chunk of `chunk`
+// samples reads them with the replay chunk kernel's access pattern; one
+// uint32 per chunk written to out.
+hipError_t launch_read_probe(const uint32_t* samples, uint64_t n_samples, uint32_t chunk,
+                             uint32_t* out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
 // Serving slot state.
 struct SlotState {
     uint32_t ring[31];   // last W-1 samples, sample k at ring[k % (W-1)]

@@ -63,6 +63,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.magus_sweep(None, None, 0, None, 0, None, 0, None, None, None) == magus.EINVAL
     assert lib.magus_server_create(None, 1 << 20, None) == magus.EINVAL
     assert lib.magus_ctx_set_chunk(None, 64) == magus.EINVAL
+    assert lib.magus_read_probe(None, None, 0, 4096, None, None) == magus.EINVAL
     assert lib.magus_server_slot_bytes() == 192
 
 
