@@ -644,12 +644,15 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                    ctx->step_funcs.as<ClampAdd>(), ctx->step_enter.as<uint32_t>(),
                                    ctx->step_sums.as<StepSum>(), ctx->step_masks.as<uint64_t>(),
                                    ctx->err.as<uint32_t>(), any_base, stream));
+    // the statistics pass's per-lane excess bins cover the widest level range
+    uint32_t bin_levels = 0;
+    for (const DevCfg& d : ctx->cfg_host) bin_levels = std::max(bin_levels, d.lmax - d.lmin + 1u);
     HIP_TRY(launch_proxy_stepped(d_samples, n_samples, d_offsets, n_traces,
                                  ctx->chunk_base.as<uint32_t>(), max_chunks,
                                  ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
                                  ctx->step_enter.as<uint32_t>(), ctx->step_masks.as<uint64_t>(),
                                  ctx->proxy_model.as<magus_proxy_model>(), d_stats, d_metrics,
-                                 stream));
+                                 bin_levels, stream));
     return MAGUS_OK;
 }
 
@@ -978,6 +981,24 @@ int magus_valu_probe(magus_ctx* ctx, uint32_t workgroups, uint32_t steps, uint32
     if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
     magus_ctx::Timing tp(ctx, MAGUS_KERNEL_PROBE);
     HIP_TRY(launch_valu_probe(workgroups, steps, mode, 0x5A17u, d_out, stream, tp.first,
+                              tp.second));
+    tp.commit();
+    return MAGUS_OK;
+}
+
+int magus_read_probe(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
+                     uint32_t chunk_steps, uint32_t* d_out, hipStream_t stream) {
+    if (!ctx) return fail(MAGUS_EINVAL, "ctx is NULL");
+    if (chunk_steps == 0 || chunk_steps % 64 || chunk_steps > (1u << 24))
+        return fail(MAGUS_EINVAL, "chunk %u is not a multiple of 64 in 64..2^24", chunk_steps);
+    if (n_samples && (!d_samples || !d_out)) return fail(MAGUS_EINVAL, "NULL buffer");
+    if ((n_samples + chunk_steps - 1) / chunk_steps > 0xFFFFFFF0ull)
+        return fail(MAGUS_EINVAL, "too many chunks");
+    if (n_samples == 0) return MAGUS_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(MAGUS_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    magus_ctx::Timing tp(ctx, MAGUS_KERNEL_PROBE);
+    HIP_TRY(launch_read_probe(d_samples, n_samples, chunk_steps, d_out, stream, tp.first,
                               tp.second));
     tp.commit();
     return MAGUS_OK;

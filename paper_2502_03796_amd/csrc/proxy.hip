@@ -30,10 +30,11 @@
 //   stepped  one wave per chunk: reads the samples and the step masks, walks
 //            the level through each block in scalar registers from the chunk's
 //            entering level, and sums per level: a block at one level adds to
-//            a run at that level (per lane); a block whose level changes scans
-//            its per-step excess once and takes each segment's sum from the
-//            scan at the segment's ends; one atomic add per non-zero sum per
-//            chunk
+//            a run at that level (per lane); a block whose level changes adds
+//            each step's excess and interval to its lane's bins of its level
+//            in LDS (samples below 2^24), else scans its per-step excess once
+//            and takes each segment's sum from the scan at the segment's
+//            ends; one atomic add per non-zero sum per chunk
 //   metrics  one thread per trace: the seven figures of each policy in FP64
 
 #include "block_masks.h"
@@ -47,6 +48,8 @@ static_assert(sizeof(magus_proxy_stats) == 16 + 8 * 64, "magus_proxy_stats layou
 static_assert(sizeof(magus_proxy_metrics) == 7 * 3 * 8, "magus_proxy_metrics layout");
 
 constexpr int kStatsWaves = 4;
+constexpr uint32_t kNarrowBound = 1u << 24;      // samples and thresholds below: narrow passes
+constexpr uint32_t kNarrowChunk = 256 * 64;      // steps per chunk the narrow sums allow
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -75,30 +78,45 @@ __device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_
 }
 
 constexpr uint32_t kStepGroup = 8;     // blocks loaded ahead by the stepped pass
+constexpr uint32_t kBinStride = 65;    // words per row of the narrow bins (one per lane + 1)
+
+// LDS words of one wave's narrow bins for a level range of `levels` rungs:
+// an excess row per level and a row of two 16-bit counts per two levels.
+__host__ __device__ constexpr uint32_t stepped_bin_words(uint32_t levels) {
+    return (levels + (levels + 1) / 2) * kBinStride;
+}
 
 // Statistics of stepped configs from the stepped replay's pass 1: one wave per
 // chunk.  The level before every step follows from the chunk's entering level
 // and the blocks' step masks (moves up by up_step, down by down_step, set to
 // level_max, each clamped to the range); the interval of step i runs at the
-// level before step i.  Lane l keeps the sums of level l.
-// (eight waves per SIMD: the register budget that keeps the scalar unit fed)
-__global__ __launch_bounds__(kStatsWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
-void proxy_stepped_kernel(
+// level before step i.  Lane l keeps the interval counts of level l.
+//
+// The excess sums take one of two forms.  The narrow pass (every sample of
+// the chunk below 2^24 and at most 16,384 steps, so a lane's sum at one level
+// fits 32 bits and its count 16) keeps them per lane in LDS, one row of
+// kBinStride words per level of the config's range and a row of two 16-bit
+// counts per two levels: a block that changes the level adds each step's
+// excess at its own level, and its interval, to its lane's words of that
+// level, and a run of blocks at one level is added when it ends, per lane,
+// without a wave reduction; the rows are summed once per chunk.  It tracks
+// the largest sample; a chunk with one of 2^24 or more is run again by the
+// wide pass, which keeps the sums per level in lane l (64-bit) and splits a
+// block that changes the level into segments of equal level with two 16-bit
+// scans.  (A lane-parallel scan of the steps' clamp-add maps in place of the
+// scalar walk moved the issue load from the scalar to the vector unit and
+// was slower: 470 us against 425 us on the bulk traces.)
+template <bool kNarrow>
+__device__ __forceinline__ bool stepped_stats_pass(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
     uint32_t chunk, const uint32_t* __restrict__ entering,
-    const uint64_t* __restrict__ masks, uint64_t n_blocks,
-    const magus_proxy_model* __restrict__ model, magus_proxy_stats* __restrict__ stats)
+    const uint64_t* __restrict__ masks, uint64_t n_blocks, const uint32_t* s_cap,
+    uint32_t* xb, uint32_t* cb, magus_proxy_stats* __restrict__ stats, uint32_t g,
+    uint32_t lane)
 {
-    __shared__ uint32_t s_cap[MAGUS_PROXY_LEVELS];
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x < MAGUS_PROXY_LEVELS) s_cap[threadIdx.x] = model->cap_mbps[threadIdx.x];
-    __syncthreads();
-    if (chunk_base[n_traces + 1] != 0) return;            // the plan rejected the batch
-    const uint32_t g = blockIdx.x * kStatsWaves + uniform(wv);
-    if (g >= chunk_base[n_traces]) return;
-
+    using acc_t = std::conditional_t<kNarrow, uint32_t, uint64_t>;
     const uint32_t t = trace_of_chunk(chunk_base, n_traces, g, lane);
     const uint64_t tbase = offsets[t];
     const uint32_t n = (uint32_t)(offsets[t + 1] - tbase);
@@ -108,6 +126,7 @@ void proxy_stepped_kernel(
     const int32_t lmin = c.lmin, lmax = c.lmax;
     const int32_t up = c.up ? (int32_t)c.up : 64, down = c.down ? (int32_t)c.down : 64;
     const uint32_t cap_hi = s_cap[lmax], cap_lo = s_cap[lmin];
+    const uint32_t rows = (uint32_t)(lmax - lmin + 1);
     const uint64_t mb = first_block(tbase, s, t);
     const uint64_t* m_hs = masks + mb;
     const uint64_t* m_up = masks + n_blocks + mb;
@@ -116,12 +135,18 @@ void proxy_stepped_kernel(
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(samples + tbase + s), (short)0, (int)(len * 4u), 0x00020000);
 
+    if constexpr (kNarrow) {
+        for (uint32_t r = 0; r < rows; ++r) xb[r * kBinStride + lane] = 0;
+        for (uint32_t r = 0; r < (rows + 1) / 2; ++r) cb[r * kBinStride + lane] = 0;
+    }
     int32_t cur = (int32_t)uniform(entering[g]);         // level before the next step
     // the run: the steps since the level last changed, all at run_lv == cur
     // (outside a block's walk); their excess is summed per lane
     uint32_t run_lv = (uint32_t)cur, cap_run = s_cap[cur], run_n = 0;
-    uint64_t ex_max = 0, ex_min = 0, run_x = 0;          // per lane
+    acc_t ex_max = 0, ex_min = 0, run_x = 0;             // per lane
+    uint32_t vmax = 0;                                   // largest sample (narrow pass)
     uint64_t bin_n = 0, bin_x = 0;                       // lane l: level l
+    auto credit_n = [&](uint32_t level, uint32_t steps) { bin_n += lane == level ? steps : 0u; };
     auto credit = [&](uint32_t level, uint32_t steps, uint64_t sum) {
         const bool mine = lane == level;
         bin_n += mine ? steps : 0u;
@@ -130,7 +155,14 @@ void proxy_stepped_kernel(
     // ends the run if the level changed and starts one at the new level
     auto follow_level = [&]() {
         if ((uint32_t)cur != run_lv) {
-            if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
+            if (run_n) {
+                if constexpr (kNarrow) {
+                    credit_n(run_lv, run_n);
+                    xb[(run_lv - lmin) * kBinStride + lane] += run_x;
+                } else {
+                    credit(run_lv, run_n, dpp_wave_sum64(run_x));
+                }
+            }
             run_n = 0;
             run_x = 0;
             run_lv = (uint32_t)cur;
@@ -196,6 +228,12 @@ void proxy_stepped_kernel(
             // level of the next block)
             run_x += over(x, cap_run);
             run_n += nv;
+        } else if constexpr (kNarrow) {
+            // each step's excess at its own level into its lane's bin (0
+            // past the end), and its interval into its lane's count
+            const uint32_t r = lv - (uint32_t)lmin;
+            xb[r * kBinStride + lane] += over(x, s_cap[lv]);
+            if (lane < nv) cb[(r >> 1) * kBinStride + lane] += 1u << (16 * (r & 1));
         } else {
             // the excess of each step at its own level (0 past the end),
             // scanned in 16-bit halves; a segment's sum is the difference of
@@ -236,6 +274,7 @@ void proxy_stepped_kernel(
         for (uint32_t k = 0; k < kStepGroup; ++k) {
             ex_max += over(x[k], cap_hi);                // lanes past the end read 0
             ex_min += over(x[k], cap_lo);
+            if constexpr (kNarrow) vmax = max(vmax, x[k]);
         }
         if (b + kStepGroup <= full) {                    // whole blocks only
             if (gm == 0) {
@@ -267,34 +306,94 @@ void proxy_stepped_kernel(
             }
         }
     };
-    uint32_t xa[kStepGroup], xb[kStepGroup];
+    uint32_t xa[kStepGroup], xc[kStepGroup];
     SpanMasks sm = load_masks(0);
 #pragma unroll
     for (uint32_t k = 0; k < kStepGroup; ++k) xa[k] = load(k);
     for (uint32_t b0 = 0; b0 < nblk; b0 += 2 * kStepGroup) {
 #pragma unroll
-        for (uint32_t k = 0; k < kStepGroup; ++k) xb[k] = load(b0 + kStepGroup + k);
+        for (uint32_t k = 0; k < kStepGroup; ++k) xc[k] = load(b0 + kStepGroup + k);
         const SpanMasks next = load_masks(b0 + 2 * kStepGroup);
         const uint64_t moving = __ballot((sm.hs | sm.up | sm.dn) != 0);
         group(b0, 0, xa, sm, moving);
         if (b0 + kStepGroup >= nblk) break;
 #pragma unroll
         for (uint32_t k = 0; k < kStepGroup; ++k) xa[k] = load(b0 + 2 * kStepGroup + k);
-        group(b0 + kStepGroup, kStepGroup, xb, sm, moving);
+        group(b0 + kStepGroup, kStepGroup, xc, sm, moving);
         sm = next;
     }
-    if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
-    ex_max = dpp_wave_sum64(ex_max);
-    ex_min = dpp_wave_sum64(ex_min);
+    if constexpr (kNarrow) {
+        // a sample of 2^24 or more: nothing is written, the wide pass takes it
+        if (__ballot(vmax >= kNarrowBound)) return false;
+        if (run_n) {
+            credit_n(run_lv, run_n);
+            xb[(run_lv - lmin) * kBinStride + lane] += run_x;
+        }
+        // lane l < rows: the sums of level lmin + l's rows (its counts are the
+        // 16-bit halves l & 1 of count row l / 2)
+        uint64_t xs = 0;
+        uint32_t ns = 0;
+        if (lane < rows) {
+            const uint32_t* crow = cb + (lane >> 1) * kBinStride;
+            const uint32_t sh = 16 * (lane & 1);
+            for (uint32_t k = 0; k < kWave; ++k) {
+                xs += xb[lane * kBinStride + k];
+                ns += (crow[k] >> sh) & 0xFFFFu;
+            }
+        }
+        bin_x = xs;
+        // the bins' counts, from lane l (level lmin + l) to lane lmin + l
+        const uint32_t from = (uint32_t)max((int32_t)lane - lmin, 0);
+        const uint32_t nmoved = (uint32_t)__shfl((int)ns, (int)from, 64);
+        if (lane >= (uint32_t)lmin && lane < (uint32_t)lmin + rows) bin_n += nmoved;
+    } else {
+        if (run_n) credit(run_lv, run_n, dpp_wave_sum64(run_x));
+    }
+    const uint64_t ex_max_w = dpp_wave_sum64(ex_max);
+    const uint64_t ex_min_w = dpp_wave_sum64(ex_min);
     unsigned long long* st = reinterpret_cast<unsigned long long*>(stats + t);
     if (lane == 0) {
-        if (ex_max) atomicAdd(st + 0, (unsigned long long)ex_max);
-        if (ex_min) atomicAdd(st + 1, (unsigned long long)ex_min);
+        if (ex_max_w) atomicAdd(st + 0, (unsigned long long)ex_max_w);
+        if (ex_min_w) atomicAdd(st + 1, (unsigned long long)ex_min_w);
     }
     if (lane < MAGUS_PROXY_LEVELS) {
         if (bin_n) atomicAdd(st + 2 + lane, (unsigned long long)bin_n);
-        if (bin_x) atomicAdd(st + 2 + MAGUS_PROXY_LEVELS + lane, (unsigned long long)bin_x);
     }
+    // the excess sums: lane l holds level l's (wide) or level lmin + l's (narrow)
+    const uint32_t xlevel = kNarrow ? lmin + lane : lane;
+    if (xlevel < MAGUS_PROXY_LEVELS && bin_x)
+        atomicAdd(st + 2 + MAGUS_PROXY_LEVELS + xlevel, (unsigned long long)bin_x);
+    return true;
+}
+
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, const uint32_t* __restrict__ entering,
+    const uint64_t* __restrict__ masks, uint64_t n_blocks,
+    const magus_proxy_model* __restrict__ model, magus_proxy_stats* __restrict__ stats,
+    uint32_t bin_levels)
+{
+    __shared__ uint32_t s_cap[MAGUS_PROXY_LEVELS];
+    extern __shared__ uint32_t s_bins[];                 // bin_levels rows per wave
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x < MAGUS_PROXY_LEVELS) s_cap[threadIdx.x] = model->cap_mbps[threadIdx.x];
+    __syncthreads();
+    if (chunk_base[n_traces + 1] != 0) return;            // the plan rejected the batch
+    const uint32_t g = blockIdx.x * kStatsWaves + uniform(wv);
+    if (g >= chunk_base[n_traces]) return;
+    // this wave's bins: bin_levels excess rows, then (bin_levels + 1) / 2 count rows
+    uint32_t* xb = s_bins + uniform(wv) * stepped_bin_words(bin_levels);
+    uint32_t* cb = xb + bin_levels * kBinStride;
+    if (bin_levels && chunk <= kNarrowChunk &&
+        stepped_stats_pass<true>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
+                                 chunk, entering, masks, n_blocks, s_cap, xb, cb, stats, g,
+                                 lane))
+        return;
+    stepped_stats_pass<false>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk,
+                              entering, masks, n_blocks, s_cap, nullptr, nullptr, stats, g,
+                              lane);
 }
 
 __global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n) {
@@ -458,8 +557,6 @@ __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
 #endif
 constexpr uint32_t kProxyIter = MAGUS_PROXY_ITER;
 constexpr uint32_t kUnseen = 2;
-constexpr uint32_t kNarrowBound = 1u << 24;      // samples and thresholds below: narrow pass
-constexpr uint32_t kNarrowChunk = 256 * 64;      // steps per chunk the narrow sums allow
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 constexpr uint32_t kSlots = kStatsWaves * kWave;
@@ -883,17 +980,21 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
                                 const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                                 const uint32_t* entering, const uint64_t* masks,
                                 const magus_proxy_model* model, magus_proxy_stats* stats,
-                                magus_proxy_metrics* metrics, hipStream_t stream)
+                                magus_proxy_metrics* metrics, uint32_t bin_levels,
+                                hipStream_t stream)
 {
     if (n_traces == 0) return hipSuccess;
     const uint64_t words = (uint64_t)n_traces * (sizeof(magus_proxy_stats) / 8);
     proxy_zero_kernel<<<(uint32_t)std::min<uint64_t>((words + 255) / 256, 4096), 256, 0, stream>>>(
         reinterpret_cast<uint64_t*>(stats), words);
     const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
+    if (bin_levels > MAGUS_PROXY_LEVELS) bin_levels = 0;
     if (blocks)
-        proxy_stepped_kernel<<<blocks, kStatsWaves * kWave, 0, stream>>>(
+        proxy_stepped_kernel<<<blocks, kStatsWaves * kWave,
+                               kStatsWaves * stepped_bin_words(bin_levels) * sizeof(uint32_t),
+                               stream>>>(
             samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, masks,
-            stepped_mask_blocks(n_samples, n_traces), model, stats);
+            stepped_mask_blocks(n_samples, n_traces), model, stats, bin_levels);
     if (metrics)
         proxy_metrics_kernel<<<(n_traces + kWave - 1) / kWave, kWave, 0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);

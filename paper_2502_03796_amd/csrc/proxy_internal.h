@@ -43,13 +43,16 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
 // per level without decision bytes.  `model` is in device memory.  stats
 // (n_traces) is cleared and filled; metrics (optional, n_traces) is written.
 // For a batch the plan rejected (status word chunk_base[n_traces + 1] != 0)
-// stats stay zero and metrics are not written.
+// stats stay zero and metrics are not written.  bin_levels: the widest level
+// range (level_max - level_min + 1) of the batch's configs, which sizes the
+// narrow pass's per-lane excess bins (0: the wide pass only).
 hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
                                 const uint64_t* offsets, uint32_t n_traces,
                                 const uint32_t* chunk_base, uint32_t max_chunks,
                                 const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
                                 const uint32_t* entering, const uint64_t* masks,
                                 const magus_proxy_model* model, magus_proxy_stats* stats,
-                                magus_proxy_metrics* metrics, hipStream_t stream);
+                                magus_proxy_metrics* metrics, uint32_t bin_levels,
+                                hipStream_t stream);
 
 }  // namespace magus

@@ -259,6 +259,43 @@ def test_narrow_pass_boundaries(ctx, oracle_mod, chunk):
     check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
 
 
+@pytest.mark.parametrize("chunk", [128, 4096, 16384, 32768])
+def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
+    """Stepped configs through the statistics pass's two forms: the narrow
+    one (per-lane 32-bit excess bins and 16-bit counts in LDS, levels from a
+    lane-parallel scan of the steps' clamp-add maps) on samples just below
+    2^24, a chunk with one sample of 2^24 (run again by the wide pass), the
+    full 32-rung ladder (the largest bins) and chunk lengths past the narrow
+    limit."""
+    lim = 1 << 24
+    rng = np.random.default_rng(chunk + 17)
+    dense = dense_traces(chunk + 9)
+    # the same shapes scaled so that their largest sample is just below 2^24
+    near = [(t.astype(np.uint64) * ((lim - 1) // max(int(t.max()), 1))).astype(np.uint32)
+            for t in dense[:3]]
+    one_big = np.concatenate(near[:1] * 3)[:3 * chunk + 50].copy()
+    one_big[min(len(one_big) - 1, chunk + 5)] = lim
+    traces = dense[:4] + near + [one_big]
+    cfgs = [default_config(up_step=2, down_step=1, level_max=31),
+            default_config(window=2, hold=3, up_step=3, down_step=2, level_min=0, level_max=31,
+                           level_init=15),
+            default_config(up_step=1, down_step=1, level_min=5, level_max=9, level_init=7)]
+    cot = (np.arange(len(traces)) % len(cfgs)).astype(np.uint32)
+    samples, offsets = synth.make_batch(traces)
+    model = dict(n_levels=32, interval_us=100000,
+                 cap_mbps=sorted(int(v) for v in rng.integers(lim - 300000, lim, 32)),
+                 uncore_mw=[int(v) for v in rng.integers(0, 50000, 32)],
+                 core_mw=30000, gpu_mw=300000)
+    s, o, c = to_dev(samples, offsets, cot)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, cfgs, model, c)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
+
+
 def test_rejects_levels_the_model_does_not_describe(ctx):
     samples, offsets = synth.make_batch([np.ones(10, np.uint32)])
     s, o, _ = to_dev(samples, offsets)
