@@ -175,6 +175,29 @@ def test_extreme_sample_values(ctx, oracle_mod):
                                      base_ref=bref)], chunk=128)
 
 
+@pytest.mark.parametrize("chunk", [128, 4096])
+def test_threshold_boundaries_at_large_samples(ctx, oracle_mod, chunk):
+    """Alg. 1 exactly on and next to the rise and fall thresholds with
+    samples just below 2^24 (where a float product of either side would be
+    off by far more than one), a chunk holding one sample of 2^24 between
+    chunks without, and threshold factors 2^16 + W q of 2^24 and just above.
+    Results and every decision byte against the oracle."""
+    from tests.test_gpu_proxy import _alg1_boundary_trace
+    lim = 1 << 24
+    cfg_a = default_config(window=2, hold=4)
+    ku = 65536 + 2 * cfg_a["inc_q16"]
+    kd = 65536 - 2 * cfg_a["dec_q16"]
+    one_big = np.full(3 * chunk + 77, lim - 2, np.uint32)
+    one_big[::5] = 9000
+    one_big[chunk + chunk // 2] = lim
+    traces = [_alg1_boundary_trace(chunk, ku, kd), _alg1_boundary_trace(chunk + 1, ku, kd, 400),
+              one_big, np.array([lim - 1, 0, lim - 1, lim // 2] * (chunk // 4 + 33), np.uint32)]
+    run_both(ctx, oracle_mod, traces, [cfg_a], chunk=chunk)
+    for q in ((lim - 65536) // 16, (lim - 65536) // 16 + 1):
+        cfg = default_config(window=16, hold=3, inc_q16=q, dec_q16=-q)
+        run_both(ctx, oracle_mod, traces, [cfg], chunk=chunk)
+
+
 def test_small_workload(ctx, oracle_mod):
     """One four-phase trace of 10,000 samples, default config: every step."""
     samples, offsets = synth.workload_small()
