@@ -428,6 +428,45 @@ def test_kernel_timing_inside_graphs(ctx, oracle_mod):
         ctx.set_graphs(False)
 
 
+def test_graph_ring_wraps_with_timing(ctx, oracle_mod):
+    """A captured call relaunched more times than its ring of graph
+    instances holds (8), with timing on, off and on again part-way and the
+    timer read in between: every launch is counted once while timing is on,
+    none while it is off, and every launch's results are right."""
+    import torch
+    traces = mixed_traces(611, LENGTHS)
+    cfgs = [default_config()]
+    samples, offsets = synth.make_batch(traces)
+    want_res, _ = oracle_mod.replay_batch(samples, offsets, cfgs, None)
+    s, o, _ = to_dev(samples, offsets)
+    res = torch.zeros((len(traces), 4), dtype=torch.int64, device="cuda")
+    ctx.set_graphs(True)
+    try:
+        ctx.set_profiling(True)
+        ctx.kernel_time(magus.KERNEL_REPLAY)
+        counted = 0
+        for i in range(21):
+            if i == 9:
+                ctx.set_profiling(False)
+            if i == 13:
+                ctx.set_profiling(True)
+            res.zero_()
+            ctx.replay(s, o, cfgs, results=res)
+            ctx.check()
+            assert (results_np(res) == want_res).all(), i
+            if i not in range(9, 13):
+                counted += 1
+            if i in (5, 17):
+                ms, n = ctx.kernel_time(magus.KERNEL_REPLAY)
+                assert n == counted and ms > 0, (i, n, counted)
+                counted = 0
+        ms, n = ctx.kernel_time(magus.KERNEL_REPLAY)
+        assert n == counted and ms > 0
+    finally:
+        ctx.set_profiling(False)
+        ctx.set_graphs(False)
+
+
 @pytest.fixture(scope="module")
 def uneven():
     return synth.workload_uneven()
