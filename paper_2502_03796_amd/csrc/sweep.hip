@@ -21,6 +21,13 @@
 namespace magus {
 namespace {
 
+// steps of the mask loop per iteration (the loop's scalar bookkeeping is
+// shared by that many steps)
+#ifndef MAGUS_SWEEP_UNROLL
+#define MAGUS_SWEEP_UNROLL 8
+#endif
+constexpr uint32_t kSweepUnroll = MAGUS_SWEEP_UNROLL;
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
@@ -167,9 +174,9 @@ __global__ __launch_bounds__(kLanes) void sweep_kernel(
             auto one_step = [&](const int2 v) { mask_step(L, v, inc, dec, hmask, thr); };
             uint32_t i = 0;
 #pragma unroll 1
-            for (; i + 4 <= nt; i += 4) {
+            for (; i + kSweepUnroll <= nt; i += kSweepUnroll) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) one_step(q[i + k]);
+                for (uint32_t k = 0; k < kSweepUnroll; ++k) one_step(q[i + k]);
             }
             for (; i < nt; ++i) one_step(q[i]);
             hist = L.hist;
