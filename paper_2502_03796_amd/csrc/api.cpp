@@ -270,7 +270,7 @@ int magus_ctx_destroy(magus_ctx* ctx) {
         for (DevBuf* b : {&ctx->err, &ctx->chunk_base, &ctx->sums, &ctx->fix, &ctx->cfgs,
                           &ctx->keys, &ctx->sweep_tab, &ctx->step_funcs, &ctx->step_enter,
                           &ctx->step_sums, &ctx->step_masks, &ctx->status,
-                          &ctx->proxy_model, &ctx->proxy_sums})
+                          &ctx->proxy_model, &ctx->proxy_sums, &ctx->proxy_redo})
             b->release();
         for (auto& r : ctx->recorded)
             for (auto& pr : r) {
@@ -610,18 +610,30 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         const uint32_t pchunk = ctx->chunk <= kProxyChunkMax / 2 ? 2 * ctx->chunk : ctx->chunk;
         const uint32_t pmax_chunks = (uint32_t)(n_samples / pchunk + n_traces + 1);
         const void* before = ctx->chunk_base.p;
+        const void* redo_before = ctx->proxy_redo.p;
         if ((rc = ctx->chunk_base.ensure(((size_t)n_traces + 2) * 4)) ||
-            (rc = ctx->proxy_sums.ensure((size_t)max_chunks * sizeof(ProxySum))))
+            (rc = ctx->proxy_sums.ensure((size_t)max_chunks * sizeof(ProxySum))) ||
+            (rc = ctx->proxy_redo.ensure(((size_t)max_chunks + 1) * 4)))
             return rc;
         if (ctx->chunk_base.p != before) ctx->drop_graphs();
+        // the exact pass's queue starts empty: its count is cleared once
+        // when the buffer is new, and after a call that did not reach its
+        // fold (every completed call leaves it at 0)
+        if (ctx->proxy_redo.p != redo_before || !ctx->proxy_redo_zero) {
+            HIP_TRY(launch_proxy_queue_clear(ctx->proxy_redo.as<uint32_t>(), stream));
+            ctx->proxy_redo_zero = true;
+        }
         HIP_TRY(launch_plan(d_offsets, n_traces, n_samples, d_cfg_of_trace, n_cfgs, pchunk,
                             pmax_chunks, ctx->chunk_base.as<uint32_t>(), ctx->err.as<uint32_t>(),
                             stream));
+        ctx->proxy_redo_zero = false;
         HIP_TRY(launch_proxy_fused(d_samples, d_offsets, n_traces, ctx->chunk_base.as<uint32_t>(),
                                    pmax_chunks, ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, pchunk,
                                    ctx->proxy_model.as<magus_proxy_model>(),
-                                   ctx->proxy_sums.as<ProxySum>(), d_stats, d_metrics, any_base,
+                                   ctx->proxy_sums.as<ProxySum>(),
+                                   ctx->proxy_redo.as<uint32_t>(), d_stats, d_metrics, any_base,
                                    mid_init, stream));
+        ctx->proxy_redo_zero = true;
         return MAGUS_OK;
     }
     // stepped actuation: pass 1 of the stepped replay (plan, step masks, the

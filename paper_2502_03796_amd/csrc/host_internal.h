@@ -76,6 +76,8 @@ struct magus_ctx {
     uint32_t sweep_shape = 0;   // sweep launch shape (index into kSweepShapes)
     magus::DevBuf proxy_model;    // proxy: the model in device memory
     magus::DevBuf proxy_sums;     // proxy: per-chunk summaries of the fused pass
+    magus::DevBuf proxy_redo;     // proxy: queue of the exact pass (count, chunk indices)
+    bool proxy_redo_zero = false; // ... its count is known to be 0
     magus_proxy_model proxy_model_host{};   // ... as last uploaded
     bool proxy_model_set = false;
     // launch shape of the replay chunk kernel (0 = one wave per chunk)

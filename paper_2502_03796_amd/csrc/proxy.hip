@@ -550,8 +550,10 @@ __device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t v) {
 // Alg. 1 compares in fp32 (below).  64-bit integer operations issue at half
 // the rate of 32-bit ones on this chip, and the pass is bound by VALU issue.
 // The narrow pass tracks the largest sample it read; a chunk that had one of
-// 2^24 or more is run again by the exact 64-bit pass, which is also taken
-// when the thresholds or the chunk length rule the narrow pass out.
+// 2^24 or more is run again by the exact 64-bit pass, which also takes the
+// chunks whose thresholds or length rule the narrow pass out.  The two
+// passes are separate kernels (the exact one over a queue of chunks), so
+// the narrow kernel's register count is its own.
 #ifndef MAGUS_PROXY_ITER
 #define MAGUS_PROXY_ITER 8
 #endif
@@ -560,6 +562,7 @@ constexpr uint32_t kUnseen = 2;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 constexpr uint32_t kSlots = kStatsWaves * kWave;
+constexpr uint32_t kExactBlocks = 2048;   // grid of the exact pass (at most)
 
 // The decisive-block state of the waves of a workgroup (one slot per lane).
 struct ProxyLds {
@@ -845,12 +848,20 @@ __device__ __forceinline__ bool proxy_pass(const ChunkView& v, uint32_t lane, ui
     return true;
 }
 
+// The narrow pass, one wave per chunk.  A chunk it cannot take (the chunk
+// length or the config's thresholds rule it out, or a sample reached 2^24)
+// is appended to the exact pass's queue: redo[0] counts the entries,
+// redo[1..] holds their chunk indices.  Only this pass's code is in the
+// kernel, so it fits 64 VGPRs (8 waves per SIMD); with the exact pass in the
+// same kernel it took 76.
 template <bool kAnyBase, bool kMidInit>
-__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
+__global__ __launch_bounds__(kStatsWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+void proxy_chunk_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
     const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
-    uint32_t chunk, const magus_proxy_model* __restrict__ model, ProxySum* __restrict__ psums)
+    uint32_t chunk, const magus_proxy_model* __restrict__ model, ProxySum* __restrict__ psums,
+    uint32_t* __restrict__ redo)
 {
     __shared__ ProxyLds L;
     const uint32_t lane = threadIdx.x & 63;
@@ -864,7 +875,31 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_chunk_kernel(
     if (narrow &&
         proxy_pass<kAnyBase, kMidInit, true>(v, lane, threadIdx.x, g, model, psums, L))
         return;
-    proxy_pass<kAnyBase, kMidInit, false>(v, lane, threadIdx.x, g, model, psums, L);
+    if (lane == 0) redo[1 + atomicAdd(redo, 1u)] = g;   // (a vector atomic)
+}
+
+// The exact 64-bit pass over the queued chunks: the grid's waves take the
+// entries round-robin (wave w: entries w, w + waves, ...); the entry index is
+// a scalar, so every wave leaves the loop together.
+template <bool kAnyBase, bool kMidInit>
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_exact_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, const magus_proxy_model* __restrict__ model, ProxySum* __restrict__ psums,
+    const uint32_t* __restrict__ redo)
+{
+    __shared__ ProxyLds L;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t n = uniform(redo[0]);
+    const uint32_t waves = gridDim.x * kStatsWaves;
+    for (uint32_t i = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6); i < n; i += waves) {
+        const uint32_t g = uniform(redo[1 + i]);
+        if (g >= chunk_base[n_traces]) continue;        // (never: every entry is this call's)
+        const ChunkView v = chunk_view(samples, offsets, n_traces, chunk_base, cfgs,
+                                       cfg_of_trace, chunk, g);
+        proxy_pass<kAnyBase, kMidInit, false>(v, lane, threadIdx.x, g, model, psums, L);
+    }
 }
 
 // Fused fold, one wave per trace; lane j takes chunk j of each group of 64.
@@ -874,9 +909,12 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
     uint32_t n_traces, const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ chunk_base,
     const ProxySum* __restrict__ psums, const DevCfg* __restrict__ cfgs,
     const uint32_t* __restrict__ cfg_of_trace, const magus_proxy_model* __restrict__ model,
-    magus_proxy_stats* __restrict__ stats, magus_proxy_metrics* __restrict__ metrics)
+    magus_proxy_stats* __restrict__ stats, magus_proxy_metrics* __restrict__ metrics,
+    uint32_t* __restrict__ redo)
 {
     __shared__ magus_proxy_model s_model;
+    // the exact pass has read the queue: empty it for the next call
+    if (blockIdx.x == 0 && threadIdx.x == 0) redo[0] = 0;
     if (metrics) model = model_to_lds(model, &s_model);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
@@ -1001,10 +1039,15 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
     return hipGetLastError();
 }
 
+hipError_t launch_proxy_queue_clear(uint32_t* redo, hipStream_t stream) {
+    proxy_zero_kernel<<<1, 64, 0, stream>>>(reinterpret_cast<uint64_t*>(redo), 1);
+    return hipGetLastError();
+}
+
 hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
                               const uint32_t* chunk_base, uint32_t max_chunks,
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
-                              const magus_proxy_model* model, ProxySum* psums,
+                              const magus_proxy_model* model, ProxySum* psums, uint32_t* redo,
                               magus_proxy_stats* stats, magus_proxy_metrics* metrics,
                               bool any_base, bool mid_init, hipStream_t stream)
 {
@@ -1016,11 +1059,25 @@ hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, 
                           : (mid_init ? proxy_chunk_kernel<false, true>
                                       : proxy_chunk_kernel<false, false>);
         k<<<blocks, kStatsWaves * kWave, 0, stream>>>(samples, offsets, n_traces, chunk_base,
-                                                      cfgs, cfg_of_trace, chunk, model, psums);
+                                                      cfgs, cfg_of_trace, chunk, model, psums,
+                                                      redo);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // the queue's length is known only on the device: a grid of up to
+        // kExactBlocks workgroups loops over it (none has work when every
+        // chunk took the narrow pass)
+        auto x = any_base ? (mid_init ? proxy_exact_kernel<true, true>
+                                      : proxy_exact_kernel<true, false>)
+                          : (mid_init ? proxy_exact_kernel<false, true>
+                                      : proxy_exact_kernel<false, false>);
+        x<<<std::min(blocks, kExactBlocks), kStatsWaves * kWave, 0, stream>>>(
+            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, model, psums, redo);
+        const hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) return e2;
     }
     proxy_fold_kernel<<<(n_traces + kStatsWaves - 1) / kStatsWaves, kStatsWaves * kWave, 0,
                         stream>>>(n_traces, offsets, chunk_base, psums, cfgs, cfg_of_trace, model,
-                                  stats, metrics);
+                                  stats, metrics, redo);
     return hipGetLastError();
 }
 

@@ -29,13 +29,18 @@ static_assert(sizeof(ProxySum) == 80, "ProxySum layout");
 // per-chunk summaries into psums (max_chunks), one wave per trace folds them
 // into stats and derives the metrics (optional) from the same sums.  For a
 // batch the plan rejected the fold writes zero statistics and metrics are not
-// written.
+// written.  redo (max_chunks + 1 words, device) is the queue of chunks for
+// the exact pass: redo[0] must be 0 when the call starts, and the fold sets
+// it to 0 again.
 hipError_t launch_proxy_fused(const uint32_t* samples, const uint64_t* offsets, uint32_t n_traces,
                               const uint32_t* chunk_base, uint32_t max_chunks,
                               const DevCfg* cfgs, const uint32_t* cfg_of_trace, uint32_t chunk,
-                              const magus_proxy_model* model, ProxySum* psums,
+                              const magus_proxy_model* model, ProxySum* psums, uint32_t* redo,
                               magus_proxy_stats* stats, magus_proxy_metrics* metrics,
                               bool any_base, bool mid_init, hipStream_t stream);
+
+// Sets the count of an exact-pass queue (redo[0]) to 0, with a kernel.
+hipError_t launch_proxy_queue_clear(uint32_t* redo, hipStream_t stream);
 
 // Stepped configs: runs after launch_stepped_prepare of the same batch
 // (chunk plan in chunk_base, the level entering every chunk in `entering`,

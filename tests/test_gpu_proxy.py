@@ -259,6 +259,41 @@ def test_narrow_pass_boundaries(ctx, oracle_mod, chunk):
     check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
 
 
+def test_exact_queue_across_calls(ctx, oracle_mod):
+    """The chunks that the narrow pass hands to the exact pass go through a
+    queue in the context that every call must start empty: one context runs
+    a batch where most chunks hold a sample of 2^24 or more (a long queue),
+    then a smaller batch with none (an entry left over would name a chunk
+    of the earlier batch), then a mix, then the first batch again; every
+    call matches the oracle.  (A stale entry would only rerun a chunk, or
+    name none of this call's; a count never cleared would overrun the
+    queue.)"""
+    lim = 1 << 24
+    cfg = default_config(window=4, hold=5)
+    model = proxy_model()
+
+    def big(n, seed):
+        r = np.random.default_rng(seed)
+        return r.integers(lim, 2**32, n, dtype=np.uint64).astype(np.uint32)
+
+    batches = [
+        [big(n, 1 + i) for i, n in enumerate((3000, 2500, 4096, 700))],
+        mixed_traces(9, [300, 900]),
+        [big(1500, 7)] + mixed_traces(11, [2000, 64]) + [big(257, 8)],
+    ]
+    batches.append(batches[0])
+    ctx.set_chunk(256)
+    try:
+        for traces in batches:
+            samples, offsets = synth.make_batch(traces)
+            s, o, _ = to_dev(samples, offsets)
+            st, me = ctx.proxy(s, o, [cfg], model)
+            ctx.check()
+            check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
+    finally:
+        ctx.set_chunk(0)
+
+
 @pytest.mark.parametrize("chunk", [128, 4096, 16384, 32768])
 def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
     """Stepped configs through the statistics pass's two forms: the narrow
