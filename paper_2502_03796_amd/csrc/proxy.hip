@@ -198,6 +198,23 @@ __device__ __forceinline__ bool stepped_stats_pass(
         // changes the level sets it for the steps after p (bit p of `chg`)
         uint32_t lv = (uint32_t)cur;
         uint64_t chg = 0;
+        if (hs == 0) {
+            // no set to level_max: unless a move is clamped, the level before
+            // step i is cur + up_step (raises before i) - down_step (lowers
+            // before i), and every move changes it.  No move is clamped iff
+            // every such partial sum, and the one after the block, lies in
+            // the range; then the walk below is not needed.
+            const int32_t li = cur + up * (int32_t)bits_below_lane(mu, 0) -
+                               down * (int32_t)bits_below_lane(md, 0);
+            const int32_t after = cur + up * __builtin_popcountll(mu) -
+                                  down * __builtin_popcountll(md);
+            if (after >= lmin && after <= lmax && !__ballot(li < lmin || li > lmax)) {
+                lv = (uint32_t)li;
+                chg = moves;
+                cur = after;
+                moves = 0;
+            }
+        }
         while (moves) {
             // p: the next move; d: its rung move (up_step, -down_step, or 64
             // for the set to level_max); the move leaves `moves`
