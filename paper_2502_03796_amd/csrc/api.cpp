@@ -645,7 +645,8 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
         (rc = ctx->step_enter.ensure((size_t)max_chunks * 4)) ||
         (rc = ctx->step_sums.ensure((size_t)max_chunks * sizeof(StepSum))) ||
         (rc = ctx->step_masks.ensure((size_t)stepped_mask_blocks(n_samples, n_traces) *
-                                     (3 * sizeof(uint64_t) + sizeof(uint32_t)))))
+                                     (3 * sizeof(uint64_t) + sizeof(uint32_t)))) ||
+        (rc = ctx->proxy_redo.ensure(((size_t)max_chunks + 1) * 4)))
         return rc;
     const void* after[5] = {ctx->chunk_base.p, ctx->step_funcs.p, ctx->step_enter.p,
                             ctx->step_sums.p, ctx->step_masks.p};
@@ -664,7 +665,10 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
                                  ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
                                  ctx->step_enter.as<uint32_t>(), ctx->step_masks.as<uint64_t>(),
                                  ctx->proxy_model.as<magus_proxy_model>(), d_stats, d_metrics,
-                                 bin_levels, stream));
+                                 bin_levels, ctx->proxy_redo.as<uint32_t>(), stream));
+    // this path clears the wide pass's queue before it runs and leaves it
+    // filled; a single-pass call clears it first
+    ctx->proxy_redo_zero = false;
     return MAGUS_OK;
 }
 

@@ -81,10 +81,13 @@ constexpr uint32_t kStepGroup = 8;     // blocks loaded ahead by the stepped pas
 constexpr uint32_t kBinStride = 65;    // words per row of the narrow bins (one per lane + 1)
 
 // LDS words of one wave's narrow bins for a level range of `levels` rungs:
-// an excess row per level and a row of two 16-bit counts per two levels.
+// an excess row per level and a row of four 8-bit counts per four levels.
 __host__ __device__ constexpr uint32_t stepped_bin_words(uint32_t levels) {
-    return (levels + (levels + 1) / 2) * kBinStride;
+    return (levels + (levels + 3) / 4) * kBinStride;
 }
+// Steps per chunk the narrow stepped pass allows: a lane's count at one level
+// (at most one step per block) stays below 2^8.
+constexpr uint32_t kNarrowSteppedChunk = 255 * 64;
 
 // Statistics of stepped configs from the stepped replay's pass 1: one wave per
 // chunk.  The level before every step follows from the chunk's entering level
@@ -93,10 +96,12 @@ __host__ __device__ constexpr uint32_t stepped_bin_words(uint32_t levels) {
 // level before step i.  Lane l keeps the interval counts of level l.
 //
 // The excess sums take one of two forms.  The narrow pass (every sample of
-// the chunk below 2^24 and at most 16,384 steps, so a lane's sum at one level
-// fits 32 bits and its count 16) keeps them per lane in LDS, one row of
-// kBinStride words per level of the config's range and a row of two 16-bit
-// counts per two levels: a block that changes the level adds each step's
+// the chunk below 2^24 and at most 16,320 steps, so a lane's sum at one level
+// fits 32 bits and its count of the level's steps in blocks that change the
+// level, at most one a block, 8) keeps them per lane in LDS, one row of
+// kBinStride words per level of the config's range and a row of four 8-bit
+// counts per four levels (a 17-rung range takes 22 rows, 5.6 KB a wave, so
+// 6 workgroups of 4 waves fit a compute unit's LDS): a block that changes the level adds each step's
 // excess at its own level, and its interval, to its lane's words of that
 // level, and a run of blocks at one level is added when it ends, per lane,
 // without a wave reduction; the rows are summed once per chunk.  It tracks
@@ -137,7 +142,7 @@ __device__ __forceinline__ bool stepped_stats_pass(
 
     if constexpr (kNarrow) {
         for (uint32_t r = 0; r < rows; ++r) xb[r * kBinStride + lane] = 0;
-        for (uint32_t r = 0; r < (rows + 1) / 2; ++r) cb[r * kBinStride + lane] = 0;
+        for (uint32_t r = 0; r < (rows + 3) / 4; ++r) cb[r * kBinStride + lane] = 0;
     }
     int32_t cur = (int32_t)uniform(entering[g]);         // level before the next step
     // the run: the steps since the level last changed, all at run_lv == cur
@@ -250,7 +255,7 @@ __device__ __forceinline__ bool stepped_stats_pass(
             // past the end), and its interval into its lane's count
             const uint32_t r = lv - (uint32_t)lmin;
             xb[r * kBinStride + lane] += over(x, s_cap[lv]);
-            if (lane < nv) cb[(r >> 1) * kBinStride + lane] += 1u << (16 * (r & 1));
+            if (lane < nv) cb[(r >> 2) * kBinStride + lane] += 1u << (8 * (r & 3));
         } else {
             // the excess of each step at its own level (0 past the end),
             // scanned in 16-bit halves; a segment's sum is the difference of
@@ -347,15 +352,15 @@ __device__ __forceinline__ bool stepped_stats_pass(
             xb[(run_lv - lmin) * kBinStride + lane] += run_x;
         }
         // lane l < rows: the sums of level lmin + l's rows (its counts are the
-        // 16-bit halves l & 1 of count row l / 2)
+        // bytes l & 3 of count row l / 4)
         uint64_t xs = 0;
         uint32_t ns = 0;
         if (lane < rows) {
-            const uint32_t* crow = cb + (lane >> 1) * kBinStride;
-            const uint32_t sh = 16 * (lane & 1);
+            const uint32_t* crow = cb + (lane >> 2) * kBinStride;
+            const uint32_t sh = 8 * (lane & 3);
             for (uint32_t k = 0; k < kWave; ++k) {
                 xs += xb[lane * kBinStride + k];
-                ns += (crow[k] >> sh) & 0xFFFFu;
+                ns += (crow[k] >> sh) & 0xFFu;
             }
         }
         bin_x = xs;
@@ -383,6 +388,12 @@ __device__ __forceinline__ bool stepped_stats_pass(
     return true;
 }
 
+// The narrow pass, one wave per chunk (its bins in dynamic LDS).  A chunk it
+// cannot take (no bins, a chunk longer than the narrow pass allows, or a
+// sample of 2^24 or more) is appended to the wide pass's queue: redo[0]
+// counts the entries, redo[1..] holds their chunk indices.  Alone the narrow
+// pass takes 62 VGPRs, so the bins of a 17-rung range (5.6 KB a wave) set
+// the occupancy: 7 waves per SIMD (6 with the wide pass in the kernel).
 __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
     const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
     uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
@@ -390,7 +401,7 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
     uint32_t chunk, const uint32_t* __restrict__ entering,
     const uint64_t* __restrict__ masks, uint64_t n_blocks,
     const magus_proxy_model* __restrict__ model, magus_proxy_stats* __restrict__ stats,
-    uint32_t bin_levels)
+    uint32_t bin_levels, uint32_t* __restrict__ redo)
 {
     __shared__ uint32_t s_cap[MAGUS_PROXY_LEVELS];
     extern __shared__ uint32_t s_bins[];                 // bin_levels rows per wave
@@ -400,20 +411,48 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_kernel(
     if (chunk_base[n_traces + 1] != 0) return;            // the plan rejected the batch
     const uint32_t g = blockIdx.x * kStatsWaves + uniform(wv);
     if (g >= chunk_base[n_traces]) return;
-    // this wave's bins: bin_levels excess rows, then (bin_levels + 1) / 2 count rows
+    // this wave's bins: bin_levels excess rows, then (bin_levels + 3) / 4 count rows
     uint32_t* xb = s_bins + uniform(wv) * stepped_bin_words(bin_levels);
     uint32_t* cb = xb + bin_levels * kBinStride;
-    if (bin_levels && chunk <= kNarrowChunk &&
+    if (bin_levels && chunk <= kNarrowSteppedChunk &&
         stepped_stats_pass<true>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
                                  chunk, entering, masks, n_blocks, s_cap, xb, cb, stats, g,
                                  lane))
         return;
-    stepped_stats_pass<false>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk,
-                              entering, masks, n_blocks, s_cap, nullptr, nullptr, stats, g,
-                              lane);
+    if (lane == 0) redo[1 + atomicAdd(redo, 1u)] = g;   // (a vector atomic)
 }
 
-__global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n) {
+// The wide pass over the queued chunks: the grid's waves take the entries
+// round-robin with a scalar entry index, so every wave leaves the loop
+// together.
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_stepped_wide_kernel(
+    const uint32_t* __restrict__ samples, const uint64_t* __restrict__ offsets,
+    uint32_t n_traces, const uint32_t* __restrict__ chunk_base,
+    const DevCfg* __restrict__ cfgs, const uint32_t* __restrict__ cfg_of_trace,
+    uint32_t chunk, const uint32_t* __restrict__ entering,
+    const uint64_t* __restrict__ masks, uint64_t n_blocks,
+    const magus_proxy_model* __restrict__ model, magus_proxy_stats* __restrict__ stats,
+    const uint32_t* __restrict__ redo)
+{
+    __shared__ uint32_t s_cap[MAGUS_PROXY_LEVELS];
+    const uint32_t lane = threadIdx.x & 63;
+    if (threadIdx.x < MAGUS_PROXY_LEVELS) s_cap[threadIdx.x] = model->cap_mbps[threadIdx.x];
+    __syncthreads();
+    const uint32_t n = uniform(redo[0]);
+    const uint32_t waves = gridDim.x * kStatsWaves;
+    for (uint32_t i = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6); i < n; i += waves) {
+        const uint32_t g = uniform(redo[1 + i]);
+        if (g >= chunk_base[n_traces]) continue;        // (never: every entry is this call's)
+        stepped_stats_pass<false>(samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace,
+                                  chunk, entering, masks, n_blocks, s_cap, nullptr, nullptr,
+                                  stats, g, lane);
+    }
+}
+
+// Zeroes p[0, n); with `queue`, also sets queue[0] (a queue's count) to 0.
+__global__ __launch_bounds__(256) void proxy_zero_kernel(uint64_t* __restrict__ p, uint64_t n,
+                                                         uint32_t* __restrict__ queue) {
+    if (queue && blockIdx.x == 0 && threadIdx.x == 0) queue[0] = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -1036,20 +1075,31 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
                                 const uint32_t* entering, const uint64_t* masks,
                                 const magus_proxy_model* model, magus_proxy_stats* stats,
                                 magus_proxy_metrics* metrics, uint32_t bin_levels,
-                                hipStream_t stream)
+                                uint32_t* redo, hipStream_t stream)
 {
     if (n_traces == 0) return hipSuccess;
+    // the statistics are summed with atomics: zero them, and the queue's count
     const uint64_t words = (uint64_t)n_traces * (sizeof(magus_proxy_stats) / 8);
     proxy_zero_kernel<<<(uint32_t)std::min<uint64_t>((words + 255) / 256, 4096), 256, 0, stream>>>(
-        reinterpret_cast<uint64_t*>(stats), words);
+        reinterpret_cast<uint64_t*>(stats), words, redo);
     const uint32_t blocks = (max_chunks + kStatsWaves - 1) / kStatsWaves;
     if (bin_levels > MAGUS_PROXY_LEVELS) bin_levels = 0;
-    if (blocks)
+    if (blocks) {
+        const uint64_t nb = stepped_mask_blocks(n_samples, n_traces);
         proxy_stepped_kernel<<<blocks, kStatsWaves * kWave,
                                kStatsWaves * stepped_bin_words(bin_levels) * sizeof(uint32_t),
                                stream>>>(
             samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, masks,
-            stepped_mask_blocks(n_samples, n_traces), model, stats, bin_levels);
+            nb, model, stats, bin_levels, redo);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        proxy_stepped_wide_kernel<<<std::min(blocks, kExactBlocks), kStatsWaves * kWave, 0,
+                                    stream>>>(
+            samples, offsets, n_traces, chunk_base, cfgs, cfg_of_trace, chunk, entering, masks,
+            nb, model, stats, redo);
+        const hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) return e2;
+    }
     if (metrics)
         proxy_metrics_kernel<<<(n_traces + kWave - 1) / kWave, kWave, 0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);
@@ -1057,7 +1107,7 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
 }
 
 hipError_t launch_proxy_queue_clear(uint32_t* redo, hipStream_t stream) {
-    proxy_zero_kernel<<<1, 64, 0, stream>>>(reinterpret_cast<uint64_t*>(redo), 1);
+    proxy_zero_kernel<<<1, 64, 0, stream>>>(nullptr, 0, redo);
     return hipGetLastError();
 }
 

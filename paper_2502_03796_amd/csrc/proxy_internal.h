@@ -50,7 +50,9 @@ hipError_t launch_proxy_queue_clear(uint32_t* redo, hipStream_t stream);
 // For a batch the plan rejected (status word chunk_base[n_traces + 1] != 0)
 // stats stay zero and metrics are not written.  bin_levels: the widest level
 // range (level_max - level_min + 1) of the batch's configs, which sizes the
-// narrow pass's per-lane excess bins (0: the wide pass only).
+// narrow pass's per-lane excess bins (0: the wide pass only).  redo
+// (max_chunks + 1 words, device): the queue of chunks for the wide pass,
+// cleared by the call's first kernel and left filled.
 hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
                                 const uint64_t* offsets, uint32_t n_traces,
                                 const uint32_t* chunk_base, uint32_t max_chunks,
@@ -58,6 +60,6 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
                                 const uint32_t* entering, const uint64_t* masks,
                                 const magus_proxy_model* model, magus_proxy_stats* stats,
                                 magus_proxy_metrics* metrics, uint32_t bin_levels,
-                                hipStream_t stream);
+                                uint32_t* redo, hipStream_t stream);
 
 }  // namespace magus

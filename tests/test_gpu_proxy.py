@@ -260,16 +260,18 @@ def test_narrow_pass_boundaries(ctx, oracle_mod, chunk):
 
 
 def test_exact_queue_across_calls(ctx, oracle_mod):
-    """The chunks that the narrow pass hands to the exact pass go through a
-    queue in the context that every call must start empty: one context runs
-    a batch where most chunks hold a sample of 2^24 or more (a long queue),
-    then a smaller batch with none (an entry left over would name a chunk
-    of the earlier batch), then a mix, then the first batch again; every
-    call matches the oracle.  (A stale entry would only rerun a chunk, or
-    name none of this call's; a count never cleared would overrun the
-    queue.)"""
+    """The chunks that a narrow pass hands to the exact (jump-to-bound) or
+    wide (stepped) pass go through one queue in the context that every call
+    must start empty: one context runs a batch where most chunks hold a
+    sample of 2^24 or more (a long queue), then a smaller batch with none
+    (an entry left over would name a chunk of the earlier batch), then a
+    mix, then the first batch again, each with a jump-to-bound and then a
+    stepped config; every call matches the oracle.  (A stale entry would
+    only rerun a chunk, or name none of this call's; a count never cleared
+    would overrun the queue.)"""
     lim = 1 << 24
-    cfg = default_config(window=4, hold=5)
+    cfgs = [default_config(window=4, hold=5),
+            default_config(window=4, hold=5, up_step=2, down_step=1)]
     model = proxy_model()
 
     def big(n, seed):
@@ -287,21 +289,22 @@ def test_exact_queue_across_calls(ctx, oracle_mod):
         for traces in batches:
             samples, offsets = synth.make_batch(traces)
             s, o, _ = to_dev(samples, offsets)
-            st, me = ctx.proxy(s, o, [cfg], model)
-            ctx.check()
-            check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
+            for cfg in cfgs:
+                st, me = ctx.proxy(s, o, [cfg], model)
+                ctx.check()
+                check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
     finally:
         ctx.set_chunk(0)
 
 
-@pytest.mark.parametrize("chunk", [128, 4096, 16384, 32768])
+@pytest.mark.parametrize("chunk", [128, 4096, 16320, 16384, 32768])
 def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
     """Stepped configs through the statistics pass's two forms: the narrow
-    one (per-lane 32-bit excess bins and 16-bit counts in LDS, levels from a
-    lane-parallel scan of the steps' clamp-add maps) on samples just below
-    2^24, a chunk with one sample of 2^24 (run again by the wide pass), the
-    full 32-rung ladder (the largest bins) and chunk lengths past the narrow
-    limit."""
+    one (per-lane 32-bit excess bins and 8-bit counts in LDS, levels from the
+    scalar walk of each block's moves) on samples just below 2^24, a chunk
+    with one sample of 2^24 (run again by the wide pass), the full 32-rung
+    ladder (the largest bins), the longest narrow chunk (16,320 steps) and
+    chunk lengths past the narrow limit."""
     lim = 1 << 24
     rng = np.random.default_rng(chunk + 17)
     dense = dense_traces(chunk + 9)
@@ -329,6 +332,42 @@ def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
     finally:
         ctx.set_chunk(0)
     check_against_oracle(oracle_mod, samples, offsets, cfgs, cot, model, st, me)
+
+
+@pytest.mark.parametrize("chunk", [16320, 16384])
+def test_stepped_narrow_counts_at_their_limit(ctx, oracle_mod, chunk):
+    """The narrow stepped pass counts, per lane and level, the steps of the
+    blocks that change the level in one byte: at most one a block, 255 in
+    the longest narrow chunk.  A period-4 trace (low, high, high, low) with
+    window 2 raises the level at every rise and lowers it at every fall (two
+    events in four steps stay below the 3/5 high fraction), so every block
+    changes the level and lane 0 is at the entering level in all of them:
+    its count reaches 255 in a 16,320-step chunk (checked on the oracle's
+    levels), and the statistics still match the oracle's."""
+    pattern = np.array([1000, 2000, 2000, 1000], np.uint32)
+    trace = np.tile(pattern, (2 * chunk + 640) // 4)
+    cfg = default_config(window=2, hold=10, up_step=1, down_step=1, level_min=0,
+                         level_max=31, level_init=5)
+    _, dec = oracle_mod.replay_trace(trace, cfg)
+    levels, high, _ = oracle_mod.decode(dec)
+    assert not high.any()
+    # the level before step i: the level after step i - 1 (level_init first)
+    before = np.concatenate([[cfg["level_init"]], levels[:-1]])
+    blocks = before[:chunk // 64 * 64].reshape(-1, 64)
+    changing = blocks.min(axis=1) != blocks.max(axis=1)
+    lane0 = blocks[changing, 0]
+    assert len(lane0) == chunk // 64 and (lane0 == lane0[0]).all()   # 255 at chunk 16,320
+    samples, offsets = synth.make_batch([trace, trace[: chunk + 64]])
+    model = proxy_model()
+    model = dict(model, n_levels=32, cap_mbps=[1500] * 32, uncore_mw=[20000] * 32)
+    s, o, _ = to_dev(samples, offsets)
+    ctx.set_chunk(chunk)
+    try:
+        st, me = ctx.proxy(s, o, [cfg], model)
+        ctx.check()
+    finally:
+        ctx.set_chunk(0)
+    check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
 
 
 def test_rejects_levels_the_model_does_not_describe(ctx):
