@@ -77,6 +77,12 @@ __device__ __forceinline__ uint32_t lane_pick(uint64_t mask, uint32_t a, uint32_
     return r;
 }
 
+// Adds v to a word of LDS with no value returned (ds_add_u32): no wait for
+// the word's old value.
+__device__ __forceinline__ void lds_add(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 constexpr uint32_t kStepGroup = 8;     // blocks loaded ahead by the stepped pass
 constexpr uint32_t kBinStride = 65;    // words per row of the narrow bins (one per lane + 1)
 
@@ -163,7 +169,7 @@ __device__ __forceinline__ bool stepped_stats_pass(
             if (run_n) {
                 if constexpr (kNarrow) {
                     credit_n(run_lv, run_n);
-                    xb[(run_lv - lmin) * kBinStride + lane] += run_x;
+                    lds_add(xb + (run_lv - lmin) * kBinStride + lane, run_x);
                 } else {
                     credit(run_lv, run_n, dpp_wave_sum64(run_x));
                 }
@@ -254,8 +260,8 @@ __device__ __forceinline__ bool stepped_stats_pass(
             // each step's excess at its own level into its lane's bin (0
             // past the end), and its interval into its lane's count
             const uint32_t r = lv - (uint32_t)lmin;
-            xb[r * kBinStride + lane] += over(x, s_cap[lv]);
-            if (lane < nv) cb[(r >> 2) * kBinStride + lane] += 1u << (8 * (r & 3));
+            lds_add(xb + r * kBinStride + lane, over(x, s_cap[lv]));
+            if (lane < nv) lds_add(cb + (r >> 2) * kBinStride + lane, 1u << (8 * (r & 3)));
         } else {
             // the excess of each step at its own level (0 past the end),
             // scanned in 16-bit halves; a segment's sum is the difference of
@@ -349,8 +355,10 @@ __device__ __forceinline__ bool stepped_stats_pass(
         if (__ballot(vmax >= kNarrowBound)) return false;
         if (run_n) {
             credit_n(run_lv, run_n);
-            xb[(run_lv - lmin) * kBinStride + lane] += run_x;
+            lds_add(xb + (run_lv - lmin) * kBinStride + lane, run_x);
         }
+        // the other lanes' adds are done before their words are read
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // lane l < rows: the sums of level lmin + l's rows (its counts are the
         // bytes l & 3 of count row l / 4)
         uint64_t xs = 0;
