@@ -84,16 +84,20 @@ __device__ __forceinline__ void lds_add(uint32_t* p, uint32_t v) {
 }
 
 constexpr uint32_t kStepGroup = 8;     // blocks loaded ahead by the stepped pass
-constexpr uint32_t kBinStride = 65;    // words per row of the narrow bins (one per lane + 1)
+constexpr uint32_t kBinLanes = 16;     // words of a narrow bin row (lane l adds to word l % 16)
+constexpr uint32_t kBinStride = 17;    // ... and the row's stride in words
 
 // LDS words of one wave's narrow bins for a level range of `levels` rungs:
-// an excess row per level and a row of four 8-bit counts per four levels.
+// an excess row per level and a row of two 16-bit counts per two levels.
 __host__ __device__ constexpr uint32_t stepped_bin_words(uint32_t levels) {
-    return (levels + (levels + 3) / 4) * kBinStride;
+    return (levels + (levels + 1) / 2) * kBinStride;
 }
-// Steps per chunk the narrow stepped pass allows: a lane's count at one level
-// (at most one step per block) stays below 2^8.
+// The narrow stepped pass: chunks of at most 16,320 steps whose samples are
+// all below 2^22.  A bin word takes at most one step a block from each of 4
+// lanes: at most 1,020 steps, whose excesses (below 2^22 each) sum below
+// 2^32, and whose count fits 16 bits.
 constexpr uint32_t kNarrowSteppedChunk = 255 * 64;
+constexpr uint32_t kNarrowSteppedBound = 1u << 22;
 
 // Statistics of stepped configs from the stepped replay's pass 1: one wave per
 // chunk.  The level before every step follows from the chunk's entering level
@@ -102,17 +106,17 @@ constexpr uint32_t kNarrowSteppedChunk = 255 * 64;
 // level before step i.  Lane l keeps the interval counts of level l.
 //
 // The excess sums take one of two forms.  The narrow pass (every sample of
-// the chunk below 2^24 and at most 16,320 steps, so a lane's sum at one level
-// fits 32 bits and its count of the level's steps in blocks that change the
-// level, at most one a block, 8) keeps them per lane in LDS, one row of
-// kBinStride words per level of the config's range and a row of four 8-bit
-// counts per four levels (a 17-rung range takes 22 rows, 5.6 KB a wave, so
-// 6 workgroups of 4 waves fit a compute unit's LDS): a block that changes the level adds each step's
-// excess at its own level, and its interval, to its lane's words of that
-// level, and a run of blocks at one level is added when it ends, per lane,
-// without a wave reduction; the rows are summed once per chunk.  It tracks
-// the largest sample; a chunk with one of 2^24 or more is run again by the
-// wide pass, which keeps the sums per level in lane l (64-bit) and splits a
+// the chunk below 2^22 and at most 16,320 steps) keeps them in LDS bins: a
+// row of 16 words per level of the config's range and a row of two 16-bit
+// counts per two levels, lane l adding to word l % 16 with LDS atomic adds
+// (4 lanes a word: at most 1,020 steps, whose excess sum fits 32 bits and
+// whose count fits 16; a 17-rung range takes 26 rows of 17 words, 1.8 KB a
+// wave, so registers alone set the occupancy).  A block that changes the
+// level adds each step's excess at its own level, and its interval, to its
+// lane's words of that level, and a run of blocks at one level is added
+// when it ends, per lane, without a wave reduction; the rows are summed
+// once per chunk.  It tracks the largest sample; a chunk with one of 2^22
+// or more is run again by the wide pass, which keeps the sums per level in lane l (64-bit) and splits a
 // block that changes the level into segments of equal level with two 16-bit
 // scans.  (A lane-parallel scan of the steps' clamp-add maps in place of the
 // scalar walk moved the issue load from the scalar to the vector unit and
@@ -138,6 +142,7 @@ __device__ __forceinline__ bool stepped_stats_pass(
     const int32_t up = c.up ? (int32_t)c.up : 64, down = c.down ? (int32_t)c.down : 64;
     const uint32_t cap_hi = s_cap[lmax], cap_lo = s_cap[lmin];
     const uint32_t rows = (uint32_t)(lmax - lmin + 1);
+    const uint32_t bin_word = lane & (kBinLanes - 1);    // this lane's word of a bin row
     const uint64_t mb = first_block(tbase, s, t);
     const uint64_t* m_hs = masks + mb;
     const uint64_t* m_up = masks + n_blocks + mb;
@@ -147,8 +152,12 @@ __device__ __forceinline__ bool stepped_stats_pass(
         (void*)(samples + tbase + s), (short)0, (int)(len * 4u), 0x00020000);
 
     if constexpr (kNarrow) {
-        for (uint32_t r = 0; r < rows; ++r) xb[r * kBinStride + lane] = 0;
-        for (uint32_t r = 0; r < (rows + 3) / 4; ++r) cb[r * kBinStride + lane] = 0;
+        if (lane < kBinLanes) {
+            for (uint32_t r = 0; r < rows; ++r) xb[r * kBinStride + lane] = 0;
+            for (uint32_t r = 0; r < (rows + 1) / 2; ++r) cb[r * kBinStride + lane] = 0;
+        }
+        // the zeros are in place before any lane adds to a word
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
     int32_t cur = (int32_t)uniform(entering[g]);         // level before the next step
     // the run: the steps since the level last changed, all at run_lv == cur
@@ -169,7 +178,7 @@ __device__ __forceinline__ bool stepped_stats_pass(
             if (run_n) {
                 if constexpr (kNarrow) {
                     credit_n(run_lv, run_n);
-                    lds_add(xb + (run_lv - lmin) * kBinStride + lane, run_x);
+                    lds_add(xb + (run_lv - lmin) * kBinStride + bin_word, run_x);
                 } else {
                     credit(run_lv, run_n, dpp_wave_sum64(run_x));
                 }
@@ -260,8 +269,8 @@ __device__ __forceinline__ bool stepped_stats_pass(
             // each step's excess at its own level into its lane's bin (0
             // past the end), and its interval into its lane's count
             const uint32_t r = lv - (uint32_t)lmin;
-            lds_add(xb + r * kBinStride + lane, over(x, s_cap[lv]));
-            if (lane < nv) lds_add(cb + (r >> 2) * kBinStride + lane, 1u << (8 * (r & 3)));
+            lds_add(xb + r * kBinStride + bin_word, over(x, s_cap[lv]));
+            if (lane < nv) lds_add(cb + (r >> 1) * kBinStride + bin_word, 1u << (16 * (r & 1)));
         } else {
             // the excess of each step at its own level (0 past the end),
             // scanned in 16-bit halves; a segment's sum is the difference of
@@ -351,24 +360,25 @@ __device__ __forceinline__ bool stepped_stats_pass(
         sm = next;
     }
     if constexpr (kNarrow) {
-        // a sample of 2^24 or more: nothing is written, the wide pass takes it
-        if (__ballot(vmax >= kNarrowBound)) return false;
+        // a sample of 2^22 or more: nothing is written, the wide pass takes it
+        if (__ballot(vmax >= kNarrowSteppedBound)) return false;
         if (run_n) {
             credit_n(run_lv, run_n);
-            lds_add(xb + (run_lv - lmin) * kBinStride + lane, run_x);
+            lds_add(xb + (run_lv - lmin) * kBinStride + bin_word, run_x);
         }
         // the other lanes' adds are done before their words are read
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // lane l < rows: the sums of level lmin + l's rows (its counts are the
-        // bytes l & 3 of count row l / 4)
+        // 16-bit halves l & 1 of count row l / 2)
         uint64_t xs = 0;
         uint32_t ns = 0;
         if (lane < rows) {
-            const uint32_t* crow = cb + (lane >> 2) * kBinStride;
-            const uint32_t sh = 8 * (lane & 3);
-            for (uint32_t k = 0; k < kWave; ++k) {
+            const uint32_t* crow = cb + (lane >> 1) * kBinStride;
+            const uint32_t sh = 16 * (lane & 1);
+#pragma unroll
+            for (uint32_t k = 0; k < kBinLanes; ++k) {
                 xs += xb[lane * kBinStride + k];
-                ns += (crow[k] >> sh) & 0xFFu;
+                ns += (crow[k] >> sh) & 0xFFFFu;
             }
         }
         bin_x = xs;

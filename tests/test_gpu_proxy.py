@@ -300,12 +300,12 @@ def test_exact_queue_across_calls(ctx, oracle_mod):
 @pytest.mark.parametrize("chunk", [128, 4096, 16320, 16384, 32768])
 def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
     """Stepped configs through the statistics pass's two forms: the narrow
-    one (per-lane 32-bit excess bins and 8-bit counts in LDS, levels from the
-    scalar walk of each block's moves) on samples just below 2^24, a chunk
-    with one sample of 2^24 (run again by the wide pass), the full 32-rung
-    ladder (the largest bins), the longest narrow chunk (16,320 steps) and
-    chunk lengths past the narrow limit."""
-    lim = 1 << 24
+    one (32-bit excess bins and 16-bit counts in LDS, each word shared by 4
+    lanes, levels from the scalar walk of each block's moves) on samples
+    just below 2^22, a chunk with one sample of 2^22 (run again by the wide
+    pass), the full 32-rung ladder (the largest bins), the longest narrow
+    chunk (16,320 steps) and chunk lengths past the narrow limit."""
+    lim = 1 << 22
     rng = np.random.default_rng(chunk + 17)
     dense = dense_traces(chunk + 9)
     # the same shapes scaled so that their largest sample is just below 2^24
@@ -336,14 +336,15 @@ def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
 
 @pytest.mark.parametrize("chunk", [16320, 16384])
 def test_stepped_narrow_counts_at_their_limit(ctx, oracle_mod, chunk):
-    """The narrow stepped pass counts, per lane and level, the steps of the
-    blocks that change the level in one byte: at most one a block, 255 in
-    the longest narrow chunk.  A period-4 trace (low, high, high, low) with
+    """The narrow stepped pass counts the steps of the blocks that change
+    the level per level in 16-bit words, each shared by 4 lanes (l, l + 16,
+    l + 32, l + 48): at most one step a block from each, 1,020 in the
+    longest narrow chunk.  A period-4 trace (low, high, high, low) with
     window 2 raises the level at every rise and lowers it at every fall (two
     events in four steps stay below the 3/5 high fraction), so every block
-    changes the level and lane 0 is at the entering level in all of them:
-    its count reaches 255 in a 16,320-step chunk (checked on the oracle's
-    levels), and the statistics still match the oracle's."""
+    changes the level and lanes 0, 16, 32 and 48 are at the entering level
+    in all of them: their word reaches 1,020 in a 16,320-step chunk (checked
+    on the oracle's levels), and the statistics still match the oracle's."""
     pattern = np.array([1000, 2000, 2000, 1000], np.uint32)
     trace = np.tile(pattern, (2 * chunk + 640) // 4)
     cfg = default_config(window=2, hold=10, up_step=1, down_step=1, level_min=0,
@@ -355,8 +356,8 @@ def test_stepped_narrow_counts_at_their_limit(ctx, oracle_mod, chunk):
     before = np.concatenate([[cfg["level_init"]], levels[:-1]])
     blocks = before[:chunk // 64 * 64].reshape(-1, 64)
     changing = blocks.min(axis=1) != blocks.max(axis=1)
-    lane0 = blocks[changing, 0]
-    assert len(lane0) == chunk // 64 and (lane0 == lane0[0]).all()   # 255 at chunk 16,320
+    lanes = blocks[changing][:, [0, 16, 32, 48]]
+    assert len(lanes) == chunk // 64 and (lanes == lanes[0, 0]).all()   # 4 x 255 at 16,320
     samples, offsets = synth.make_batch([trace, trace[: chunk + 64]])
     model = proxy_model()
     model = dict(model, n_levels=32, cap_mbps=[1500] * 32, uncore_mw=[20000] * 32)
