@@ -236,12 +236,14 @@ def bench_stepped(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr,
     for _ in range(2):
         sctx.replay(s, o, sarr, results=sres)
     torch.cuda.synchronize()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        sctx.replay(s, o, sarr, results=sres)
-    torch.cuda.synchronize()
-    sdt = (time.perf_counter() - t0) / reps
+    ts = []
+    for _ in range(3):            # the median of 3 timings of 20 back-to-back calls
+        t0 = time.perf_counter()
+        for _ in range(20):
+            sctx.replay(s, o, sarr, results=sres)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) / 20)
+    sdt = sorted(ts)[1]
     sctx.check()
     sgot = sres.cpu().numpy().view(np.uint64)
     extra["stepped"] = {
@@ -276,12 +278,19 @@ def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, p
     pctx = magus.Context(0)
     pctx.proxy(s, o, cfg_arr, model)
     torch.cuda.synchronize()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        pst, pme = pctx.proxy(s, o, cfg_arr, model)
-    torch.cuda.synchronize()
-    pdt = (time.perf_counter() - t0) / reps
+
+    def per_call(call, reps=20, trials=3):
+        # the median over `trials` timings of `reps` back-to-back calls
+        ts = []
+        for _ in range(trials):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = call()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) / reps)
+        return sorted(ts)[len(ts) // 2], out
+
+    pdt, (pst, pme) = per_call(lambda: pctx.proxy(s, o, cfg_arr, model))
     pctx.check()
     pst_np, pme_np = pst.cpu().numpy(), pme.cpu().numpy()
     # the same model with stepped actuation (up 2 rungs, down 1): the stepped
@@ -289,11 +298,7 @@ def bench_proxy(magus, synth, np, torch, s, o, samples, offsets, cfg, cfg_arr, p
     sarr = magus.config_array([synth.default_config(up_step=2, down_step=1)])
     pctx.proxy(s, o, sarr, model)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        pctx.proxy(s, o, sarr, model)
-    torch.cuda.synchronize()
-    sdt = (time.perf_counter() - t0) / reps
+    sdt, _ = per_call(lambda: pctx.proxy(s, o, sarr, model))
     pctx.check()
 
     def check_proxy(oracle):
