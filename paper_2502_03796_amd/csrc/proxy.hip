@@ -482,32 +482,34 @@ __device__ __forceinline__ double stretched(uint64_t steps, uint64_t excess, uin
     return (double)steps + (double)excess / (double)cap;
 }
 
-// The seven figures of each policy for one trace from its statistics:
-// level_stats(l, steps, excess) gives level l's intervals and excess sum, in
-// increasing level order (FP64, the same operations in the same order
-// wherever it runs).
-template <class LevelStats>
+// FP64 sum across the wave (butterfly: every lane gets the total).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// The seven figures of each policy for one trace from its statistics, by
+// one wave: lane l passes level l's intervals and excess sum (lanes past the
+// model's levels pass zeros).  Each lane forms its level's stretched length
+// and package energy, two wave sums give MAGUS's totals, and every lane then
+// derives the same figures (FP64).
 __device__ __forceinline__ magus_proxy_metrics metrics_of(const magus_proxy_model* model,
                                                          const DevCfg& c, uint64_t n,
                                                          uint64_t excess_max, uint64_t excess_min,
-                                                         LevelStats&& level_stats)
+                                                         uint64_t steps_l, uint64_t excess_l,
+                                                         uint32_t lane)
 {
     const double dt = (double)model->interval_us * 1e-6;
     const double core = (double)model->core_mw, gpu = (double)model->gpu_mw * 1e-3;
     double T[3], P[3];                       // intervals (stretched), package energy
-    T[0] = 0.0;
-    P[0] = 0.0;
-    const uint32_t n_levels = model->n_levels;
-#pragma unroll
-    for (uint32_t l = 0; l < MAGUS_PROXY_LEVELS; ++l) {
-        if (l >= n_levels) break;
-        uint64_t steps, excess;
-        level_stats(l, steps, excess);
-        if (!steps) continue;
-        const double len = stretched(steps, excess, model->cap_mbps[l]);
-        T[0] += len;
-        P[0] += len * (core + (double)model->uncore_mw[l]);
+    double len = 0.0, pw = 0.0;
+    if (lane < model->n_levels && steps_l) {
+        len = stretched(steps_l, excess_l, model->cap_mbps[lane]);
+        pw = len * (core + (double)model->uncore_mw[lane]);
     }
+    T[0] = wave_sum_f64(len);
+    P[0] = wave_sum_f64(pw);
     T[1] = stretched(n, excess_max, model->cap_mbps[c.lmax]);
     P[1] = T[1] * (core + (double)model->uncore_mw[c.lmax]);
     T[2] = stretched(n, excess_min, model->cap_mbps[c.lmin]);
@@ -532,6 +534,17 @@ __device__ __forceinline__ magus_proxy_metrics metrics_of(const magus_proxy_mode
     return r;
 }
 
+// Writes one trace's metrics from the wave: lane i < 21 stores word i.
+__device__ __forceinline__ void store_metrics(magus_proxy_metrics* out,
+                                              const magus_proxy_metrics& r, uint32_t lane) {
+    constexpr uint32_t kWords = sizeof(magus_proxy_metrics) / 8;
+    const double* w = reinterpret_cast<const double*>(&r);
+    double v = 0.0;
+#pragma unroll
+    for (uint32_t i = 0; i < kWords; ++i) v = lane == i ? w[i] : v;
+    if (lane < kWords) reinterpret_cast<double*>(out)[lane] = v;
+}
+
 // The model copied into LDS by the workgroup (the metrics read it in a
 // dependent chain, each global load of which would be a full memory latency).
 __device__ __forceinline__ const magus_proxy_model* model_to_lds(const magus_proxy_model* model,
@@ -543,7 +556,8 @@ __device__ __forceinline__ const magus_proxy_model* model_to_lds(const magus_pro
     return s_model;
 }
 
-__global__ __launch_bounds__(kWave) void proxy_metrics_kernel(
+// One wave per trace (4 a workgroup).
+__global__ __launch_bounds__(kStatsWaves * kWave) void proxy_metrics_kernel(
     const uint64_t* __restrict__ offsets, uint32_t n_traces,
     const uint32_t* __restrict__ chunk_base, const DevCfg* __restrict__ cfgs,
     const uint32_t* __restrict__ cfg_of_trace, const magus_proxy_model* __restrict__ model,
@@ -551,15 +565,16 @@ __global__ __launch_bounds__(kWave) void proxy_metrics_kernel(
 {
     __shared__ magus_proxy_model s_model;
     model = model_to_lds(model, &s_model);
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * kStatsWaves + uniform(threadIdx.x >> 6);
     if (t >= n_traces || chunk_base[n_traces + 1] != 0) return;
     const DevCfg c = cfgs[cfg_of_trace ? cfg_of_trace[t] : 0];
     const magus_proxy_stats& st = stats[t];
-    out[t] = metrics_of(model, c, offsets[t + 1] - offsets[t], st.excess_max, st.excess_min,
-                        [&](uint32_t l, uint64_t& steps, uint64_t& excess) {
-                            steps = st.steps[l];
-                            excess = st.excess[l];
-                        });
+    const bool lv = lane < MAGUS_PROXY_LEVELS;
+    const magus_proxy_metrics r =
+        metrics_of(model, c, offsets[t + 1] - offsets[t], st.excess_max, st.excess_min,
+                   lv ? st.steps[lane] : 0ull, lv ? st.excess[lane] : 0ull, lane);
+    store_metrics(out + t, r, lane);
 }
 
 __device__ __forceinline__ uint32_t sat_sub(uint32_t x, uint32_t cap) {
@@ -1079,9 +1094,14 @@ __global__ __launch_bounds__(kStatsWaves * kWave) void proxy_fold_kernel(
         }
         out[w] = val;
     }
-    // the metrics from the same sums, by one lane
-    if (metrics && lane == 0)
-        metrics[t] = metrics_of(model, c, offsets[t + 1] - offsets[t], emax, emin, level_stats);
+    // the metrics from the same sums, lane l taking level l
+    if (metrics) {
+        uint64_t steps_l, excess_l;
+        level_stats(lane, steps_l, excess_l);
+        const magus_proxy_metrics r =
+            metrics_of(model, c, offsets[t + 1] - offsets[t], emax, emin, steps_l, excess_l, lane);
+        store_metrics(metrics + t, r, lane);
+    }
 }
 
 }  // namespace
@@ -1119,7 +1139,8 @@ hipError_t launch_proxy_stepped(const uint32_t* samples, uint64_t n_samples,
         if (e2 != hipSuccess) return e2;
     }
     if (metrics)
-        proxy_metrics_kernel<<<(n_traces + kWave - 1) / kWave, kWave, 0, stream>>>(
+        proxy_metrics_kernel<<<(n_traces + kStatsWaves - 1) / kStatsWaves, kStatsWaves * kWave,
+                               0, stream>>>(
             offsets, n_traces, chunk_base, cfgs, cfg_of_trace, model, stats, metrics);
     return hipGetLastError();
 }
