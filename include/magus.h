@@ -441,6 +441,9 @@ int magus_proxy_model_check(const magus_proxy_model* model);
  * 8,192 steps, else of the context's length);
  * stepped configs take the stepped replay's first pass (context-owned step
  * masks, 28 B per 64 steps) and one statistics pass over samples and masks.
+ * Either pass runs in 32-bit sums; a chunk holding a sample of 2^24 or more
+ * (2^22 for stepped configs) is queued in the context and run again in
+ * 64-bit sums, with identical results.
  *   h_model    the proxy model (host memory, read before return); an invalid
  *              model, or a config with level_max >= n_levels, is MAGUS_EINVAL.
  *   d_stats    n_traces magus_proxy_stats (written).
