@@ -20,22 +20,27 @@
 //   plan        (replay_fold.hip) chunk prefix and data checks
 //   fused chunk one wave per chunk: Alg. 1 / Alg. 2 per 64-step block, the
 //               block's level bits from the carries of ~DN + UP + level, the
-//               excess sums per level -> ProxySum
+//               excess sums per level in 32 bits -> ProxySum; a chunk with a
+//               sample of 2^24 or more is queued
+//   exact       the queued chunks again in 64-bit sums (none on real traces)
 //   fused fold  one wave per trace -> magus_proxy_stats, and the trace's
-//               metrics from the same sums (one lane, as the metrics kernel)
+//               metrics from the same sums; empties the queue
 // Stepped configs take the path over the stepped replay's pass 1 (its step
 // masks and the level entering every chunk, stepped.hip):
-//   zero     clears the statistics (no memset node, so the sequence can be
-//            captured into a graph)
+//   zero     clears the statistics and the queue (no memset node, so the
+//            sequence can be captured into a graph)
 //   stepped  one wave per chunk: reads the samples and the step masks, walks
 //            the level through each block in scalar registers from the chunk's
-//            entering level, and sums per level: a block at one level adds to
-//            a run at that level (per lane); a block whose level changes adds
-//            each step's excess and interval to its lane's bins of its level
-//            in LDS (samples below 2^24), else scans its per-step excess once
-//            and takes each segment's sum from the scan at the segment's
-//            ends; one atomic add per non-zero sum per chunk
-//   metrics  one thread per trace: the seven figures of each policy in FP64
+//            entering level (or takes it from raise / lower counts when no
+//            move in the block is clamped), and sums per level: a block at one
+//            level adds to a run at that level (per lane); a block whose level
+//            changes adds each step's excess and interval to its lane's word
+//            of its level's bins in LDS; a chunk with a sample of 2^22 or more
+//            is queued
+//   wide     the queued chunks: scans a changing block's per-step excess once
+//            and takes each segment's sum from the scan at the segment's ends
+//            (64-bit); one atomic add per non-zero sum per chunk in both
+//   metrics  one wave per trace: the seven figures of each policy in FP64
 
 #include "block_masks.h"
 #include "proxy_internal.h"
