@@ -660,15 +660,16 @@ int magus_proxy(magus_ctx* ctx, const uint32_t* d_samples, uint64_t n_samples,
     // the statistics pass's per-lane excess bins cover the widest level range
     uint32_t bin_levels = 0;
     for (const DevCfg& d : ctx->cfg_host) bin_levels = std::max(bin_levels, d.lmax - d.lmin + 1u);
+    // this path clears the wide pass's queue before it runs and leaves it
+    // filled (also when a launch fails part-way): a single-pass call clears
+    // it first
+    ctx->proxy_redo_zero = false;
     HIP_TRY(launch_proxy_stepped(d_samples, n_samples, d_offsets, n_traces,
                                  ctx->chunk_base.as<uint32_t>(), max_chunks,
                                  ctx->cfgs.as<DevCfg>(), d_cfg_of_trace, ctx->chunk,
                                  ctx->step_enter.as<uint32_t>(), ctx->step_masks.as<uint64_t>(),
                                  ctx->proxy_model.as<magus_proxy_model>(), d_stats, d_metrics,
                                  bin_levels, ctx->proxy_redo.as<uint32_t>(), stream));
-    // this path clears the wide pass's queue before it runs and leaves it
-    // filled; a single-pass call clears it first
-    ctx->proxy_redo_zero = false;
     return MAGUS_OK;
 }
 
