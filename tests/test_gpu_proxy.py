@@ -297,6 +297,29 @@ def test_exact_queue_across_calls(ctx, oracle_mod):
         ctx.set_chunk(0)
 
 
+def test_exact_queue_longer_than_its_grid(ctx, oracle_mod):
+    """More queued chunks than the exact and wide kernels have waves (their
+    grids stop at 2,048 workgroups of 4 waves): with chunks of 64 steps
+    (128 for the single pass) 1.2 million samples of 2^24 or more queue
+    9,375 chunks on the single pass and 18,750 on the stepped one, so waves
+    take several queue entries each; both match the oracle."""
+    rng = np.random.default_rng(7)
+    traces = [rng.integers(1 << 24, 2**32, 200000, dtype=np.uint64).astype(np.uint32)
+              for _ in range(6)]
+    samples, offsets = synth.make_batch(traces)
+    model = proxy_model()
+    s, o, _ = to_dev(samples, offsets)
+    ctx.set_chunk(64)
+    try:
+        for cfg in (default_config(window=4, hold=5),
+                    default_config(window=4, hold=5, up_step=2, down_step=1)):
+            st, me = ctx.proxy(s, o, [cfg], model)
+            ctx.check()
+            check_against_oracle(oracle_mod, samples, offsets, [cfg], None, model, st, me)
+    finally:
+        ctx.set_chunk(0)
+
+
 @pytest.mark.parametrize("chunk", [128, 4096, 16320, 16384, 32768])
 def test_stepped_narrow_and_wide_passes(ctx, oracle_mod, chunk):
     """Stepped configs through the statistics pass's two forms: the narrow
