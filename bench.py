@@ -361,6 +361,22 @@ def bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks, cp
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     uctx.check()
+    # the read probe over the same samples (the chunk kernel's loads with no
+    # other work, one wave per chunk), timed by the library's events: the
+    # floor the call is measured against
+    probe_ms = {}
+    for pc in sorted({4096, int(chosen["chunk_steps"])}):
+        pout = uctx.read_probe(us, pc)
+        torch.cuda.synchronize()
+        uctx.set_profiling(True)
+        uctx.kernel_time(magus.KERNEL_PROBE)
+        for _ in range(10):
+            uctx.read_probe(us, pc, out=pout)
+        torch.cuda.synchronize()
+        uctx.set_profiling(False)
+        pms, pn = uctx.kernel_time(magus.KERNEL_PROBE)
+        probe_ms[str(pc)] = pms / pn
+        del pout
     ugot = ures.cpu().numpy().view(np.uint64)
     # the first fifth of the traces (4,000, contiguous) for the oracle: every
     # one of their results is checked, and the run is the oracle's baseline
@@ -408,9 +424,12 @@ def bench_uneven(magus, synth, np, torch, dev, grid, grid_arr, extra, checks, cp
         "makespan_vs_ideal": dt * 1e3 / ideal_ms, "parity": "not checked (--no-cpu)",
         "autotuned": {"chunk_steps": chosen["chunk_steps"],
                       "persistent_workgroups": chosen["persistent_blocks"],
-                      "default_ms": chosen["default_ms"], "best_ms": chosen["best_ms"]}}
+                      "default_ms": chosen["default_ms"], "best_ms": chosen["best_ms"]},
+        "read_probe_ms": probe_ms,
+        "call_frac_of_probe": min(probe_ms.values()) / (dt * 1e3)}
     log(f"  uneven {len(usmp) / dt:.3e} samples/s ({dt * 1e3:.3f} ms, "
-        f"{ideal_ms / (dt * 1e3):.2%} of HBM), chosen {chosen}")
+        f"{ideal_ms / (dt * 1e3):.2%} of HBM), chosen {chosen}; read probe "
+        + ", ".join(f"{v * 1e3:.0f} us at chunk {k}" for k, v in probe_ms.items()))
     uctx.close()
     del us, uo, uc, usmp
 
